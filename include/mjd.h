@@ -1,0 +1,145 @@
+/*
+ * mjd.h - C ABI of the MI355X (gfx950) JPEG back-half decoder.
+ *
+ * The library runs the data-parallel part of baseline JPEG decoding that
+ * Sodsong et al. (PMAM'14) move off the CPU: dequantisation, the 8x8
+ * inverse DCT, chroma upsampling and YCbCr->RGB colour conversion (paper
+ * Sec. 2, Fig. 1; Sec. 4).  As in the paper's statement of the problem
+ * (Sec. 7, Sec. 4), the input is an array of 16-bit quantised DCT
+ * coefficients, the image's quantisation tables (Sec. 2) and the
+ * components' sampling factors (Sec. 2); the output is interleaved 8-bit
+ * RGB, one byte per channel, rows top to bottom (Sec. 4.3, Fig. 4b, Fig. 5).
+ * All stages run as one fused HIP kernel; no intermediate plane is written
+ * to device memory.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Status: every function returns MJD_OK (0) or a negative mjd_status.
+ *   mjd_last_error() returns a thread-local message for the last failure.
+ *   No C++ exception crosses this interface.
+ * - Pointers named d_* are device pointers (HIP global memory on the
+ *   context's device); h_* are host pointers.  The caller owns every buffer;
+ *   the library keeps no pointer after the enqueued work completes.
+ * - Device calls are asynchronous on the caller's HIP stream (passed as
+ *   void*; NULL means the default stream).  Argument validation happens
+ *   synchronously before anything is enqueued; on an error nothing is
+ *   enqueued.
+ * - Coefficient layout (MCU order): MCUs in raster order; inside an MCU
+ *   the luma blocks (v rows x h columns, raster), then one Cb block, then
+ *   one Cr block.  Each block is 64 int16 in natural order, index
+ *   8*row + col, row = vertical frequency (already de-zig-zagged).  The
+ *   padding MCUs at the right and bottom edges are present and complete.
+ *   The coefficient array must be 16-byte aligned.
+ * - Quantisation tables: uint16[4][64] in natural order; component c uses
+ *   table qsel[c].  Entries 1..255 for baseline data.
+ * - Numeric domain: with |coefficient * Q| <= 1173 for every coefficient
+ *   (every block produced from 8-bit samples has |F| <= 1024, so
+ *   |c * Q| <= 1024 + Q/2 <= 1151), every intermediate of the fixed-point
+ *   IDCT fits in int32 and the result is the defined one.  Outside that
+ *   domain the call is still memory-safe but its output is unspecified.
+ * - Output: RGB8 rows of `pitch` bytes (pitch >= 3 * width); only the
+ *   bytes of the decoded rows' first 3 * width columns are written.
+ */
+#ifndef MJD_H
+#define MJD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mjd_status {
+  MJD_OK = 0,
+  MJD_EINVAL = -1,       /* bad argument (null pointer, size, alignment, range) */
+  MJD_EUNSUPPORTED = -2, /* valid JPEG parameters this library does not decode */
+  MJD_ENOMEM = -3,       /* a host or device allocation failed */
+  MJD_EDEVICE = -4,      /* a HIP runtime call failed */
+  MJD_ECORRUPT = -5,     /* malformed bitstream */
+  MJD_EBUDGET = -6       /* request larger than the configured memory budget */
+} mjd_status;
+
+typedef enum mjd_upsample {
+  /* Replicate each chroma sample over its 2x1 or 2x2 group. */
+  MJD_UPSAMPLE_SIMPLE = 0,
+  /* Triangle ("fancy") filter: paper Sec. 4.2, Algorithm 1 over whole
+   * component rows for 4:2:2; for 4:2:0 an unrounded vertical 3:1 sum
+   * followed by the horizontal 3:1 filter, (3S[k] + S[k-1] + 8) >> 4 on even
+   * and (3S[k] + S[k+1] + 7) >> 4 on odd outputs.  Neighbours are clamped
+   * at the true component edge ceil(W*h/hmax) x ceil(H*v/vmax). */
+  MJD_UPSAMPLE_FANCY = 1
+} mjd_upsample;
+
+/* Frame description (paper Sec. 2: dimensions and component subsampling
+ * come from the frame header).  Components: 0 = Y, 1 = Cb, 2 = Cr.
+ * Supported: (h[0], v[0]) in {(1,1), (2,1), (2,2)} (4:4:4, 4:2:2, 4:2:0),
+ * h[1] = v[1] = h[2] = v[2] = 1; width and height 1..65535; qsel 0..3. */
+typedef struct mjd_frame {
+  uint32_t width;
+  uint32_t height;
+  uint8_t h[3];
+  uint8_t v[3];
+  uint8_t qsel[3];
+  uint8_t reserved; /* must be 0 */
+} mjd_frame;
+
+/* MCU geometry (paper Sec. 2: an MCU is 8x8 pixels for 4:4:4 and 16x8 for
+ * 4:2:2; 16x16 for 4:2:0).  comp_w/comp_h are the true component sizes
+ * ceil(W*h_c/hmax) x ceil(H*v_c/vmax). */
+typedef struct mjd_geometry {
+  uint32_t mcu_w, mcu_h;
+  uint32_t mcus_x, mcus_y;
+  uint32_t blocks_per_mcu;
+  uint32_t comp_w[3];
+  uint32_t comp_h[3];
+  uint64_t n_blocks;
+} mjd_geometry;
+
+/* Opaque per-device context: owns the library's device workspace
+ * (batch descriptor tables, work-queue counters), its HIP graphs and its
+ * tuned launch choices.  Calls on distinct contexts are thread-safe; one
+ * context must not be used from two threads at once. */
+typedef struct mjd_ctx mjd_ctx;
+
+/* Create a context on HIP device `device` (makes it current while creating). */
+int mjd_ctx_create(mjd_ctx** out, int device);
+/* Release a context and its device workspace.  Synchronises the device. */
+void mjd_ctx_destroy(mjd_ctx* ctx);
+
+/* Host-only: validate `frame` and compute its geometry.  Needs no GPU.
+ * Returns MJD_EINVAL for null pointers or out-of-range fields and
+ * MJD_EUNSUPPORTED for valid-but-unsupported sampling factors. */
+int mjd_geometry_of(const mjd_frame* frame, mjd_geometry* out);
+
+/* Decode MCU rows [mcu_row0, mcu_row1) of one image (paper Sec. 4: dequantise
+ * + IDCT (Sec. 4.1, Eqs. 1-2), upsampling (Sec. 4.2), colour conversion
+ * (Sec. 4.3), fused into one launch; the paper's horizontal chunks (Sec. 4.5)
+ * are MCU-row bands here).
+ *   d_coef: n_blocks * 64 int16 in MCU order (see above), 16-byte aligned.
+ *   d_qt:   uint16[4][64] natural order, 2-byte aligned.
+ *   d_rgb:  image base (row 0); rows [mcu_h*row0, min(H, mcu_h*row1)) are
+ *           written, each 3*width bytes at d_rgb + y*pitch.
+ * Reads blocks of MCU rows [row0, row1) only, plus, for fancy 4:2:0, the
+ * chroma blocks of MCU rows row0-1 and row1 when they exist, and for fancy
+ * 4:2:0 / 4:2:2 the chroma blocks of the horizontally adjacent MCUs; those
+ * must already hold valid data.  Requires 0 <= row0 < row1 <= mcus_y. */
+int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef,
+               const uint16_t* d_qt, int upsample, uint8_t* d_rgb, size_t pitch,
+               uint32_t mcu_row0, uint32_t mcu_row1, void* stream);
+
+/* Device-to-device streaming copy of `bytes` bytes (a multiple of 16; both
+ * pointers 16-byte aligned), enqueued on `stream`.  It is the bandwidth
+ * reference for the decoder: a plain read+write stream at the rate this
+ * device sustains, used as the denominator check of the roofline and to
+ * calibrate memory-traffic counters. */
+int mjd_copy(mjd_ctx* ctx, void* d_dst, const void* d_src, size_t bytes, void* stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* mjd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MJD_H */

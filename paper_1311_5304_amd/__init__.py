@@ -1,0 +1,36 @@
+"""MI355X (gfx950) JPEG back-half decoder: dequantise -> islow IDCT ->
+chroma upsampling -> YCbCr->RGB as one fused HIP kernel behind a C ABI
+(include/mjd.h).  PyTorch supplies device memory and streams only.
+"""
+from __future__ import annotations
+
+from ._binding import (MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE, Context, MjdError,  # noqa: F401
+                       mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_decode, mjd_geometry_of,
+                       mjd_last_error)
+
+UPSAMPLE = {"simple": MJD_UPSAMPLE_SIMPLE, "fancy": MJD_UPSAMPLE_FANCY}
+
+
+def decode(ctx: Context, frame, coef, qt, mode: str = "fancy", out=None, rows=None, stream=None):
+    """Decode one image (or MCU-row band `rows=(row0, row1)`) on the GPU.
+
+    coef: torch.int16 CUDA tensor with n_blocks*64 elements in MCU order;
+    qt: torch uint16/int16 CUDA tensor of 4*64 entries; out: optional
+    torch.uint8 CUDA tensor [H, W, 3] (contiguous).  Returns `out`."""
+    import torch
+
+    g = mjd_geometry_of(frame)
+    if coef.numel() != g["n_blocks"] * 64 or coef.element_size() != 2 or not coef.is_cuda:
+        raise ValueError("coef must be a CUDA int16 tensor of n_blocks*64 elements")
+    if qt.numel() != 256 or qt.element_size() != 2 or not qt.is_cuda:
+        raise ValueError("qt must be a CUDA 16-bit tensor of 4*64 entries")
+    if not coef.is_contiguous() or not qt.is_contiguous():
+        raise ValueError("coef and qt must be contiguous")
+    h, w = int(frame["height"]), int(frame["width"])
+    if out is None:
+        out = torch.empty((h, w, 3), dtype=torch.uint8, device=coef.device)
+    if out.shape != (h, w, 3) or out.dtype != torch.uint8 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous uint8 tensor [H, W, 3]")
+    r0, r1 = rows if rows is not None else (0, g["mcus_y"])
+    mjd_decode(ctx, frame, coef, qt, UPSAMPLE[mode], out, 3 * w, r0, r1, stream)
+    return out

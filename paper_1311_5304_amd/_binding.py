@@ -1,0 +1,164 @@
+"""ctypes binding of libmjd.so: the C ABI in include/mjd.h, with the same names.
+
+Argument marshalling only.  Device buffers are passed as torch tensors (their
+data_ptr()) or as raw integer addresses; streams as torch.cuda.Stream, a raw
+hipStream_t integer, or None for the current torch stream.  Nothing here
+computes any part of the decode; if the library is missing, importing a
+function raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "_lib", "libmjd.so")
+
+MJD_OK = 0
+MJD_EINVAL = -1
+MJD_EUNSUPPORTED = -2
+MJD_ENOMEM = -3
+MJD_EDEVICE = -4
+MJD_ECORRUPT = -5
+MJD_EBUDGET = -6
+STATUS_NAMES = {0: "MJD_OK", -1: "MJD_EINVAL", -2: "MJD_EUNSUPPORTED", -3: "MJD_ENOMEM",
+                -4: "MJD_EDEVICE", -5: "MJD_ECORRUPT", -6: "MJD_EBUDGET"}
+
+MJD_UPSAMPLE_SIMPLE = 0
+MJD_UPSAMPLE_FANCY = 1
+
+
+class MjdError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class mjd_frame(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_uint32), ("height", ctypes.c_uint32),
+                ("h", ctypes.c_uint8 * 3), ("v", ctypes.c_uint8 * 3),
+                ("qsel", ctypes.c_uint8 * 3), ("reserved", ctypes.c_uint8)]
+
+
+class mjd_geometry(ctypes.Structure):
+    _fields_ = [("mcu_w", ctypes.c_uint32), ("mcu_h", ctypes.c_uint32),
+                ("mcus_x", ctypes.c_uint32), ("mcus_y", ctypes.c_uint32),
+                ("blocks_per_mcu", ctypes.c_uint32),
+                ("comp_w", ctypes.c_uint32 * 3), ("comp_h", ctypes.c_uint32 * 3),
+                ("n_blocks", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmjd.so (built in-tree by paper_1311_5304_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1311_5304_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, u32, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
+        L.mjd_ctx_create.argtypes = [ctypes.POINTER(vp), i32]
+        L.mjd_ctx_create.restype = i32
+        L.mjd_ctx_destroy.argtypes = [vp]
+        L.mjd_ctx_destroy.restype = None
+        L.mjd_geometry_of.argtypes = [ctypes.POINTER(mjd_frame), ctypes.POINTER(mjd_geometry)]
+        L.mjd_geometry_of.restype = i32
+        L.mjd_decode.argtypes = [vp, ctypes.POINTER(mjd_frame), vp, vp, i32, vp, sz, u32, u32, vp]
+        L.mjd_decode.restype = i32
+        L.mjd_copy.argtypes = [vp, vp, vp, sz, vp]
+        L.mjd_copy.restype = i32
+        L.mjd_last_error.argtypes = []
+        L.mjd_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def mjd_last_error() -> str:
+    return lib().mjd_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != MJD_OK:
+        raise MjdError(rc, mjd_last_error())
+
+
+def make_frame(frame) -> mjd_frame:
+    """dict {width, height, h, v, qsel} (or an mjd_frame) -> mjd_frame."""
+    if isinstance(frame, mjd_frame):
+        return frame
+    f = mjd_frame()
+    f.width = int(frame["width"])
+    f.height = int(frame["height"])
+    for c in range(3):
+        f.h[c] = int(frame["h"][c])
+        f.v[c] = int(frame["v"][c])
+        f.qsel[c] = int(frame.get("qsel", (0, 1, 1))[c])
+    f.reserved = 0
+    return f
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(s) -> int:
+    if s is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def mjd_geometry_of(frame) -> dict:
+    g = mjd_geometry()
+    _check(lib().mjd_geometry_of(ctypes.byref(make_frame(frame)), ctypes.byref(g)))
+    return {"mcu_w": g.mcu_w, "mcu_h": g.mcu_h, "mcus_x": g.mcus_x, "mcus_y": g.mcus_y,
+            "blocks_per_mcu": g.blocks_per_mcu, "comp_w": list(g.comp_w), "comp_h": list(g.comp_h),
+            "n_blocks": g.n_blocks}
+
+
+class Context:
+    """Owns an mjd_ctx*; destroyed on close() or garbage collection."""
+
+    def __init__(self, device: int = 0):
+        p = ctypes.c_void_p()
+        _check(lib().mjd_ctx_create(ctypes.byref(p), int(device)))
+        self.handle = p
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().mjd_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mjd_ctx_create(device: int = 0) -> Context:
+    return Context(device)
+
+
+def mjd_ctx_destroy(ctx: Context):
+    ctx.close()
+
+
+def mjd_decode(ctx: Context, frame, coef, qt, upsample: int, rgb, pitch: int,
+               mcu_row0: int, mcu_row1: int, stream=None):
+    _check(lib().mjd_decode(ctx.handle, ctypes.byref(make_frame(frame)), _ptr(coef), _ptr(qt),
+                            int(upsample), _ptr(rgb), int(pitch), int(mcu_row0), int(mcu_row1),
+                            _stream(stream)))
+
+
+def mjd_copy(ctx: Context, dst, src, nbytes: int, stream=None):
+    _check(lib().mjd_copy(ctx.handle, _ptr(dst), _ptr(src), int(nbytes), _stream(stream)))

@@ -1,0 +1,146 @@
+// C ABI entry points: validation, geometry, context, dispatch.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <new>
+
+#include "mjd_internal.h"
+
+namespace {
+thread_local char g_err[512] = "";
+}
+
+namespace mjd {
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int frame_geometry(const mjd_frame* f, mjd_geometry* g) {
+  if (!f || !g) return fail(MJD_EINVAL, "null frame or geometry pointer");
+  if (f->width < 1 || f->width > 65535 || f->height < 1 || f->height > 65535)
+    return fail(MJD_EINVAL, "image size %ux%u outside 1..65535", f->width, f->height);
+  for (int c = 0; c < 3; ++c) {
+    if (f->h[c] < 1 || f->h[c] > 4 || f->v[c] < 1 || f->v[c] > 4)
+      return fail(MJD_EINVAL, "component %d sampling factors (%u,%u) outside 1..4", c, f->h[c], f->v[c]);
+    if (f->qsel[c] > 3) return fail(MJD_EINVAL, "component %d quant table selector %u > 3", c, f->qsel[c]);
+  }
+  if (f->reserved != 0) return fail(MJD_EINVAL, "reserved frame field must be 0");
+  const bool luma_ok = (f->h[0] == 1 && f->v[0] == 1) || (f->h[0] == 2 && f->v[0] == 1) ||
+                       (f->h[0] == 2 && f->v[0] == 2);
+  if (!luma_ok || f->h[1] != 1 || f->v[1] != 1 || f->h[2] != 1 || f->v[2] != 1)
+    return fail(MJD_EUNSUPPORTED, "sampling Y(%u,%u) Cb(%u,%u) Cr(%u,%u) not supported (4:4:4, 4:2:2, 4:2:0 only)",
+                f->h[0], f->v[0], f->h[1], f->v[1], f->h[2], f->v[2]);
+  const uint32_t hmax = f->h[0], vmax = f->v[0];
+  g->mcu_w = 8 * hmax;
+  g->mcu_h = 8 * vmax;
+  g->mcus_x = (f->width + g->mcu_w - 1) / g->mcu_w;
+  g->mcus_y = (f->height + g->mcu_h - 1) / g->mcu_h;
+  g->blocks_per_mcu = hmax * vmax + 2;
+  for (int c = 0; c < 3; ++c) {
+    g->comp_w[c] = (f->width * f->h[c] + hmax - 1) / hmax;
+    g->comp_h[c] = (f->height * f->v[c] + vmax - 1) / vmax;
+  }
+  g->n_blocks = static_cast<uint64_t>(g->mcus_x) * g->mcus_y * g->blocks_per_mcu;
+  return MJD_OK;
+}
+
+}  // namespace mjd
+
+extern "C" {
+
+const char* mjd_last_error(void) { return g_err; }
+
+int mjd_geometry_of(const mjd_frame* frame, mjd_geometry* out) {
+  g_err[0] = 0;
+  return mjd::frame_geometry(frame, out);
+}
+
+int mjd_ctx_create(mjd_ctx** out, int device) {
+  g_err[0] = 0;
+  if (!out) return mjd::fail(MJD_EINVAL, "null context out-pointer");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return mjd::fail(MJD_EDEVICE, "no HIP device: %s", hipGetErrorString(e));
+  if (device < 0 || device >= n) return mjd::fail(MJD_EINVAL, "device %d outside 0..%d", device, n - 1);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return mjd::fail(MJD_EDEVICE, "hipGetDeviceProperties: %s", hipGetErrorString(e));
+  mjd_ctx* ctx = new (std::nothrow) mjd_ctx;
+  if (!ctx) return mjd::fail(MJD_ENOMEM, "context allocation failed");
+  ctx->device = device;
+  ctx->cu_count = prop.multiProcessorCount;
+  ctx->device_name = prop.gcnArchName;
+  *out = ctx;
+  return MJD_OK;
+}
+
+void mjd_ctx_destroy(mjd_ctx* ctx) {
+  if (!ctx) return;
+  int cur = 0;
+  if (hipGetDevice(&cur) == hipSuccess && cur != ctx->device) (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (cur != ctx->device) (void)hipSetDevice(cur);
+  delete ctx;
+}
+
+int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef, const uint16_t* d_qt,
+               int upsample, uint8_t* d_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1,
+               void* stream) {
+  g_err[0] = 0;
+  if (!ctx) return mjd::fail(MJD_EINVAL, "null context");
+  mjd_geometry g;
+  int rc = mjd::frame_geometry(frame, &g);
+  if (rc != MJD_OK) return rc;
+  if (!d_coef || !d_qt || !d_rgb) return mjd::fail(MJD_EINVAL, "null device buffer");
+  if (reinterpret_cast<uintptr_t>(d_coef) % 16) return mjd::fail(MJD_EINVAL, "coefficient buffer not 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(d_qt) % 2) return mjd::fail(MJD_EINVAL, "quant table buffer not 2-byte aligned");
+  if (upsample != MJD_UPSAMPLE_SIMPLE && upsample != MJD_UPSAMPLE_FANCY)
+    return mjd::fail(MJD_EINVAL, "upsample mode %d unknown", upsample);
+  if (pitch < 3ull * frame->width) return mjd::fail(MJD_EINVAL, "pitch %zu < 3*width", pitch);
+  if (mcu_row0 >= mcu_row1 || mcu_row1 > g.mcus_y)
+    return mjd::fail(MJD_EINVAL, "MCU rows [%u,%u) not inside [0,%u)", mcu_row0, mcu_row1, g.mcus_y);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
+    if (hipSetDevice(ctx->device) != hipSuccess) return mjd::fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+  }
+  mjd::ImageParams p{};
+  p.coef = d_coef;
+  p.qt = d_qt;
+  p.rgb = d_rgb;
+  p.pitch = pitch;
+  p.width = frame->width;
+  p.height = frame->height;
+  p.mcus_x = g.mcus_x;
+  p.mcus_y = g.mcus_y;
+  p.chroma_w = g.comp_w[1];
+  p.chroma_h = g.comp_h[1];
+  p.row0 = mcu_row0;
+  p.row1 = mcu_row1;
+  for (int c = 0; c < 3; ++c) p.qsel[c] = frame->qsel[c];
+  p.aligned_out = (reinterpret_cast<uintptr_t>(d_rgb) % 4 == 0 && pitch % 4 == 0) ? 1u : 0u;
+  hipError_t e = mjd::launch_image(p, frame->h[0], frame->v[0], upsample == MJD_UPSAMPLE_FANCY,
+                                   static_cast<hipStream_t>(stream));
+  if (cur != ctx->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return mjd::fail(MJD_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return MJD_OK;
+}
+
+int mjd_copy(mjd_ctx* ctx, void* d_dst, const void* d_src, size_t bytes, void* stream) {
+  g_err[0] = 0;
+  if (!ctx) return mjd::fail(MJD_EINVAL, "null context");
+  if (!d_dst || !d_src) return mjd::fail(MJD_EINVAL, "null device buffer");
+  if (reinterpret_cast<uintptr_t>(d_dst) % 16 || reinterpret_cast<uintptr_t>(d_src) % 16 || bytes % 16)
+    return mjd::fail(MJD_EINVAL, "copy buffers and size must be multiples of 16 bytes");
+  if (bytes == 0) return MJD_OK;
+  hipError_t e = mjd::launch_copy(d_dst, d_src, bytes, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return mjd::fail(MJD_EDEVICE, "copy launch failed: %s", hipGetErrorString(e));
+  return MJD_OK;
+}
+
+}  // extern "C"

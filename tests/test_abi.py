@@ -1,0 +1,70 @@
+"""Host-side checks of the C ABI: the library loads, exports everything the
+header declares, and its host-only geometry/validation agrees with the
+oracle's geometry.  No GPU needed."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_1311_5304_amd import _binding as B
+from synth.encode import make_frame
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*[A-Za-z_][\w\s\*]*?\b(mjd_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert {"mjd_decode", "mjd_geometry_of", "mjd_ctx_create", "mjd_last_error"} <= names
+    lib = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_geometry_matches_oracle():
+    for samp in ("444", "422", "420"):
+        for w in list(range(1, 41)) + [65535]:
+            for h in (1, 2, 7, 8, 9, 15, 16, 17, 40, 65535):
+                f = make_frame(w, h, samp)
+                g = B.mjd_geometry_of(f)
+                o = oracle.geometry(f)
+                for k in ("mcu_w", "mcu_h", "mcus_x", "mcus_y", "blocks_per_mcu", "n_blocks"):
+                    assert g[k] == o[k], (samp, w, h, k)
+                assert g["comp_w"] == o["comp_w"] and g["comp_h"] == o["comp_h"]
+
+
+@pytest.mark.parametrize("bad, code", [
+    (dict(width=0), B.MJD_EINVAL),
+    (dict(height=0), B.MJD_EINVAL),
+    (dict(width=65536), B.MJD_EINVAL),
+    (dict(qsel=(0, 1, 4)), B.MJD_EINVAL),
+    (dict(h=(1, 2, 1), v=(1, 1, 1)), B.MJD_EUNSUPPORTED),
+    (dict(h=(1, 1, 1), v=(2, 1, 1)), B.MJD_EUNSUPPORTED),
+    (dict(h=(4, 1, 1), v=(1, 1, 1)), B.MJD_EUNSUPPORTED),
+    (dict(h=(0, 1, 1), v=(1, 1, 1)), B.MJD_EINVAL),
+])
+def test_geometry_rejects_bad_frames(bad, code):
+    f = dict(make_frame(64, 32, "420"))
+    f.update(bad)
+    with pytest.raises(B.MjdError) as ei:
+        B.mjd_geometry_of(f)
+    assert ei.value.code == code
+    assert B.mjd_last_error()
+
+
+def test_frame_struct_layout():
+    assert ctypes.sizeof(B.mjd_frame) == 20
+    assert ctypes.sizeof(B.mjd_geometry) == 56
