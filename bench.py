@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--sets", type=int, default=5, help="rotating buffer sets")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-latency", action="store_true", help="skip the small-image latency loop")
     return ap.parse_args()
 
 
@@ -108,7 +108,7 @@ def main():
         gpu_out = o_sets[(args.steps - 1) % args.sets].cpu().numpy()
         extras["bit_exact_vs_oracle"] = bool(np.array_equal(gpu_out, ref))
 
-    if not args.no_extras:
+    if True:
         # copy-kernel bandwidth over the same byte count (read coef-size, write coef-size)
         n = (algo_bytes // 2) // 16 * 16
         src = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(args.sets)]
@@ -124,7 +124,9 @@ def main():
         torch.cuda.synchronize()
         copy_ms = e0.elapsed_time(e1) / 100
         extras["copy_GBps"] = round(2 * n / (copy_ms * 1e-3) / 1e9, 1)
+        extras["copy_bytes_per_launch"] = 2 * n
         del src, dst
+    if not args.no_latency:
         # small-image latency: 256x256 4:2:0 simple, kernel-only, per call
         f1, c1, q1 = workloads.small_420_simple()
         c1d = torch.from_numpy(c1).to(dev)

@@ -18,6 +18,9 @@ SOURCES = ["api.hip", "decode.hip", "copy.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+    # integer arithmetic wraps (two's complement); only the descaled results
+    # of the transform need to fit in 32 bits
+    "-fwrapv",
     # no packed-FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",

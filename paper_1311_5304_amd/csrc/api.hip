@@ -103,6 +103,7 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef, cons
   if (upsample != MJD_UPSAMPLE_SIMPLE && upsample != MJD_UPSAMPLE_FANCY)
     return mjd::fail(MJD_EINVAL, "upsample mode %d unknown", upsample);
   if (pitch < 3ull * frame->width) return mjd::fail(MJD_EINVAL, "pitch %zu < 3*width", pitch);
+  if (pitch >= (1ull << 24)) return mjd::fail(MJD_EINVAL, "pitch %zu not below 2^24 bytes", pitch);
   if (mcu_row0 >= mcu_row1 || mcu_row1 > g.mcus_y)
     return mjd::fail(MJD_EINVAL, "MCU rows [%u,%u) not inside [0,%u)", mcu_row0, mcu_row1, g.mcus_y);
   int cur = 0;

@@ -1,15 +1,5 @@
-// Fused JPEG back-half kernel for gfx950: dequantise -> 8x8 islow IDCT ->
-// chroma upsampling -> YCbCr->RGB -> interleaved RGB8 store.
-//
-// One workgroup decodes one tile of TMX x TMY MCUs.
-//  Phase 1: every lane takes whole 8x8 blocks (the tile's blocks, plus for
-//           the fancy filter the chroma blocks of the ring of MCUs around the
-//           tile) and runs dequantisation and both IDCT passes in registers
-//           (paper Sec. 4.1: columns first, Eq. 1, then rows, Eq. 2).  The
-//           uint8 samples land in LDS planes; nothing goes back to HBM.
-//  Phase 2: every lane takes a run of 4 chroma samples of one chroma row,
-//           upsamples them (Sec. 4.2) and converts each pixel (Sec. 4.3), and
-//           stores the RGB bytes (Fig. 5: dword stores of packed RGB).
+// Device building blocks of the fused JPEG back-half kernel for gfx950:
+// dequantise -> 8x8 islow IDCT -> chroma upsampling -> YCbCr->RGB -> RGB8.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,7 +10,8 @@ namespace mjd {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // --- LL&M 8-point IDCT in 13-bit fixed point --------------------------------
-// Each constant is round(2^13 * k).  With a_j = sqrt(2) cos(j*pi/16):
+// Each constant is round(2^13 * k).  With a_j = sqrt(2) cos(j*pi/16), the
+// sqrt(8)-scaled 1-D IDCT is y[n] = x0 + sum_{k>=1} sqrt(2) cos((2n+1)k pi/16) x_k.
 constexpr int kConstBits = 13;
 constexpr int kR = 4433;    // a6
 constexpr int kR2 = 6270;   // a2 - a6
@@ -35,87 +26,138 @@ constexpr int kZ2 = 20995;  // a1 + a3
 constexpr int kZ3 = 16069;  // a3 + a5
 constexpr int kZ4 = 3196;   // a3 - a5
 
-// 24-bit signed multiply: every multiplicand in the transform is a
-// dequantised coefficient, a pass-1 result or a sum of at most four of
-// either, all far inside +-2^23 on the documented input domain.
-__device__ __forceinline__ int m24(int a, int b) { return __mul24(a, b); }
+// Pass 1 keeps two extra fraction bits; pass 2 removes them, the 2-D gain of
+// 8 and the constants' 2^13, and adds the +128 level shift through its
+// rounding bias ((v + 2^17 + 128*2^18) >> 18 == ((v + 2^17) >> 18) + 128).
+constexpr int kPass1Shift = kConstBits - 2;
+constexpr int kPass2Shift = kConstBits + 2 + 3;
+constexpr int kPass1Bias = 1 << (kPass1Shift - 1);
+constexpr int kPass2Bias = (1 << (kPass2Shift - 1)) + (128 << kPass2Shift);
 
-// One sqrt(8)-scaled 1-D IDCT followed by (v + bias) >> SHIFT on each output.
-template <int SHIFT>
-__device__ __forceinline__ void idct8(const int x0, const int x1, const int x2, const int x3,
-                                      const int x4, const int x5, const int x6, const int x7,
-                                      const int bias, int* __restrict__ y, const int stride) {
-  // even part: x0, x4 through shifts, (x2, x6) through a 3-multiply rotation
-  const int z1 = m24(x2 + x6, kR);
-  const int t2 = z1 + m24(x2, kR2);
-  const int t3 = z1 - m24(x6, kR6);
-  const int t0 = ((x0 + x4) << kConstBits) + bias;
-  const int t1 = ((x0 - x4) << kConstBits) + bias;
-  const int e0 = t0 + t2, e3 = t0 - t2;
-  const int e1 = t1 + t3, e2 = t1 - t3;
-  // odd part: LL&M network over pair sums
-  const int s17 = x7 + x1, s35 = x5 + x3, s37 = x7 + x3, s15 = x5 + x1;
-  const int z5 = m24(s37 + s15, kZ5);
-  const int q17 = -m24(s17, kZ1);
-  const int q35 = -m24(s35, kZ2);
-  const int q37 = z5 - m24(s37, kZ3);
-  const int q15 = z5 - m24(s15, kZ4);
-  const int o0 = m24(x1, kP1) + q17 + q15;
-  const int o1 = m24(x3, kP3) + q35 + q37;
-  const int o2 = m24(x5, kP5) + q35 + q15;
-  const int o3 = m24(x7, kP7) + q17 + q37;
-  y[0 * stride] = (e0 + o0) >> SHIFT;
-  y[7 * stride] = (e0 - o0) >> SHIFT;
-  y[1 * stride] = (e1 + o1) >> SHIFT;
-  y[6 * stride] = (e1 - o1) >> SHIFT;
-  y[2 * stride] = (e2 + o2) >> SHIFT;
-  y[5 * stride] = (e2 - o2) >> SHIFT;
-  y[3 * stride] = (e3 + o3) >> SHIFT;
-  y[4 * stride] = (e3 - o3) >> SHIFT;
+// 24-bit signed multiply(-add).  Every multiplicand of the transform is a
+// dequantised coefficient, a pass-1 result, or a sum of at most four of them;
+// on the documented input domain all stay inside +-2^23, so the 24-bit forms
+// (full-rate v_mul_i32_i24 / v_mad_i32_i24) are exact.
+// mad24 pins v_mad_i32_i24: left to itself the compiler may pick the
+// quarter-rate v_mad_u64_u32 for a 32-bit multiply-add.  `b` is always a
+// compile-time constant here and travels in an SGPR.
+__device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+  int r;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  return r;
 }
 
-__device__ __forceinline__ int clamp255(int v) { return min(max(v, 0), 255); }
+// One sqrt(8)-scaled 1-D IDCT; returns the 8 outputs before the descale
+// shift, with `bias` already added.
+__device__ __forceinline__ void idct8_raw(const int x0, const int x1, const int x2, const int x3,
+                                          const int x4, const int x5, const int x6, const int x7,
+                                          const int bias, int y[8]) {
+  // even part: x0, x4 through shifts; (x2, x6) through a 3-multiply rotation
+  const int z1 = mul24(x2 + x6, kR);
+  const int t2 = mad24(x2, kR2, z1);            // a2*x2 + a6*x6
+  const int t3 = mad24(x6, -kR6, z1);           // a6*x2 - a2*x6
+  const int t0 = ((x0 + x4) << kConstBits) + bias;
+  const int t1 = mad24(x4, -(2 << kConstBits), t0);  // ((x0 - x4) << 13) + bias
+  const int e0 = t0 + t2, e3 = t0 - t2;
+  const int e1 = t1 + t3, e2 = t1 - t3;
+  // odd part: the LL&M network over pair sums
+  const int s17 = x7 + x1, s35 = x5 + x3, s37 = x7 + x3, s15 = x5 + x1;
+  const int z5 = mul24(s37 + s15, kZ5);
+  const int q17 = mul24(s17, -kZ1);
+  const int q35 = mul24(s35, -kZ2);
+  const int q37 = mad24(s37, -kZ3, z5);
+  const int q15 = mad24(s15, -kZ4, z5);
+  const int o0 = mad24(x1, kP1, q17 + q15);
+  const int o1 = mad24(x3, kP3, q35 + q37);
+  const int o2 = mad24(x5, kP5, q35 + q15);
+  const int o3 = mad24(x7, kP7, q17 + q37);
+  y[0] = e0 + o0;
+  y[7] = e0 - o0;
+  y[1] = e1 + o1;
+  y[6] = e1 - o1;
+  y[2] = e2 + o2;
+  y[5] = e2 - o2;
+  y[3] = e3 + o3;
+  y[4] = e3 - o3;
+}
 
-// Dequantise + 2-D IDCT of one block.  coef: 64 int16 natural order (16-byte
-// aligned, global); q: 64 int32 dequantisation factors (LDS).  Output: 16
-// dwords, two per sample row, bytes in x order (little endian).
+// Output 0 (LAST = false) or output 7 (LAST = true) of idct8_raw alone.
+template <bool LAST>
+__device__ __forceinline__ int idct8_edge_raw(const int x0, const int x1, const int x2, const int x3,
+                                              const int x4, const int x5, const int x6, const int x7,
+                                              const int bias) {
+  const int z1 = mul24(x2 + x6, kR);
+  const int e0 = ((x0 + x4) << kConstBits) + bias + mad24(x2, kR2, z1);
+  const int s15 = x5 + x1;
+  const int z5 = mul24(x7 + x3 + s15, kZ5);
+  const int o0 = mad24(x1, kP1, mad24(x7 + x1, -kZ1, mad24(s15, -kZ4, z5)));
+  return LAST ? e0 - o0 : e0 + o0;
+}
+
+// Saturating pack of two int16-range ints to bytes: returns sat(a) | sat(b) << 8.
+__device__ __forceinline__ uint32_t sat_u8x2(int a, int b) {
+  const uint32_t pair = __builtin_amdgcn_perm(static_cast<uint32_t>(b), static_cast<uint32_t>(a), 0x05040100u);
+  uint32_t r;
+  asm("v_sat_pk_u8_i16 %0, %1" : "=v"(r) : "v"(pair));
+  return r;
+}
+
+// Same, from the high halves: sat(a >> 16) | sat(b >> 16) << 8 (arithmetic
+// shifts; a and b must lie in +-2^31 with (x >> 16) inside int16).
+__device__ __forceinline__ uint32_t sat_u8x2_hi(int a, int b) {
+  const uint32_t pair = __builtin_amdgcn_perm(static_cast<uint32_t>(b), static_cast<uint32_t>(a), 0x07060302u);
+  uint32_t r;
+  asm("v_sat_pk_u8_i16 %0, %1" : "=v"(r) : "v"(pair));
+  return r;
+}
+
+__device__ __forceinline__ uint32_t pack4(int s0, int s1, int s2, int s3) {
+  return sat_u8x2(s0, s1) | (sat_u8x2(s2, s3) << 16);
+}
+
+// Dequantise + 2-D IDCT of one block (paper Sec. 4.1: columns first, Eq. 1,
+// then rows, Eq. 2).  coef: 64 int16 natural order, 16-byte aligned (global);
+// q: the 64 uint16 factors as 32 dwords (LDS, 16-byte aligned).  out: 16
+// dwords, two per sample row (x order, little endian), samples level-shifted
+// and clamped to 0..255.
 __device__ __forceinline__ void decode_block(const int16_t* __restrict__ coef,
-                                             const int* __restrict__ q, uint32_t out[16]) {
+                                             const uint32_t* __restrict__ q, uint32_t out[16]) {
   int ws[64];
   {
     int d[64];
     const v4i* src = reinterpret_cast<const v4i*>(coef);
+    const v4i* qv = reinterpret_cast<const v4i*>(q);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const v4i v = __builtin_nontemporal_load(src + r);
+      const v4i qq = qv[r];
       const int w[4] = {v.x, v.y, v.z, v.w};
+      const int qw[4] = {qq.x, qq.y, qq.z, qq.w};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        d[8 * r + 2 * i] = static_cast<int>(static_cast<int16_t>(w[i] & 0xFFFF)) * q[8 * r + 2 * i];
-        d[8 * r + 2 * i + 1] = (w[i] >> 16) * q[8 * r + 2 * i + 1];
+        d[8 * r + 2 * i] = static_cast<int16_t>(w[i] & 0xFFFF) * (qw[i] & 0xFFFF);
+        d[8 * r + 2 * i + 1] = (w[i] >> 16) * static_cast<int>(static_cast<uint32_t>(qw[i]) >> 16);
       }
     }
-    // pass 1: each column (fixed horizontal frequency u) over v = 0..7; keep
-    // 2 fraction bits: descale by 13 - 2 with half-LSB rounding
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      idct8<kConstBits - 2>(d[u], d[8 + u], d[16 + u], d[24 + u], d[32 + u], d[40 + u], d[48 + u],
-                            d[56 + u], 1 << (kConstBits - 2 - 1), ws + u, 8);
-  }
-  // pass 2: each row of the column results; descale by 13 + 2 + 3, +128, clamp
+    for (int u = 0; u < 8; ++u) {
+      int y[8];
+      idct8_raw(d[u], d[8 + u], d[16 + u], d[24 + u], d[32 + u], d[40 + u], d[48 + u], d[56 + u],
+                kPass1Bias, y);
 #pragma unroll
-  for (int y = 0; y < 8; ++y) {
-    int s[8];
-    idct8<kConstBits + 5>(ws[8 * y], ws[8 * y + 1], ws[8 * y + 2], ws[8 * y + 3], ws[8 * y + 4],
-                          ws[8 * y + 5], ws[8 * y + 6], ws[8 * y + 7], 1 << (kConstBits + 5 - 1), s, 1);
-    uint32_t lo = 0, hi = 0;
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-      lo |= static_cast<uint32_t>(clamp255(s[x] + 128)) << (8 * x);
-      hi |= static_cast<uint32_t>(clamp255(s[x + 4] + 128)) << (8 * x);
+      for (int i = 0; i < 8; ++i) ws[8 * i + u] = y[i] >> kPass1Shift;
     }
-    out[2 * y] = lo;
-    out[2 * y + 1] = hi;
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    int s[8];
+    idct8_raw(ws[8 * r], ws[8 * r + 1], ws[8 * r + 2], ws[8 * r + 3], ws[8 * r + 4], ws[8 * r + 5],
+              ws[8 * r + 6], ws[8 * r + 7], kPass2Bias, s);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s[i] >>= kPass2Shift;
+    out[2 * r] = pack4(s[0], s[1], s[2], s[3]);
+    out[2 * r + 1] = pack4(s[4], s[5], s[6], s[7]);
   }
 }
 
@@ -126,14 +168,27 @@ constexpr int kCbG = 22554;
 constexpr int kCrG = 46802;
 constexpr int kCbB = 116130;
 
-// Returns R | G << 8 | B << 16.
-__device__ __forceinline__ uint32_t ycc_rgb(int y, int cb, int cr) {
-  const int xb = cb - 128, xr = cr - 128;
-  const int r = y + ((m24(xr, kCrR) + 32768) >> 16);
-  const int g = y + ((m24(xb, -kCbG) + m24(xr, -kCrG) + 32768) >> 16);
-  const int b = y + ((m24(xb, kCbB) + 32768) >> 16);
-  return static_cast<uint32_t>(clamp255(r)) | (static_cast<uint32_t>(clamp255(g)) << 8) |
-         (static_cast<uint32_t>(clamp255(b)) << 16);
+// y16 = (Y << 16) + 2^15; xb = Cb - 128, xr = Cr - 128.  The channel value
+// before clamping is the high half of each returned word:
+// Y + ((K*x + 2^15) >> 16) == ((Y << 16) + 2^15 + K*x) >> 16.
+struct RGBWide {
+  int r, g, b;
+};
+__device__ __forceinline__ RGBWide ycc_wide(int y16, int xb, int xr) {
+  return {mad24(xr, kCrR, y16), mad24(xb, -kCbG, mad24(xr, -kCrG, y16)), mad24(xb, kCbB, y16)};
+}
+
+// Y byte i (0..3) of `ydw` as (Y << 16) + 2^15, in one byte permute.
+__device__ __forceinline__ int y16_of(uint32_t ydw, int i) {
+  return static_cast<int>(__builtin_amdgcn_perm(0x80808080u, ydw, 0x0C00040Cu | (static_cast<uint32_t>(i) << 16)));
+}
+
+// Four pixels -> 12 RGB bytes as 3 dwords (paper Fig. 5: pixel bytes grouped
+// into 4-byte vectors).
+__device__ __forceinline__ void pack_rgb4(const RGBWide p[4], uint32_t w[3]) {
+  w[0] = sat_u8x2_hi(p[0].r, p[0].g) | (sat_u8x2_hi(p[0].b, p[1].r) << 16);
+  w[1] = sat_u8x2_hi(p[1].g, p[1].b) | (sat_u8x2_hi(p[2].r, p[2].g) << 16);
+  w[2] = sat_u8x2_hi(p[2].b, p[3].r) | (sat_u8x2_hi(p[3].g, p[3].b) << 16);
 }
 
 // --- launch parameters --------------------------------------------------------
@@ -147,7 +202,7 @@ struct ImageParams {
   uint32_t chroma_w, chroma_h;  // true chroma component size
   uint32_t row0, row1;          // MCU-row band
   uint32_t qsel[3];
-  uint32_t tiles_x;             // tiles per tile row
+  uint32_t tiles_x, tiles;      // tiles per tile row, tiles in the band
   uint32_t aligned_out;         // rgb base and pitch are multiples of 4
 };
 
