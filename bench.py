@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget for the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-image latency loop")
+    ap.add_argument("--tune", action="store_true", help="autotune the launch shape before timing")
     return ap.parse_args()
 
 
@@ -68,6 +69,15 @@ def main():
     o_sets = [torch.empty((H, W, 3), dtype=torch.uint8, device=dev) for _ in range(args.sets)]
     stream = torch.cuda.current_stream()
 
+    if args.tune:
+        from paper_1311_5304_amd import autotune
+        best, table = autotune.tune(ctx, frame, c_sets, q_dev, M.MJD_UPSAMPLE_FANCY, o_sets,
+                                    wg_candidates=(0, 256, 512, 768, 1024))
+        M.mjd_ctx_set_tuning(ctx, best["seg_subtiles"], best["max_workgroups"])
+        tuned = {"best": best, "table": table}
+    else:
+        tuned = None
+
     def step(i):
         k = i % args.sets
         M.mjd_decode(ctx, frame, c_sets[k], q_dev, M.MJD_UPSAMPLE_FANCY, o_sets[k], 3 * W, 0, g["mcus_y"],
@@ -91,7 +101,9 @@ def main():
 
     # parity spot check of the timed output against the oracle (full image)
     out = {}
-    extras = {"generation_s": round(gen_s, 2)}
+    extras = {"generation_s": round(gen_s, 2), "tuning": M.mjd_ctx_get_tuning(ctx)}
+    if tuned:
+        extras["autotune"] = tuned
     cpu = None
     if not args.no_cpu_baseline:
         import oracle

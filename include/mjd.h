@@ -32,7 +32,7 @@
  *   The coefficient array must be 16-byte aligned.
  * - Quantisation tables: uint16[4][64] in natural order; component c uses
  *   table qsel[c].  Entries 1..255 for baseline data.
- * - Numeric domain: with |coefficient * Q| <= 1173 for every coefficient
+ * - Numeric domain: with |coefficient * Q| <= 1155 for every coefficient
  *   (every block produced from 8-bit samples has |F| <= 1024, so
  *   |c * Q| <= 1024 + Q/2 <= 1151), every intermediate of the fixed-point
  *   IDCT fits in int32 and the result is the defined one.  Outside that
@@ -102,10 +102,27 @@ typedef struct mjd_geometry {
  * context must not be used from two threads at once. */
 typedef struct mjd_ctx mjd_ctx;
 
+/* Launch shape of the decode kernels (paper Sec. 4.1 and Sec. 5: the best
+ * work-group size is hardware specific and chosen by profiling).  A
+ * workgroup walks a segment of `seg_subtiles` consecutive sub-tile rows of
+ * one strip of MCU columns, prefetching the next sub-tile while it decodes
+ * the current one; at most `max_workgroups` workgroups are launched and each
+ * takes further segments when it finishes one.  0 in either field selects
+ * the automatic choice (enough segments to fill every resident slot once).
+ * The values change only speed, never the output. */
+typedef struct mjd_tuning {
+  uint32_t seg_subtiles;
+  uint32_t max_workgroups;
+} mjd_tuning;
+
 /* Create a context on HIP device `device` (makes it current while creating). */
 int mjd_ctx_create(mjd_ctx** out, int device);
 /* Release a context and its device workspace.  Synchronises the device. */
 void mjd_ctx_destroy(mjd_ctx* ctx);
+
+/* Set / read the context's launch shape (see mjd_tuning).  Host only. */
+int mjd_ctx_set_tuning(mjd_ctx* ctx, const mjd_tuning* tuning);
+int mjd_ctx_get_tuning(const mjd_ctx* ctx, mjd_tuning* tuning);
 
 /* Host-only: validate `frame` and compute its geometry.  Needs no GPU.
  * Returns MJD_EINVAL for null pointers or out-of-range fields and

@@ -48,6 +48,10 @@ class mjd_geometry(ctypes.Structure):
                 ("n_blocks", ctypes.c_uint64)]
 
 
+class mjd_tuning(ctypes.Structure):
+    _fields_ = [("seg_subtiles", ctypes.c_uint32), ("max_workgroups", ctypes.c_uint32)]
+
+
 _lib = None
 
 
@@ -67,6 +71,10 @@ def lib() -> ctypes.CDLL:
         L.mjd_geometry_of.restype = i32
         L.mjd_decode.argtypes = [vp, ctypes.POINTER(mjd_frame), vp, vp, i32, vp, sz, u32, u32, vp]
         L.mjd_decode.restype = i32
+        L.mjd_ctx_set_tuning.argtypes = [vp, ctypes.POINTER(mjd_tuning)]
+        L.mjd_ctx_set_tuning.restype = i32
+        L.mjd_ctx_get_tuning.argtypes = [vp, ctypes.POINTER(mjd_tuning)]
+        L.mjd_ctx_get_tuning.restype = i32
         L.mjd_copy.argtypes = [vp, vp, vp, sz, vp]
         L.mjd_copy.restype = i32
         L.mjd_last_error.argtypes = []
@@ -151,6 +159,17 @@ def mjd_ctx_create(device: int = 0) -> Context:
 
 def mjd_ctx_destroy(ctx: Context):
     ctx.close()
+
+
+def mjd_ctx_set_tuning(ctx: Context, seg_subtiles: int = 0, max_workgroups: int = 0):
+    t = mjd_tuning(int(seg_subtiles), int(max_workgroups))
+    _check(lib().mjd_ctx_set_tuning(ctx.handle, ctypes.byref(t)))
+
+
+def mjd_ctx_get_tuning(ctx: Context) -> dict:
+    t = mjd_tuning()
+    _check(lib().mjd_ctx_get_tuning(ctx.handle, ctypes.byref(t)))
+    return {"seg_subtiles": t.seg_subtiles, "max_workgroups": t.max_workgroups}
 
 
 def mjd_decode(ctx: Context, frame, coef, qt, upsample: int, rgb, pitch: int,

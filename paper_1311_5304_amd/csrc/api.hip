@@ -110,25 +110,42 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef, cons
   if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
     if (hipSetDevice(ctx->device) != hipSuccess) return mjd::fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
   }
-  mjd::ImageParams p{};
-  p.coef = d_coef;
-  p.qt = d_qt;
-  p.rgb = d_rgb;
-  p.pitch = pitch;
-  p.width = frame->width;
-  p.height = frame->height;
-  p.mcus_x = g.mcus_x;
-  p.mcus_y = g.mcus_y;
-  p.chroma_w = g.comp_w[1];
-  p.chroma_h = g.comp_h[1];
-  p.row0 = mcu_row0;
-  p.row1 = mcu_row1;
-  for (int c = 0; c < 3; ++c) p.qsel[c] = frame->qsel[c];
-  p.aligned_out = (reinterpret_cast<uintptr_t>(d_rgb) % 4 == 0 && pitch % 4 == 0) ? 1u : 0u;
-  hipError_t e = mjd::launch_image(p, frame->h[0], frame->v[0], upsample == MJD_UPSAMPLE_FANCY,
+  mjd::ImageView im{};
+  im.coef = d_coef;
+  im.qt = d_qt;
+  im.rgb = d_rgb;
+  im.pitch = static_cast<uint32_t>(pitch);
+  im.width = static_cast<int>(frame->width);
+  im.height = static_cast<int>(frame->height);
+  im.mcus_x = static_cast<int>(g.mcus_x);
+  im.mcus_y = static_cast<int>(g.mcus_y);
+  im.chroma_w = static_cast<int>(g.comp_w[1]);
+  im.chroma_h = static_cast<int>(g.comp_h[1]);
+  im.qsel0 = frame->qsel[0];
+  im.qsel1 = frame->qsel[1];
+  im.qsel2 = frame->qsel[2];
+  im.aligned_out = (reinterpret_cast<uintptr_t>(d_rgb) % 4 == 0 && pitch % 4 == 0) ? 1 : 0;
+  hipError_t e = mjd::launch_image(im, static_cast<int>(mcu_row0), static_cast<int>(mcu_row1), frame->h[0],
+                                   frame->v[0], upsample == MJD_UPSAMPLE_FANCY, ctx->cu_count, ctx->tuning,
                                    static_cast<hipStream_t>(stream));
   if (cur != ctx->device) (void)hipSetDevice(cur);
   if (e != hipSuccess) return mjd::fail(MJD_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return MJD_OK;
+}
+
+int mjd_ctx_set_tuning(mjd_ctx* ctx, const mjd_tuning* tuning) {
+  g_err[0] = 0;
+  if (!ctx || !tuning) return mjd::fail(MJD_EINVAL, "null context or tuning");
+  if (tuning->seg_subtiles > 65536 || tuning->max_workgroups > (1u << 20))
+    return mjd::fail(MJD_EINVAL, "tuning values out of range");
+  ctx->tuning = *tuning;
+  return MJD_OK;
+}
+
+int mjd_ctx_get_tuning(const mjd_ctx* ctx, mjd_tuning* tuning) {
+  g_err[0] = 0;
+  if (!ctx || !tuning) return mjd::fail(MJD_EINVAL, "null context or tuning");
+  *tuning = ctx->tuning;
   return MJD_OK;
 }
 

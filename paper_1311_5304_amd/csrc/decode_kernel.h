@@ -117,20 +117,19 @@ __device__ __forceinline__ uint32_t pack4(int s0, int s1, int s2, int s3) {
 }
 
 // Dequantise + 2-D IDCT of one block (paper Sec. 4.1: columns first, Eq. 1,
-// then rows, Eq. 2).  coef: 64 int16 natural order, 16-byte aligned (global);
-// q: the 64 uint16 factors as 32 dwords (LDS, 16-byte aligned).  out: 16
-// dwords, two per sample row (x order, little endian), samples level-shifted
-// and clamped to 0..255.
-__device__ __forceinline__ void decode_block(const int16_t* __restrict__ coef,
-                                             const uint32_t* __restrict__ q, uint32_t out[16]) {
+// then rows, Eq. 2).  rows: the block's 8 coefficient rows (8 int16 each, in
+// registers); q: the 64 uint16 factors as 32 dwords (LDS, 16-byte aligned).
+// out: 16 dwords, two per sample row (x order, little endian), samples
+// level-shifted and clamped to 0..255.
+__device__ __forceinline__ void idct_block_regs(const v4i rows[8], const uint32_t* __restrict__ q,
+                                                uint32_t out[16]) {
   int ws[64];
   {
     int d[64];
-    const v4i* src = reinterpret_cast<const v4i*>(coef);
     const v4i* qv = reinterpret_cast<const v4i*>(q);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const v4i v = __builtin_nontemporal_load(src + r);
+      const v4i v = rows[r];
       const v4i qq = qv[r];
       const int w[4] = {v.x, v.y, v.z, v.w};
       const int qw[4] = {qq.x, qq.y, qq.z, qq.w};
@@ -190,20 +189,5 @@ __device__ __forceinline__ void pack_rgb4(const RGBWide p[4], uint32_t w[3]) {
   w[1] = sat_u8x2_hi(p[1].g, p[1].b) | (sat_u8x2_hi(p[2].r, p[2].g) << 16);
   w[2] = sat_u8x2_hi(p[2].b, p[3].r) | (sat_u8x2_hi(p[3].g, p[3].b) << 16);
 }
-
-// --- launch parameters --------------------------------------------------------
-struct ImageParams {
-  const int16_t* coef;
-  const uint16_t* qt;
-  uint8_t* rgb;
-  uint64_t pitch;
-  uint32_t width, height;
-  uint32_t mcus_x, mcus_y;
-  uint32_t chroma_w, chroma_h;  // true chroma component size
-  uint32_t row0, row1;          // MCU-row band
-  uint32_t qsel[3];
-  uint32_t tiles_x, tiles;      // tiles per tile row, tiles in the band
-  uint32_t aligned_out;         // rgb base and pitch are multiples of 4
-};
 
 }  // namespace mjd

@@ -5,14 +5,15 @@
 
 #include <string>
 
-#include "../../include/mjd.h"
-#include "decode_kernel.h"
+#include "mjd.h"
+#include "segment.h"
 
 struct mjd_ctx {
   int device = 0;
   int cu_count = 0;
   int xcd_count = 8;
   std::string device_name;
+  mjd_tuning tuning{0, 0};
 };
 
 namespace mjd {
@@ -23,8 +24,9 @@ int fail(int code, const char* fmt, ...);
 // Host-only frame validation + geometry (no HIP calls).
 int frame_geometry(const mjd_frame* f, mjd_geometry* g);
 
-// Enqueues the tile kernel for one image band.
-hipError_t launch_image(const ImageParams& p, int hf, int vf, bool fancy, hipStream_t stream);
+// Enqueues the segment kernel for MCU rows [row0, row1) of one image.
+hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf, bool fancy, int cu_count,
+                        const mjd_tuning& tuning, hipStream_t stream);
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 

@@ -1,0 +1,529 @@
+// Pipelined segment decoder: the body shared by the single-image and the
+// batched kernels.
+//
+// A workgroup decodes a *segment*: a column of sub-tiles (SX x SY MCUs each)
+// of one image, walked top to bottom.  Per sub-tile k the stages are
+//   DMA      the coefficient blocks of sub-tile k+1 (and the chroma blocks of
+//            its left/right neighbour MCUs) are copied global -> LDS with
+//            global_load_lds_dwordx4, fully coalesced, into a swizzled staging
+//            buffer, while the lanes compute on sub-tile k;
+//   phase 1  dequantise + 8x8 islow IDCT (paper Sec. 4.1), one block per
+//            lane, both passes in registers; samples go to an LDS luma
+//            buffer and an LDS chroma ring.  The neighbour chroma blocks the
+//            fancy filter needs (Sec. 4.2) are split 8 lanes per block and only
+//            the column the filter reads is formed;
+//   phase 2  (LAG sub-tiles later) upsampling + YCbCr->RGB (Sec. 4.3) + RGB8
+//            stores (Fig. 5).
+// For the 4:2:0 fancy filter a sub-tile's bottom chroma row needs the first
+// chroma row of the next sub-tile, so phase 2 runs two sub-tiles behind
+// phase 1 and the rows above and below a sub-tile come from the ring instead
+// of being decoded twice; only the rows above and below the whole segment are
+// decoded as neighbour blocks.  Phase 2 of an older sub-tile is issued before
+// phase 1 of the current one, so its stores drain while the IDCT runs, and the
+// next sub-tile's DMA is in flight during phase 1.
+#pragma once
+
+#include "decode_kernel.h"
+
+namespace mjd {
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+constexpr int round64c(int n) { return (n + 63) & ~63; }
+
+__device__ __forceinline__ int clamp255i(int v) { return min(max(v, 0), 255); }
+__device__ __forceinline__ uint32_t byte_at(uint32_t w, int i) { return (w >> (8 * i)) & 0xFFu; }
+
+// One image as the segment decoder sees it.
+struct ImageView {
+  const int16_t* coef;
+  const uint16_t* qt;
+  uint8_t* rgb;
+  uint32_t pitch;  // < 2^24
+  int width, height;
+  int mcus_x, mcus_y;
+  int chroma_w, chroma_h;
+  int qsel0, qsel1, qsel2;
+  int aligned_out;
+};
+
+// Segment = MCU columns [mx0, mx0 + SX) (clipped) x MCU rows [r0, r1).
+struct SegmentRange {
+  int mx0, r0, r1;
+};
+
+template <int HF_, int VF_, bool FANCY_, int SX_, int SY_, int NT_>
+struct SegCfg {
+  static constexpr int HF = HF_, VF = VF_, SX = SX_, SY = SY_, NT = NT_;
+  static constexpr bool FANCY = FANCY_;
+  static constexpr int NY = HF * VF;
+  static constexpr int BPM = NY + 2;
+  static constexpr bool HALO_X = FANCY && HF == 2;
+  static constexpr bool HALO_Y = FANCY && VF == 2;
+  static constexpr int LAG = HALO_Y ? 2 : 1;
+  static constexpr int SM = SX * SY;                       // MCUs per sub-tile
+  static constexpr int N_MAIN = BPM * SM;                  // blocks per sub-tile
+  static constexpr int N_SIDE = HALO_X ? 4 * SY : 0;       // left/right neighbour chroma blocks
+  static constexpr int N_SLOT = N_MAIN + N_SIDE;           // staged blocks
+  static constexpr int SIDE_LANE0 = round64c(N_MAIN);      // first lane of the side tasks
+  static constexpr int P1_LANES = SIDE_LANE0 + 8 * N_SIDE;
+  static constexpr int N_TB = HALO_Y ? 2 * (SX + 2) : 0;   // above or below neighbour blocks
+  static constexpr int YWD = SX * 2 * HF;                  // luma sub-tile row, dwords
+  static constexpr int YROWS = SY * 8 * VF;
+  static constexpr int NYB = LAG + 1;                      // luma buffers in flight
+  static constexpr int CWD = (SX + 2) * 2;                 // chroma ring row, dwords (8-sample margins)
+  static constexpr int CROWS = (HALO_Y ? 4 : 2) * 8 * SY;  // chroma ring rows
+  static constexpr int UX = 2 * SX;                        // phase-2 units per chroma row
+  static constexpr int UNITS = UX * 8 * SY;
+  // LDS carve-up (bytes, 16-byte aligned pieces)
+  static constexpr int OFF_STAGE = 0;
+  static constexpr int OFF_Y = OFF_STAGE + N_SLOT * 128;
+  static constexpr int OFF_C = OFF_Y + NYB * YROWS * YWD * 4;
+  static constexpr int OFF_Q = OFF_C + 2 * CROWS * CWD * 4;
+  static constexpr int OFF_WS = OFF_Q + 3 * 128;
+  static constexpr int OFF_WT = OFF_WS + (N_SIDE > 0 ? N_SIDE * 256 : 16);
+  static constexpr int LDS_BYTES = OFF_WT + (N_TB > 0 ? N_TB * 32 : 16);
+  static_assert(P1_LANES <= NT, "one phase-1 round per sub-tile");
+  static_assert(NT % 64 == 0 && NT >= 96, "whole waves; quant table load needs 96 lanes");
+  static_assert(N_MAIN % 64 == 0, "tile blocks fill whole waves");
+};
+
+template <class C>
+struct SegmentDecoder {
+  static constexpr int HF = C::HF, VF = C::VF, SX = C::SX, SY = C::SY, NT = C::NT;
+  static constexpr int NY = C::NY, BPM = C::BPM, SM = C::SM, N_MAIN = C::N_MAIN;
+  static constexpr int N_SIDE = C::N_SIDE, N_SLOT = C::N_SLOT, N_TB = C::N_TB;
+  static constexpr int YWD = C::YWD, YROWS = C::YROWS, NYB = C::NYB, CWD = C::CWD, CROWS = C::CROWS;
+  static constexpr int LAG = C::LAG;
+  static constexpr bool FANCY = C::FANCY, HALO_X = C::HALO_X, HALO_Y = C::HALO_Y;
+
+  uint8_t* lds;
+  const ImageView& im;
+  int tid;
+  // segment geometry
+  int mx0, nmx, r0, r1, K;
+  int gcx0;  // global chroma column of the strip's first sample
+
+  __device__ SegmentDecoder(uint8_t* lds_, const ImageView& im_, int tid_) : lds(lds_), im(im_), tid(tid_) {}
+
+  __device__ uint8_t* stage() const { return lds + C::OFF_STAGE; }
+  __device__ uint32_t* ybuf(int k) const { return reinterpret_cast<uint32_t*>(lds + C::OFF_Y) + (k % NYB) * (YROWS * YWD); }
+  __device__ uint32_t* cring(int c) const { return reinterpret_cast<uint32_t*>(lds + C::OFF_C) + c * (CROWS * CWD); }
+  __device__ uint32_t* qtab(int c) const { return reinterpret_cast<uint32_t*>(lds + C::OFF_Q) + c * 32; }
+  __device__ int* wside() const { return reinterpret_cast<int*>(lds + C::OFF_WS); }
+  __device__ int* wtb() const { return reinterpret_cast<int*>(lds + C::OFF_WT); }
+  __device__ static int ring_row(int gy) { return (gy + CROWS) % CROWS; }
+
+  __device__ int sub_r0(int k) const { return r0 + k * SY; }
+  __device__ int sub_rows(int k) const { return min(SY, r1 - (r0 + k * SY)); }
+
+  __device__ const int16_t* block_ptr(int my, int mx, int b) const {
+    return im.coef + (static_cast<size_t>(my) * im.mcus_x + mx) * (BPM * 64) + b * 64;
+  }
+
+  // Global address of staged block `j` of sub-tile k, or null when absent.
+  __device__ const int16_t* slot_src(int k, int j) const {
+    const int my0 = sub_r0(k), nmy = sub_rows(k);
+    if (j < N_MAIN) {
+      const int b = j / SM;
+      const int m = j - b * SM;
+      const int lmy = m / SX, lmx = m - (m / SX) * SX;
+      if (lmx >= nmx || lmy >= nmy) return nullptr;
+      return block_ptr(my0 + lmy, mx0 + lmx, b);
+    }
+    const int t = j - N_MAIN;  // (row << 2) | (right << 1) | chroma component
+    const int pos = t >> 2;
+    const int mx = ((t >> 1) & 1) ? mx0 + nmx : mx0 - 1;
+    if (pos >= nmy || mx < 0 || mx >= im.mcus_x) return nullptr;
+    return block_ptr(my0 + pos, mx, NY + (t & 1));
+  }
+
+  // Copy sub-tile k's blocks into the staging buffer.  16-byte chunk i lands
+  // at LDS i*16: block j = i/8 keeps its 8 rows rotated by j (row c at
+  // position (c + j) & 7), so that lanes reading whole blocks later hit
+  // distinct banks; the 8 lanes of a block still read one 128-byte line.
+  __device__ void dma(int k) const {
+    constexpr int CHUNKS = N_SLOT * 8;
+    for (int base = (tid & ~63); base < CHUNKS; base += NT) {
+      const int i = base + (tid & 63);
+      if (i < CHUNKS) {
+        const int j = i >> 3;
+        const int c = ((i & 7) - j) & 7;
+        const int16_t* src = slot_src(k, j);
+        if (src) __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + 8 * c),
+                                                 (lds_void_t*)(stage() + base * 16), 16, 0, 0);
+      }
+    }
+  }
+
+  __device__ void load_qtabs() const {
+    if (tid < 96) {
+      const int c = tid >> 5;
+      const int sel = c == 0 ? im.qsel0 : (c == 1 ? im.qsel1 : im.qsel2);
+      const uint16_t* q = im.qt + sel * 64 + 2 * (tid & 31);
+      qtab(c)[tid & 31] = static_cast<uint32_t>(q[0]) | (static_cast<uint32_t>(q[1]) << 16);
+    }
+  }
+
+  // ---- neighbour blocks above/below the segment (4:2:0 fancy) ----
+  // Step A: lanes (task, column u) read one column straight from global
+  // memory and form the single pass-1 output of the sample row the filter
+  // needs (7 for the block above, 0 for the block below).
+  __device__ void tb_step_a(bool below) const {
+    const int my = below ? r1 : r0 - 1;
+    if (my < 0 || my >= im.mcus_y) return;
+    for (int s = tid; s < 8 * N_TB; s += NT) {
+      const int t = s >> 3, u = s & 7;
+      const int pos = t >> 1;
+      const int mx = mx0 - 1 + pos;
+      if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) continue;
+      const int comp = t & 1;
+      const int16_t* col = block_ptr(my, mx, NY + comp) + u;
+      const uint16_t* q = reinterpret_cast<const uint16_t*>(qtab(1 + comp)) + u;
+      int x[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) x[v] = col[8 * v] * static_cast<int>(q[8 * v]);
+      const int o = below ? idct8_edge_raw<false>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias)
+                          : idct8_edge_raw<true>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias);
+      wtb()[t * 8 + u] = o >> kPass1Shift;
+    }
+  }
+
+  // Step B: one lane per neighbour block finishes the row pass and writes
+  // the 8 samples into the ring row above/below the segment; at the true
+  // left edge and at the true right chroma edge it also writes the
+  // replicated sample the filter reads beyond the edge.
+  __device__ void tb_step_b(bool below) const {
+    const int my = below ? r1 : r0 - 1;
+    if (my < 0 || my >= im.mcus_y || tid >= N_TB) return;
+    const int t = tid, pos = t >> 1;
+    const int mx = mx0 - 1 + pos;
+    if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) return;
+    const int* w = wtb() + t * 8;
+    int y[8];
+    idct8_raw(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias, y);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) y[i] >>= kPass2Shift;
+    uint32_t* row = cring(t & 1) + ring_row(below ? 8 * r1 : 8 * r0 - 1) * CWD;
+    row[2 * pos] = pack4(y[0], y[1], y[2], y[3]);
+    row[2 * pos + 1] = pack4(y[4], y[5], y[6], y[7]);
+    uint8_t* row8 = reinterpret_cast<uint8_t*>(row);
+    // the strip starts at the image's left edge: x = -1 repeats x = 0
+    if (mx0 == 0 && mx == 0) row8[7] = static_cast<uint8_t>(clamp255i(y[0]));
+    // the true right chroma edge lies in this strip: x = cw repeats x = cw - 1
+    const int cw = im.chroma_w;
+    if (cw - 1 < gcx0 + 8 * nmx && mx == ((cw - 1) >> 3))
+    {
+      int e = y[0];
+#pragma unroll
+      for (int i = 1; i < 8; ++i)
+        if (((cw - 1) & 7) == i) e = y[i];  // constant indices: y stays in registers
+      row8[cw - gcx0 + 8] = static_cast<uint8_t>(clamp255i(e));
+    }
+  }
+
+  // ---- phase 1 of sub-tile k ----
+  // Registers carried from the staging read (before the next DMA overwrites
+  // the buffer) to the transform.
+  struct Held {
+    v4i r0, r1, r2, r3, r4, r5, r6, r7;  // named members: always promoted to registers
+    __device__ __forceinline__ void set(int c, v4i v) {
+      switch (c) {  // c is a compile-time constant after unrolling
+        case 0: r0 = v; break;
+        case 1: r1 = v; break;
+        case 2: r2 = v; break;
+        case 3: r3 = v; break;
+        case 4: r4 = v; break;
+        case 5: r5 = v; break;
+        case 6: r6 = v; break;
+        default: r7 = v; break;
+      }
+    }
+  };
+
+  __device__ void read_stage(int k, Held& h) const {
+    if (tid < N_MAIN) {
+      const int j = tid;
+      const uint8_t* blk = stage() + j * 128;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) h.set(c, *reinterpret_cast<const v4i*>(blk + (((c + j) & 7) << 4)));
+    } else if constexpr (HALO_X) {
+      if (tid >= C::SIDE_LANE0 && tid < C::P1_LANES) {
+        const int t = (tid - C::SIDE_LANE0) >> 3, u = tid & 7;
+        const int j = N_MAIN + t;
+        const uint8_t* blk = stage() + j * 128 + 2 * u;
+        int x[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) x[v] = *reinterpret_cast<const int16_t*>(blk + (((v + j) & 7) << 4));
+        h.r0 = v4i{x[0], x[1], x[2], x[3]};
+        h.r1 = v4i{x[4], x[5], x[6], x[7]};
+      }
+    }
+    (void)k;
+  }
+
+  __device__ void phase1(int k, const Held& h) const {
+    const int my0 = sub_r0(k), nmy = sub_rows(k);
+    if (tid < N_MAIN) {
+      const int j = tid;
+      const int b = j / SM;
+      const int m = j - b * SM;
+      const int lmy = m / SX, lmx = m - (m / SX) * SX;
+      if (lmx >= nmx || lmy >= nmy) return;
+      const int comp = b < NY ? 0 : b - NY + 1;
+      uint32_t o[16];
+      const v4i rows[8] = {h.r0, h.r1, h.r2, h.r3, h.r4, h.r5, h.r6, h.r7};
+      idct_block_regs(rows, qtab(comp), o);
+      if (comp == 0) {
+        const int by = b / HF, bx = b - (b / HF) * HF;
+        uint32_t* dst = ybuf(k) + (lmy * 8 * VF + by * 8) * YWD + lmx * 2 * HF + bx * 2;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          dst[r * YWD] = o[2 * r];
+          dst[r * YWD + 1] = o[2 * r + 1];
+        }
+      } else {
+        uint32_t* dst = cring(comp - 1) + ring_row(8 * (my0 + lmy)) * CWD + lmx * 2 + 2;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          dst[r * CWD] = o[2 * r];
+          dst[r * CWD + 1] = o[2 * r + 1];
+        }
+      }
+    } else if constexpr (HALO_X) {
+      if (tid >= C::SIDE_LANE0 && tid < C::P1_LANES) {
+        const int t = (tid - C::SIDE_LANE0) >> 3, u = tid & 7;
+        const int pos = t >> 2;
+        const int mx = ((t >> 1) & 1) ? mx0 + nmx : mx0 - 1;
+        if (pos >= nmy || mx < 0 || mx >= im.mcus_x) return;
+        const uint16_t* q = reinterpret_cast<const uint16_t*>(qtab(1 + (t & 1))) + u;
+        int x[8] = {h.r0.x, h.r0.y, h.r0.z, h.r0.w, h.r1.x, h.r1.y, h.r1.z, h.r1.w};
+#pragma unroll
+        for (int v = 0; v < 8; ++v) x[v] *= static_cast<int>(q[8 * v]);
+        int y[8];
+        idct8_raw(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias, y);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) wside()[t * 64 + i * 8 + u] = y[i] >> kPass1Shift;
+      }
+    }
+  }
+
+  // After phase 1 of k (and a barrier): finish the left/right neighbour
+  // blocks (one lane per sample row, one output each) and replicate samples
+  // beyond the true left/right chroma edges into the ring.
+  __device__ void phase1_finish(int k) const {
+    const int my0 = sub_r0(k), nmy = sub_rows(k);
+    if constexpr (HALO_X) {
+      for (int s = tid; s < 8 * N_SIDE; s += NT) {
+        const int t = s >> 3, i = s & 7;
+        const int pos = t >> 2;
+        const bool right = (t >> 1) & 1;
+        const int mx = right ? mx0 + nmx : mx0 - 1;
+        if (pos >= nmy || mx < 0 || mx >= im.mcus_x) continue;
+        const int* w = wside() + t * 64 + i * 8;
+        const int v = right ? idct8_edge_raw<false>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias)
+                            : idct8_edge_raw<true>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias);
+        uint8_t* row8 = reinterpret_cast<uint8_t*>(cring(t & 1) + ring_row(8 * (my0 + pos) + i) * CWD);
+        row8[right ? nmx * 8 + 8 : 7] = static_cast<uint8_t>(clamp255i(v >> kPass2Shift));
+      }
+      const int cw = im.chroma_w;
+      const bool left_edge = gcx0 == 0;
+      const bool right_edge = cw - 1 < gcx0 + 8 * nmx;
+      if (left_edge || right_edge) {
+        const int rows = 8 * nmy;
+        for (int s = tid; s < 4 * rows; s += NT) {
+          const int c = s & 1;
+          const bool is_right = (s >> 1) >= rows;
+          const int rr = (s >> 1) - (is_right ? rows : 0);
+          if (is_right ? !right_edge : !left_edge) continue;
+          uint8_t* row8 = reinterpret_cast<uint8_t*>(cring(c) + ring_row(8 * my0 + rr) * CWD);
+          if (is_right) row8[cw - gcx0 + 8] = row8[cw - 1 - gcx0 + 8];
+          else row8[7] = row8[8];
+        }
+      }
+    }
+  }
+
+  // Rows beyond the true top/bottom chroma edge of sub-tile k (4:2:0 fancy):
+  // copy the edge row, margins included.  Runs one step after phase1_finish.
+  __device__ void vertical_edges(int k) const {
+    if constexpr (HALO_Y) {
+      const int gy0 = 8 * sub_r0(k), rows = 8 * sub_rows(k);
+      const int ch = im.chroma_h;
+      const bool top = gy0 == 0;
+      const bool bottom = ch - 1 < gy0 + rows;
+      if (!top && !bottom) return;
+      for (int s = tid; s < 4 * CWD; s += NT) {
+        const int c = s & 1;
+        const bool is_bottom = (s >> 1) >= CWD;
+        const int d = (s >> 1) - (is_bottom ? CWD : 0);
+        if (is_bottom ? !bottom : !top) continue;
+        uint32_t* ring = cring(c);
+        if (is_bottom) ring[ring_row(ch) * CWD + d] = ring[ring_row(ch - 1) * CWD + d];
+        else ring[ring_row(-1) * CWD + d] = ring[ring_row(0) * CWD + d];
+      }
+    }
+  }
+
+  // ---- phase 2 of sub-tile k: upsample + colour + store ----
+  __device__ void phase2(int k) const {
+    const int my0 = sub_r0(k), nmy = sub_rows(k);
+    const int gcy0 = 8 * my0;
+    const int W = im.width, H = im.height;
+    const uint32_t* ys = ybuf(k);
+    uint8_t* const sub_rgb = im.rgb + static_cast<size_t>(gcy0 * VF) * im.pitch + static_cast<size_t>(gcx0 * HF) * 3;
+    const int pitch24 = static_cast<int>(im.pitch);
+    for (int uidx = tid; uidx < C::UNITS; uidx += NT) {
+      const int cr_l = uidx / C::UX;
+      const int g = uidx - cr_l * C::UX;
+      if (g >= 2 * nmx || cr_l >= 8 * nmy) continue;
+      const int px0 = (gcx0 + 4 * g) * HF;
+      const int py0 = (gcy0 + cr_l) * VF;
+      if (px0 >= W || py0 >= H) continue;
+
+      int xb[VF][4 * HF], xr[VF][4 * HF];  // chroma - 128 per output pixel
+      const int rc = ring_row(gcy0 + cr_l);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const uint32_t* ring = cring(c);
+        const uint32_t* plane = ring + rc * CWD + g + 2;
+        int out[VF][4 * HF];
+        if constexpr (!FANCY || HF == 1) {
+          const uint32_t w = plane[0];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int dy = 0; dy < VF; ++dy)
+#pragma unroll
+              for (int dx = 0; dx < HF; ++dx) out[dy][i * HF + dx] = static_cast<int>(byte_at(w, i)) - 128;
+        } else {
+          int cc[6];
+          {
+            const uint32_t l = plane[-1], m = plane[0], r = plane[1];
+            cc[0] = byte_at(l, 3);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cc[1 + i] = byte_at(m, i);
+            cc[5] = byte_at(r, 0);
+          }
+          if constexpr (VF == 1) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int m3 = 3 * cc[1 + i];
+              out[0][2 * i] = (m3 + cc[i] - 511) >> 2;          // (3C + Cprev + 1) / 4 - 128
+              out[0][2 * i + 1] = (m3 + cc[i + 2] - 510) >> 2;  // (3C + Cnext + 2) / 4 - 128
+            }
+          } else {
+            int su[6], sd[6];
+            {
+              const uint32_t* up = ring + ring_row(gcy0 + cr_l - 1) * CWD + g + 2;
+              const uint32_t* dn = ring + ring_row(gcy0 + cr_l + 1) * CWD + g + 2;
+              const uint32_t ul = up[-1], um = up[0], ur = up[1];
+              const uint32_t dl = dn[-1], dm = dn[0], dr = dn[1];
+              const int cu[6] = {static_cast<int>(byte_at(ul, 3)), static_cast<int>(byte_at(um, 0)),
+                                 static_cast<int>(byte_at(um, 1)), static_cast<int>(byte_at(um, 2)),
+                                 static_cast<int>(byte_at(um, 3)), static_cast<int>(byte_at(ur, 0))};
+              const int cd[6] = {static_cast<int>(byte_at(dl, 3)), static_cast<int>(byte_at(dm, 0)),
+                                 static_cast<int>(byte_at(dm, 1)), static_cast<int>(byte_at(dm, 2)),
+                                 static_cast<int>(byte_at(dm, 3)), static_cast<int>(byte_at(dr, 0))};
+#pragma unroll
+              for (int j = 0; j < 6; ++j) {
+                const int m3 = 3 * cc[j];
+                su[j] = m3 + cu[j];  // unrounded vertical triangle sums
+                sd[j] = m3 + cd[j];
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              out[0][2 * i] = (3 * su[1 + i] + su[i] - 2040) >> 4;          // (.. + 8) / 16 - 128
+              out[0][2 * i + 1] = (3 * su[1 + i] + su[i + 2] - 2041) >> 4;  // (.. + 7) / 16 - 128
+              out[VF - 1][2 * i] = (3 * sd[1 + i] + sd[i] - 2040) >> 4;
+              out[VF - 1][2 * i + 1] = (3 * sd[1 + i] + sd[i + 2] - 2041) >> 4;
+            }
+          }
+        }
+#pragma unroll
+        for (int dy = 0; dy < VF; ++dy)
+#pragma unroll
+          for (int i = 0; i < 4 * HF; ++i) {
+            if (c) xr[dy][i] = out[dy][i];
+            else xb[dy][i] = out[dy][i];
+          }
+      }
+
+      const int nv = min(4 * HF, W - px0);
+#pragma unroll
+      for (int dy = 0; dy < VF; ++dy) {
+        const int py = py0 + dy;
+        if (py >= H) break;
+        const uint32_t* yrow = ys + (cr_l * VF + dy) * YWD + g * HF;
+        uint32_t w[3 * HF];
+#pragma unroll
+        for (int kk = 0; kk < HF; ++kk) {
+          const uint32_t ydw = yrow[kk];
+          RGBWide px[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) px[i] = ycc_wide(y16_of(ydw, i), xb[dy][4 * kk + i], xr[dy][4 * kk + i]);
+          pack_rgb4(px, w + 3 * kk);
+        }
+        uint8_t* row = sub_rgb + (mul24(cr_l * VF + dy, pitch24) + 12 * HF * g);
+        if (nv == 4 * HF && im.aligned_out) {
+          uint32_t* wd = reinterpret_cast<uint32_t*>(row);
+#pragma unroll
+          for (int kk = 0; kk < 3 * HF; ++kk) wd[kk] = w[kk];
+        } else {
+          store_ragged(row, w, 3 * nv);
+        }
+      }
+    }
+  }
+
+  // Ragged right edge: byte stores of the first nbytes bytes of w (constant
+  // register indices; the run is at most 12*HF bytes).
+  __device__ static void store_ragged(uint8_t* row, const uint32_t* w, int nbytes) {
+#pragma unroll
+    for (int kk = 0; kk < 3 * HF; ++kk)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (4 * kk + b < nbytes) row[4 * kk + b] = static_cast<uint8_t>(w[kk] >> (8 * b));
+  }
+
+  // ---- the pipelined walk over one segment ----
+  __device__ void run(const SegmentRange& seg) {
+    mx0 = seg.mx0;
+    nmx = min(SX, im.mcus_x - mx0);
+    r0 = seg.r0;
+    r1 = seg.r1;
+    K = (r1 - r0 + SY - 1) / SY;
+    gcx0 = 8 * mx0;
+
+    __syncthreads();  // the previous segment's readers are done with every buffer
+    load_qtabs();
+    dma(0);
+    __syncthreads();  // quant tables visible
+    if constexpr (HALO_Y) tb_step_a(false);
+
+    for (int k = 0; k < K + LAG; ++k) {
+      Held h{};  // per step, fully defined so it stays in registers
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();  // staging of k landed; last step's LDS writes visible
+      if constexpr (HALO_Y) {
+        if (k == 0) tb_step_b(false);
+        if (k >= 1 && k - 1 < K) vertical_edges(k - 1);
+        if (k == K) tb_step_a(true);
+      }
+      // stores of the older sub-tile first: they drain while phase 1 computes
+      if (k >= LAG) phase2(k - LAG);
+      if (k < K) read_stage(k, h);
+      __syncthreads();  // staging free for the next sub-tile
+      if (k + 1 < K) dma(k + 1);
+      if (k < K) phase1(k, h);
+      __syncthreads();
+      if (k < K) phase1_finish(k);
+      if constexpr (HALO_Y) {
+        if (k == K) tb_step_b(true);
+      }
+    }
+  }
+};
+
+}  // namespace mjd

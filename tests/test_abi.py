@@ -28,7 +28,7 @@ def declared_functions():
 
 def test_library_exports_every_declared_symbol():
     names = declared_functions()
-    assert {"mjd_decode", "mjd_geometry_of", "mjd_ctx_create", "mjd_last_error"} <= names
+    assert {"mjd_decode", "mjd_geometry_of", "mjd_ctx_create", "mjd_last_error", "mjd_ctx_set_tuning"} <= names
     lib = ctypes.CDLL(B.LIB_PATH)
     missing = [n for n in sorted(names) if not hasattr(lib, n)]
     assert not missing, missing
@@ -63,6 +63,12 @@ def test_geometry_rejects_bad_frames(bad, code):
         B.mjd_geometry_of(f)
     assert ei.value.code == code
     assert B.mjd_last_error()
+
+
+def test_tuning_rejects_null_context():
+    t = B.mjd_tuning(2, 8)
+    assert B.lib().mjd_ctx_set_tuning(None, ctypes.byref(t)) == B.MJD_EINVAL
+    assert B.lib().mjd_ctx_get_tuning(None, ctypes.byref(t)) == B.MJD_EINVAL
 
 
 def test_frame_struct_layout():

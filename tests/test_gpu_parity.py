@@ -167,3 +167,33 @@ def test_copy_probe_copies(M, ctx):
     M.mjd_copy(ctx, dst, src, src.numel())
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+
+
+@pytest.mark.parametrize("samp,mode", [("420", "fancy"), ("420", "simple"), ("422", "fancy"),
+                                       ("422", "simple"), ("444", "simple")])
+def test_launch_shapes_bit_exact(M, ctx, samp, mode):
+    """Segments of several sub-tiles (the prefetch pipeline and the chroma
+    ring), few workgroups (each takes many segments), and bands: the output
+    never depends on the launch shape."""
+    rgb = images.texture_rgb(523, 437, 31, sigma=12)
+    frame, coef, qt = encode.encode_rgb(rgb, samp, 83)
+    exp = oracle.decode(frame, coef, qt, mode)
+    g = oracle.geometry(frame)
+    c, q = to_dev(coef, qt)
+    try:
+        for seg, wgs in ((1, 0), (2, 0), (3, 8), (7, 0), (64, 0), (5, 16), (0, 8)):
+            M.mjd_ctx_set_tuning(ctx, seg, wgs)
+            say(f"shape {samp} {mode} seg_subtiles={seg} max_workgroups={wgs}")
+            out = M.decode(ctx, frame, c, q, mode)
+            torch.cuda.synchronize()
+            assert_same(out.cpu().numpy(), exp, f"{samp} {mode} seg={seg} wgs={wgs}")
+            for r0, r1 in ((3, g["mcus_y"] - 2), (g["mcus_y"] - 5, g["mcus_y"])):
+                band = torch.full((frame["height"], frame["width"], 3), 5, dtype=torch.uint8, device="cuda")
+                M.decode(ctx, frame, c, q, mode, out=band, rows=(r0, r1))
+                torch.cuda.synchronize()
+                got = band.cpu().numpy()
+                y0, y1 = r0 * g["mcu_h"], min(frame["height"], r1 * g["mcu_h"])
+                assert_same(got[y0:y1], exp[y0:y1], f"band {r0}..{r1} seg={seg} wgs={wgs}")
+                assert np.all(got[:y0] == 5) and np.all(got[y1:] == 5)
+    finally:
+        M.mjd_ctx_set_tuning(ctx, 0, 0)
