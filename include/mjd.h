@@ -145,6 +145,44 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef,
                const uint16_t* d_qt, int upsample, uint8_t* d_rgb, size_t pitch,
                uint32_t mcu_row0, uint32_t mcu_row1, void* stream);
 
+/* One image of a batch: its frame, device buffers and output pitch, with
+ * the same meaning and constraints as the arguments of mjd_decode (whole
+ * image: MCU rows [0, mcus_y)). */
+typedef struct mjd_job {
+  mjd_frame frame;
+  const int16_t* d_coef;
+  const uint16_t* d_qt;
+  uint8_t* d_rgb;
+  size_t pitch;
+} mjd_job;
+
+/* A planned batch: device tables describing many images and the work queue
+ * over them, owned by the library until mjd_batch_destroy. */
+typedef struct mjd_batch mjd_batch;
+
+/* Plan a batch of `n` images of any supported sizes and samplings, all
+ * decoded with the same upsampling mode.  Validates every job (an invalid job
+ * fails the whole call, naming the job), cuts every image into segments of
+ * sub-tiles (the paper's horizontal chunks, Sec. 4.5, here also cut into MCU
+ * columns) and uploads the per-image views and the segment queue, longest
+ * segments first, to device memory (synchronous).  The launch shape follows
+ * the context's tuning at the time of this call.  The device buffers named by
+ * the jobs are only recorded, not accessed. */
+int mjd_batch_create(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, mjd_batch** out);
+
+/* Enqueue the whole batch as ONE persistent kernel on `stream`: resident
+ * workgroups pop segments from a device counter until the queue is empty;
+ * the last workgroup rearms the counter.  use_graph != 0 launches it through
+ * a hipGraph instantiated on first use and replayed afterwards.  Launches of
+ * one batch must be serialised (one stream); each writes every job's output. */
+int mjd_batch_launch(mjd_batch* batch, int use_graph, void* stream);
+
+/* Segments in the queue, workgroups per launch and total pixels. */
+int mjd_batch_info(const mjd_batch* batch, uint32_t* segments, uint32_t* workgroups, uint64_t* pixels);
+
+/* Synchronise the device and free the batch's tables and graph. */
+void mjd_batch_destroy(mjd_batch* batch);
+
 /* Device-to-device streaming copy of `bytes` bytes (a multiple of 16; both
  * pointers 16-byte aligned), enqueued on `stream`.  It is the bandwidth
  * reference for the decoder: a plain read+write stream at the rate this

@@ -52,6 +52,11 @@ class mjd_tuning(ctypes.Structure):
     _fields_ = [("seg_subtiles", ctypes.c_uint32), ("max_workgroups", ctypes.c_uint32)]
 
 
+class mjd_job(ctypes.Structure):
+    _fields_ = [("frame", mjd_frame), ("d_coef", ctypes.c_void_p), ("d_qt", ctypes.c_void_p),
+                ("d_rgb", ctypes.c_void_p), ("pitch", ctypes.c_size_t)]
+
+
 _lib = None
 
 
@@ -75,6 +80,14 @@ def lib() -> ctypes.CDLL:
         L.mjd_ctx_set_tuning.restype = i32
         L.mjd_ctx_get_tuning.argtypes = [vp, ctypes.POINTER(mjd_tuning)]
         L.mjd_ctx_get_tuning.restype = i32
+        L.mjd_batch_create.argtypes = [vp, ctypes.POINTER(mjd_job), sz, i32, ctypes.POINTER(vp)]
+        L.mjd_batch_create.restype = i32
+        L.mjd_batch_launch.argtypes = [vp, i32, vp]
+        L.mjd_batch_launch.restype = i32
+        L.mjd_batch_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_uint64)]
+        L.mjd_batch_info.restype = i32
+        L.mjd_batch_destroy.argtypes = [vp]
+        L.mjd_batch_destroy.restype = None
         L.mjd_copy.argtypes = [vp, vp, vp, sz, vp]
         L.mjd_copy.restype = i32
         L.mjd_last_error.argtypes = []
@@ -181,3 +194,52 @@ def mjd_decode(ctx: Context, frame, coef, qt, upsample: int, rgb, pitch: int,
 
 def mjd_copy(ctx: Context, dst, src, nbytes: int, stream=None):
     _check(lib().mjd_copy(ctx.handle, _ptr(dst), _ptr(src), int(nbytes), _stream(stream)))
+
+
+class Batch:
+    """Owns an mjd_batch*: a planned set of images decoded by one persistent launch."""
+
+    def __init__(self, ctx: Context, jobs, upsample: int):
+        arr = (mjd_job * len(jobs))()
+        for i, (frame, coef, qt, rgb, pitch) in enumerate(jobs):
+            arr[i].frame = make_frame(frame)
+            arr[i].d_coef = _ptr(coef)
+            arr[i].d_qt = _ptr(qt)
+            arr[i].d_rgb = _ptr(rgb)
+            arr[i].pitch = int(pitch)
+        p = ctypes.c_void_p()
+        _check(lib().mjd_batch_create(ctx.handle, arr, len(jobs), int(upsample), ctypes.byref(p)))
+        self.handle = p
+        self._keep = jobs  # the device buffers must outlive the batch
+
+    def info(self) -> dict:
+        seg, wg, px = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        _check(lib().mjd_batch_info(self.handle, ctypes.byref(seg), ctypes.byref(wg), ctypes.byref(px)))
+        return {"segments": seg.value, "workgroups": wg.value, "pixels": px.value}
+
+    def launch(self, use_graph: bool = False, stream=None):
+        _check(lib().mjd_batch_launch(self.handle, int(bool(use_graph)), _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().mjd_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mjd_batch_create(ctx: Context, jobs, upsample: int) -> Batch:
+    """jobs: sequence of (frame, coef, qt, rgb, pitch) with device tensors or addresses."""
+    return Batch(ctx, jobs, upsample)
+
+
+def mjd_batch_launch(batch: Batch, use_graph: bool = False, stream=None):
+    batch.launch(use_graph, stream)
+
+
+def mjd_batch_destroy(batch: Batch):
+    batch.close()

@@ -14,7 +14,7 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libmjd.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["api.hip", "decode.hip", "copy.hip"]
+SOURCES = ["api.hip", "decode.hip", "batch.hip", "copy.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

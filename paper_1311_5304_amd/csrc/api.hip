@@ -49,6 +49,34 @@ int frame_geometry(const mjd_frame* f, mjd_geometry* g) {
   return MJD_OK;
 }
 
+int job_view(const mjd_job* j, int upsample, ImageView* im, mjd_geometry* g) {
+  if (!j) return fail(MJD_EINVAL, "null job");
+  int rc = frame_geometry(&j->frame, g);
+  if (rc != MJD_OK) return rc;
+  if (!j->d_coef || !j->d_qt || !j->d_rgb) return fail(MJD_EINVAL, "null device buffer");
+  if (reinterpret_cast<uintptr_t>(j->d_coef) % 16) return fail(MJD_EINVAL, "coefficient buffer not 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(j->d_qt) % 2) return fail(MJD_EINVAL, "quant table buffer not 2-byte aligned");
+  if (upsample != MJD_UPSAMPLE_SIMPLE && upsample != MJD_UPSAMPLE_FANCY)
+    return fail(MJD_EINVAL, "upsample mode %d unknown", upsample);
+  if (j->pitch < 3ull * j->frame.width) return fail(MJD_EINVAL, "pitch %zu < 3*width", j->pitch);
+  if (j->pitch >= (1ull << 24)) return fail(MJD_EINVAL, "pitch %zu not below 2^24 bytes", j->pitch);
+  im->coef = j->d_coef;
+  im->qt = j->d_qt;
+  im->rgb = j->d_rgb;
+  im->pitch = static_cast<uint32_t>(j->pitch);
+  im->width = static_cast<int>(j->frame.width);
+  im->height = static_cast<int>(j->frame.height);
+  im->mcus_x = static_cast<int>(g->mcus_x);
+  im->mcus_y = static_cast<int>(g->mcus_y);
+  im->chroma_w = static_cast<int>(g->comp_w[1]);
+  im->chroma_h = static_cast<int>(g->comp_h[1]);
+  im->qsel0 = j->frame.qsel[0];
+  im->qsel1 = j->frame.qsel[1];
+  im->qsel2 = j->frame.qsel[2];
+  im->aligned_out = (reinterpret_cast<uintptr_t>(j->d_rgb) % 4 == 0 && j->pitch % 4 == 0) ? 1 : 0;
+  return MJD_OK;
+}
+
 }  // namespace mjd
 
 extern "C" {
@@ -94,37 +122,18 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef, cons
                void* stream) {
   g_err[0] = 0;
   if (!ctx) return mjd::fail(MJD_EINVAL, "null context");
+  if (!frame) return mjd::fail(MJD_EINVAL, "null frame");
+  mjd_job job{*frame, d_coef, d_qt, d_rgb, pitch};
+  mjd::ImageView im{};
   mjd_geometry g;
-  int rc = mjd::frame_geometry(frame, &g);
+  int rc = mjd::job_view(&job, upsample, &im, &g);
   if (rc != MJD_OK) return rc;
-  if (!d_coef || !d_qt || !d_rgb) return mjd::fail(MJD_EINVAL, "null device buffer");
-  if (reinterpret_cast<uintptr_t>(d_coef) % 16) return mjd::fail(MJD_EINVAL, "coefficient buffer not 16-byte aligned");
-  if (reinterpret_cast<uintptr_t>(d_qt) % 2) return mjd::fail(MJD_EINVAL, "quant table buffer not 2-byte aligned");
-  if (upsample != MJD_UPSAMPLE_SIMPLE && upsample != MJD_UPSAMPLE_FANCY)
-    return mjd::fail(MJD_EINVAL, "upsample mode %d unknown", upsample);
-  if (pitch < 3ull * frame->width) return mjd::fail(MJD_EINVAL, "pitch %zu < 3*width", pitch);
-  if (pitch >= (1ull << 24)) return mjd::fail(MJD_EINVAL, "pitch %zu not below 2^24 bytes", pitch);
   if (mcu_row0 >= mcu_row1 || mcu_row1 > g.mcus_y)
     return mjd::fail(MJD_EINVAL, "MCU rows [%u,%u) not inside [0,%u)", mcu_row0, mcu_row1, g.mcus_y);
   int cur = 0;
   if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
     if (hipSetDevice(ctx->device) != hipSuccess) return mjd::fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
   }
-  mjd::ImageView im{};
-  im.coef = d_coef;
-  im.qt = d_qt;
-  im.rgb = d_rgb;
-  im.pitch = static_cast<uint32_t>(pitch);
-  im.width = static_cast<int>(frame->width);
-  im.height = static_cast<int>(frame->height);
-  im.mcus_x = static_cast<int>(g.mcus_x);
-  im.mcus_y = static_cast<int>(g.mcus_y);
-  im.chroma_w = static_cast<int>(g.comp_w[1]);
-  im.chroma_h = static_cast<int>(g.comp_h[1]);
-  im.qsel0 = frame->qsel[0];
-  im.qsel1 = frame->qsel[1];
-  im.qsel2 = frame->qsel[2];
-  im.aligned_out = (reinterpret_cast<uintptr_t>(d_rgb) % 4 == 0 && pitch % 4 == 0) ? 1 : 0;
   hipError_t e = mjd::launch_image(im, static_cast<int>(mcu_row0), static_cast<int>(mcu_row1), frame->h[0],
                                    frame->v[0], upsample == MJD_UPSAMPLE_FANCY, ctx->cu_count, ctx->tuning,
                                    static_cast<hipStream_t>(stream));
