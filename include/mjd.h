@@ -183,6 +183,75 @@ int mjd_batch_info(const mjd_batch* batch, uint32_t* segments, uint32_t* workgro
 /* Synchronise the device and free the batch's tables and graph. */
 void mjd_batch_destroy(mjd_batch* batch);
 
+/* ---------------------------------------------------------------------
+ * Host side: baseline JPEG bitstreams -> coefficient blocks.
+ *
+ * The paper keeps entropy decoding on the CPU because Huffman code words
+ * have variable length, which makes it sequential (Sec. 1; Sec. 4.5).  Here
+ * the restart intervals of the scan (DRI/RSTn, T.81 B.2.4.4 and F.2) are
+ * independent, so several host threads decode them at once.  The frame
+ * structure read here is the one the paper lists (Sec. 2): frame header with
+ * the dimensions and sampling factors, quantisation tables, Huffman tables,
+ * and the entropy-coded data.
+ * ------------------------------------------------------------------- */
+
+/* One Huffman table as a DHT segment defines it. */
+typedef struct mjd_huffman {
+  uint8_t bits[16];  /* number of codes of length 1..16 */
+  uint8_t vals[256]; /* symbols in order of increasing code */
+  uint32_t defined;  /* nonzero once a DHT segment defined the table */
+} mjd_huffman;
+
+/* Everything the entropy decoder needs about one baseline scan. */
+typedef struct mjd_scan {
+  mjd_frame frame;           /* frame header, in the form mjd_decode takes */
+  uint32_t restart_interval; /* MCUs per restart interval (DRI); 0 = none */
+  uint32_t n_intervals;      /* entropy-coded segments: ceil(MCUs / interval), or 1 */
+  uint64_t data_offset;      /* byte offset of the first entropy-coded byte */
+  uint64_t data_end;         /* byte offset of the EOI marker */
+  uint8_t dc_sel[3];         /* DC Huffman table per component (0..3) */
+  uint8_t ac_sel[3];         /* AC Huffman table per component (0..3) */
+  uint8_t reserved[2];
+  mjd_huffman dc[4];
+  mjd_huffman ac[4];
+} mjd_scan;
+
+/* Parse the markers of a baseline (SOF0/SOF1, 8-bit) JPEG held in host
+ * memory: SOI, DQT, SOF, DHT, DRI, one SOS over the three components in
+ * frame order (Ss=0, Se=63, Ah=Al=0), EOI; APPn and COM are skipped.
+ *   h_qt: receives uint16[4][64] in natural order (tables the stream does
+ *         not define are all ones).
+ * Returns MJD_ECORRUPT for malformed or truncated streams and
+ * MJD_EUNSUPPORTED for valid JPEG this library does not decode
+ * (progressive, arithmetic, 12-bit, not three components, sampling other
+ * than 4:4:4 / 4:2:2 / 4:2:0, more than one scan).  Reads only
+ * [h_jpg, h_jpg + len). */
+int mjd_parse(const uint8_t* h_jpg, size_t len, mjd_scan* scan, uint16_t h_qt[4][64]);
+
+/* Locate the restart intervals: h_offsets[i] (i < n_intervals) receives
+ * the byte offset of interval i's first entropy-coded byte, and
+ * h_offsets[n_intervals] the offset just past the EOI marker, so interval
+ * i's data ends 2 bytes (its RSTn or EOI marker) before h_offsets[i + 1],
+ * not counting 0xFF fill bytes.  h_offsets holds n_intervals + 1 entries.
+ * MJD_ECORRUPT if the RSTn markers are missing, out of sequence or too
+ * many. */
+int mjd_restart_index(const uint8_t* h_jpg, size_t len, const mjd_scan* scan, uint64_t* h_offsets);
+
+/* Huffman-decode MCU rows [mcu_row0, mcu_row1) into h_coef, which holds the
+ * whole image's n_blocks * 64 int16 in the MCU order mjd_decode reads
+ * (natural order inside a block, DC prediction applied).  Only the blocks
+ * of those rows are written.  Restart intervals that cover the rows are
+ * decoded by up to n_threads threads (created for this call; 1 = the
+ * calling thread only); an interval that starts before mcu_row0 is decoded
+ * from its start and its earlier MCUs are discarded.  Without restart
+ * markers the whole scan is one interval.  h_offsets is the output of
+ * mjd_restart_index, or NULL to have it computed here.  MJD_ECORRUPT for
+ * invalid codes, coefficient runs past the end of a block, or an interval
+ * that needs more bits than its data holds; the rows' contents are then
+ * unspecified.  Memory-safe for any input bytes. */
+int mjd_entropy_decode(const uint8_t* h_jpg, size_t len, const mjd_scan* scan, const uint64_t* h_offsets,
+                       int16_t* h_coef, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads);
+
 /* Device-to-device streaming copy of `bytes` bytes (a multiple of 16; both
  * pointers 16-byte aligned), enqueued on `stream`.  It is the bandwidth
  * reference for the decoder: a plain read+write stream at the rate this

@@ -7,7 +7,8 @@ from __future__ import annotations
 from ._binding import (MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE, Batch, Context, MjdError,  # noqa: F401
                        mjd_batch_create, mjd_batch_destroy, mjd_batch_launch,
                        mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
-                       mjd_decode, mjd_geometry_of, mjd_last_error)
+                       mjd_decode, mjd_entropy_decode, mjd_geometry_of, mjd_last_error, mjd_parse,
+                       mjd_restart_index, scan_frame)
 
 UPSAMPLE = {"simple": MJD_UPSAMPLE_SIMPLE, "fancy": MJD_UPSAMPLE_FANCY}
 
@@ -35,3 +36,19 @@ def decode(ctx: Context, frame, coef, qt, mode: str = "fancy", out=None, rows=No
     r0, r1 = rows if rows is not None else (0, g["mcus_y"])
     mjd_decode(ctx, frame, coef, qt, UPSAMPLE[mode], out, 3 * w, r0, r1, stream)
     return out
+
+
+def entropy_decode(jpg, n_threads: int = 1, out=None):
+    """Parse a baseline JPEG and Huffman-decode it on host threads.
+
+    -> (frame dict, coefficients int16 [n_blocks, 64] in MCU order, qt uint16 [4, 64]).
+    `out` may be a host buffer (numpy array or pinned tensor) of n_blocks*64 int16."""
+    import numpy as np
+
+    scan, qt = mjd_parse(jpg)
+    frame = scan_frame(scan)
+    g = mjd_geometry_of(frame)
+    off = mjd_restart_index(jpg, scan)
+    coef = np.empty((g["n_blocks"], 64), dtype=np.int16) if out is None else out
+    mjd_entropy_decode(jpg, scan, off, coef, 0, g["mcus_y"], n_threads)
+    return frame, coef, qt

@@ -57,6 +57,17 @@ class mjd_job(ctypes.Structure):
                 ("d_rgb", ctypes.c_void_p), ("pitch", ctypes.c_size_t)]
 
 
+class mjd_huffman(ctypes.Structure):
+    _fields_ = [("bits", ctypes.c_uint8 * 16), ("vals", ctypes.c_uint8 * 256), ("defined", ctypes.c_uint32)]
+
+
+class mjd_scan(ctypes.Structure):
+    _fields_ = [("frame", mjd_frame), ("restart_interval", ctypes.c_uint32), ("n_intervals", ctypes.c_uint32),
+                ("data_offset", ctypes.c_uint64), ("data_end", ctypes.c_uint64),
+                ("dc_sel", ctypes.c_uint8 * 3), ("ac_sel", ctypes.c_uint8 * 3), ("reserved", ctypes.c_uint8 * 2),
+                ("dc", mjd_huffman * 4), ("ac", mjd_huffman * 4)]
+
+
 _lib = None
 
 
@@ -88,6 +99,12 @@ def lib() -> ctypes.CDLL:
         L.mjd_batch_info.restype = i32
         L.mjd_batch_destroy.argtypes = [vp]
         L.mjd_batch_destroy.restype = None
+        L.mjd_parse.argtypes = [vp, sz, ctypes.POINTER(mjd_scan), vp]
+        L.mjd_parse.restype = i32
+        L.mjd_restart_index.argtypes = [vp, sz, ctypes.POINTER(mjd_scan), vp]
+        L.mjd_restart_index.restype = i32
+        L.mjd_entropy_decode.argtypes = [vp, sz, ctypes.POINTER(mjd_scan), vp, vp, u32, u32, i32]
+        L.mjd_entropy_decode.restype = i32
         L.mjd_copy.argtypes = [vp, vp, vp, sz, vp]
         L.mjd_copy.restype = i32
         L.mjd_last_error.argtypes = []
@@ -121,11 +138,14 @@ def make_frame(frame) -> mjd_frame:
 
 
 def _ptr(x) -> int:
+    """Address of a torch tensor, a numpy array or a raw integer address."""
     if x is None:
         return 0
     if isinstance(x, int):
         return x
-    return int(x.data_ptr())
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    return int(x.ctypes.data)
 
 
 def _stream(s) -> int:
@@ -243,3 +263,42 @@ def mjd_batch_launch(batch: Batch, use_graph: bool = False, stream=None):
 
 def mjd_batch_destroy(batch: Batch):
     batch.close()
+
+
+# ---- host side: bitstreams -> coefficients -------------------------------------------
+
+def _bytes_view(jpg):
+    import numpy as np
+    a = np.frombuffer(jpg, dtype=np.uint8) if isinstance(jpg, (bytes, bytearray, memoryview)) else jpg
+    return a, int(a.size)
+
+
+def mjd_parse(jpg):
+    """-> (mjd_scan, qt numpy uint16[4, 64])."""
+    import numpy as np
+    a, n = _bytes_view(jpg)
+    scan = mjd_scan()
+    qt = np.zeros((4, 64), dtype=np.uint16)
+    _check(lib().mjd_parse(_ptr(a), n, ctypes.byref(scan), _ptr(qt)))
+    return scan, qt
+
+
+def mjd_restart_index(jpg, scan: mjd_scan):
+    """-> numpy uint64[n_intervals + 1]."""
+    import numpy as np
+    a, n = _bytes_view(jpg)
+    off = np.zeros(scan.n_intervals + 1, dtype=np.uint64)
+    _check(lib().mjd_restart_index(_ptr(a), n, ctypes.byref(scan), _ptr(off)))
+    return off
+
+
+def mjd_entropy_decode(jpg, scan: mjd_scan, offsets, coef, row0: int, row1: int, n_threads: int = 1):
+    """Decode MCU rows [row0, row1) into `coef` (host array or pinned tensor of n_blocks*64 int16)."""
+    a, n = _bytes_view(jpg)
+    _check(lib().mjd_entropy_decode(_ptr(a), n, ctypes.byref(scan), _ptr(offsets), _ptr(coef),
+                                    int(row0), int(row1), int(n_threads)))
+
+
+def scan_frame(scan: mjd_scan) -> dict:
+    f = scan.frame
+    return {"width": f.width, "height": f.height, "h": tuple(f.h), "v": tuple(f.v), "qsel": tuple(f.qsel)}

@@ -15,6 +15,8 @@ LIB = os.path.join(LIBDIR, "libmjd.so")
 BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["api.hip", "decode.hip", "batch.hip", "copy.hip"]
+# host-only C++ (no device code): built with the host compiler
+HOST_SOURCES = ["host_jpeg.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -26,6 +28,17 @@ HIPCC_FLAGS = [
     "-Wall", "-Wno-unused-function",
     "-I" + os.path.join(ROOT, "include"),
 ]
+
+
+CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", "-Wno-unused-parameter",
+             "-I" + os.path.join(ROOT, "include"), "-I" + "/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
+
+
+def cxx() -> str:
+    for cand in (os.environ.get("CXX"), shutil.which("g++"), shutil.which("c++")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("no host C++ compiler found")
 
 
 def hipcc() -> str:
@@ -52,12 +65,16 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         cmds.append([cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+    for src in HOST_SOURCES:
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".host.o")
+        objs.append(obj)
+        cmds.append([cxx(), *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
     with ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
         for r in ex.map(_run, cmds):
             if verbose and (r.stdout or r.stderr):
                 print(r.stdout, r.stderr, file=sys.stderr)
     tmp = LIB + ".tmp"
-    _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)
     return LIB
 

@@ -6,6 +6,7 @@
 #include <string>
 
 #include "mjd.h"
+#include "mjd_common.h"
 #include "segment.h"
 
 struct mjd_ctx {
@@ -17,12 +18,6 @@ struct mjd_ctx {
 };
 
 namespace mjd {
-
-// Records a thread-local message and returns `code`.
-int fail(int code, const char* fmt, ...);
-
-// Host-only frame validation + geometry (no HIP calls).
-int frame_geometry(const mjd_frame* f, mjd_geometry* g);
 
 // Enqueues the segment kernel for MCU rows [row0, row1) of one image.
 hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf, bool fancy, int cu_count,
