@@ -39,7 +39,244 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-image latency loop")
     ap.add_argument("--tune", action="store_true", help="autotune the launch shape before timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the mixed 256-image batch measurement")
+    ap.add_argument("--batch-images", type=int, default=256)
+    ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--no-pipeline", action="store_true", help="skip the end-to-end bitstream corpus measurement")
+    ap.add_argument("--corpus-images", type=int, default=1000)
+    ap.add_argument("--pipeline-threads", type=int, default=15, help="entropy worker threads (plus the caller)")
     return ap.parse_args()
+
+
+PROFILE = os.path.join(ROOT, "profiles", "decode_segments_420_fancy_4096x3072.md")
+KERNEL_SOURCES = ("segment.h", "decode_kernel.h", "decode.hip")
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    if not os.path.exists(PROFILE):
+        return None
+    text = open(PROFILE).read()
+    m_hash = re.search(r"kernel_sources_sha256: ([0-9a-f]{64})", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch: (\d+)", text)
+    if not m_hash or not m_bytes:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1311_5304_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return int(m_bytes.group(1)) if h.hexdigest() == m_hash.group(1) else None
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _events_ms(torch, stream, fn, reps):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batch_workload(args, M, ctx, dev, stream):
+    """Mixed batch: N images, W and H uniform in 320..4096 (never multiples
+    of 16), thirds of 4:4:4 / 4:2:2 / 4:2:0, quality 50..95 with per-image
+    tables, gradient content with sigma 8 noise, generated on the GPU.
+
+    Reports the batched persistent launch (hipGraph replay and direct) against
+    per-image launches (back-to-back on one stream, and synchronised after each
+    image), all on the same resident buffers, plus the autotuner's table and a
+    sampled bit-exactness check against the oracle."""
+    import torch
+
+    from paper_1311_5304_amd import autotune
+    from synth import gpu_encode, workloads
+
+    log(f"generating the {args.batch_images}-image batch on the GPU")
+    t0 = time.time()
+    specs = workloads.batch_specs(n=args.batch_images)
+    imgs = []
+    for spec in specs:
+        frame, coef, qt = gpu_encode.batch_image_gpu(torch, spec, dev)
+        qd = torch.from_numpy(qt.view(np.int16)).to(dev)
+        out = torch.empty((frame["height"], frame["width"], 3), dtype=torch.uint8, device=dev)
+        imgs.append((frame, coef, qd, out, 3 * frame["width"], qt))
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    jobs = [im[:5] for im in imgs]
+    px = sum(f["width"] * f["height"] for f, *_ in imgs)
+    nbytes = sum(c.numel() * 2 + o.numel() for _, c, _, o, _, _ in imgs)
+    res = {"images": len(imgs), "megapixels": round(px / 1e6, 1), "algorithmic_bytes": nbytes,
+           "generation_s": round(gen_s, 1)}
+
+    def rate(ms):
+        return {"ms": round(ms, 3), "MPix_s": round(px / (ms * 1e-3) / 1e6, 1),
+                "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    log("autotuning the batch")
+    best, table = autotune.tune_batch(ctx, jobs, M.MJD_UPSAMPLE_FANCY, reps=3)
+    log("timing batched and per-image launches")
+    res["autotune"] = {"best": best, "table": table}
+    saved = M.mjd_ctx_get_tuning(ctx)
+    M.mjd_ctx_set_tuning(ctx, best["seg_subtiles"], best["max_workgroups"])
+    batch = M.Batch(ctx, jobs, M.MJD_UPSAMPLE_FANCY)
+    M.mjd_ctx_set_tuning(ctx, saved["seg_subtiles"], saved["max_workgroups"])
+    res["plan"] = batch.info()
+    batch.launch(use_graph=True)
+    torch.cuda.synchronize()
+    res["fancy_batched_graph"] = rate(_events_ms(torch, stream, lambda: batch.launch(use_graph=True),
+                                                 args.batch_reps))
+    res["fancy_batched_direct"] = rate(_events_ms(torch, stream, lambda: batch.launch(use_graph=False),
+                                                  args.batch_reps))
+
+    def per_image():
+        for frame, c, q, o, pitch, _ in imgs:
+            M.mjd_decode(ctx, frame, c, q, M.MJD_UPSAMPLE_FANCY, o, pitch, 0,
+                         M.mjd_geometry_of(frame)["mcus_y"], stream)
+    per_image()
+    torch.cuda.synchronize()
+    res["fancy_per_image_back_to_back"] = rate(_events_ms(torch, stream, per_image, max(1, args.batch_reps // 2)))
+    t = time.perf_counter()
+    for frame, c, q, o, pitch, _ in imgs:
+        M.mjd_decode(ctx, frame, c, q, M.MJD_UPSAMPLE_FANCY, o, pitch, 0, M.mjd_geometry_of(frame)["mcus_y"],
+                     stream)
+        torch.cuda.synchronize()
+    res["fancy_per_image_synced"] = rate((time.perf_counter() - t) * 1e3)
+    res["speedup_batched_vs_per_image_synced"] = round(
+        res["fancy_per_image_synced"]["ms"] / res["fancy_batched_graph"]["ms"], 2)
+
+    # bit-exactness on samples: the last launch wrote every output (per image);
+    # replay the batch so the checked bytes are the batched kernel's
+    for *_, o, _, _ in imgs:
+        o.fill_(0)
+    batch.launch(use_graph=True)
+    torch.cuda.synchronize()
+    log("oracle check of batch samples")
+    res["bit_exact_samples"] = batch_samples_match(imgs, "fancy")
+
+    simple = M.Batch(ctx, jobs, M.MJD_UPSAMPLE_SIMPLE)
+    simple.launch(use_graph=True)
+    torch.cuda.synchronize()
+    res["simple_batched_graph"] = rate(_events_ms(torch, stream, lambda: simple.launch(use_graph=True),
+                                                  args.batch_reps))
+    simple.close()
+    batch.close()
+    return res
+
+
+def pipeline_workload(args, M, ctx, dev):
+    """End-to-end decode of a corpus of baseline JPEG bitstreams (our encoder;
+    1..24 MP, 4:3 / 3:2 / 16:9 either way up, 4:2:0, quality 85, a restart
+    marker every 32 MCUs, texture content): host worker threads Huffman-decode
+    restart intervals of MCU-row bands into pinned buffers, pipelined with
+    host->device copies, the fused kernel and device->host copies of RGB8 on
+    three streams.  The entropy-only run (same threads, nothing sent to the
+    GPU) is the entropy-bound limit."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    import oracle
+    from synth import fast_bitstream, gpu_encode, workloads
+
+    log(f"generating the {args.corpus_images}-bitstream corpus")
+    t0 = time.time()
+    specs = workloads.corpus_specs(n=args.corpus_images)
+    jpgs = [None] * len(specs)
+    sample = None
+    smallest = min(range(len(specs)), key=lambda i: specs[i][0] * specs[i][1])
+
+    def encode_one(i, frame, coef, qt):
+        jpgs[i] = fast_bitstream.write_jpeg(frame, coef, qt, restart_interval=32)
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        futs = []
+        for i, spec in enumerate(specs):
+            frame, c, qt = gpu_encode.batch_image_gpu(torch, spec, dev, sigma=12.0, content="texture")
+            coef = c.cpu().numpy()
+            if i == smallest:
+                sample = (frame, coef, qt)
+            futs.append(ex.submit(encode_one, i, frame, coef, qt))
+            if len(futs) > 32:
+                futs.pop(0).result()
+        for f in futs:
+            f.result()
+    gen_s = time.time() - t0
+    px = sum(w * h for w, h, *_ in specs)
+    nbytes = sum(len(j) for j in jpgs)
+    frames = [workloads.make_frame(w, h, s) for w, h, s, _, _ in specs]
+    max_blocks = max(oracle.geometry(f)["n_blocks"] for f in frames)
+    max_px = max(w * h for w, h, *_ in specs)
+    ring = [torch.empty(max_px * 3, dtype=torch.uint8).pin_memory() for _ in range(4)]
+    outs = [ring[i % len(ring)] for i in range(len(jpgs))]
+    pitches = [3 * w for w, *_ in specs]
+    pipe = M.Pipeline(ctx, args.pipeline_threads, max_blocks, max_px, M.MJD_UPSAMPLE_FANCY, n_slots=3)
+    try:
+        log("pipeline: entropy-only run")
+        ent = pipe.run(jpgs, outs, pitches, entropy_only=True)
+        log("pipeline: end-to-end run")
+        full = pipe.run(jpgs, outs, pitches)
+        # bit-exactness: the smallest image through the pipeline against the
+        # oracle's back half on the coefficients it was encoded from
+        frame, coef, qt = sample
+        o = torch.empty(frame["width"] * frame["height"] * 3, dtype=torch.uint8).pin_memory()
+        pipe.run([jpgs[smallest]], [o], [3 * frame["width"]])
+        exact = bool(np.array_equal(o.numpy().reshape(frame["height"], frame["width"], 3),
+                                    oracle.decode(frame, coef.reshape(-1, 64), qt, "fancy")))
+    finally:
+        pipe.close()
+    gpu_ms = full["h2d_ms"] + full["kernel_ms"] + full["d2h_ms"]
+    return {
+        "images": len(jpgs), "megapixels": round(px / 1e6, 1), "bitstream_MB": round(nbytes / 1e6, 1),
+        "bits_per_pixel": round(8 * nbytes / px, 3), "generation_s": round(gen_s, 1),
+        "threads": args.pipeline_threads + 1, "slots": 3,
+        "MPix_s": round(px / (full["wall_ms"] * 1e-3) / 1e6, 1),
+        "wall_ms": round(full["wall_ms"], 1),
+        "entropy_only_wall_ms": round(ent["wall_ms"], 1),
+        "entropy_only_MPix_s": round(px / (ent["wall_ms"] * 1e-3) / 1e6, 1),
+        "fraction_of_entropy_bound": round(ent["wall_ms"] / full["wall_ms"], 4),
+        "stage_overlap": round(1 - (full["wall_ms"] - ent["wall_ms"]) / gpu_ms, 4) if gpu_ms > 0 else None,
+        "h2d_ms": round(full["h2d_ms"], 1), "kernel_ms": round(full["kernel_ms"], 1),
+        "d2h_ms": round(full["d2h_ms"], 1), "worker_entropy_ms": round(full["entropy_ms"], 1),
+        "parse_ms": round(full["parse_ms"], 1), "bands": full["bands"],
+        "bit_exact_sample": {"image": smallest, "size": [frame["width"], frame["height"]], "equal": exact},
+    }
+
+
+def batch_samples_match(imgs, mode):
+    """Oracle check of the batched outputs: the three smallest images whole,
+    and one interior MCU row of the three largest (decoded by the oracle from
+    that row and its neighbours, which is all the row depends on)."""
+    import oracle
+    order = sorted(range(len(imgs)), key=lambda i: imgs[i][0]["width"] * imgs[i][0]["height"])
+    ok = True
+    checked = []
+    for i in order[:3]:
+        frame, c, _, o, _, qt = imgs[i]
+        ref = oracle.decode(frame, c.cpu().numpy().reshape(-1, 64), qt, mode)
+        ok &= bool(np.array_equal(o.cpu().numpy(), ref))
+        checked.append(f"image {i} whole")
+    for i in order[-3:]:
+        frame, c, _, o, _, qt = imgs[i]
+        g = oracle.geometry(frame)
+        mh = g["mcu_h"]
+        r = g["mcus_y"] // 2
+        per_row = c.numel() // g["mcus_y"]
+        band = c[(r - 1) * per_row:(r + 2) * per_row].cpu().numpy().reshape(-1, 64)
+        sub = dict(frame, height=3 * mh)
+        ref = oracle.decode(sub, band, qt, mode)[mh:2 * mh]
+        ok &= bool(np.array_equal(o[r * mh:(r + 1) * mh].cpu().numpy(), ref))
+        checked.append(f"image {i} MCU row {r}")
+    return {"all_equal": ok, "checked": checked}
 
 
 def main():
@@ -57,6 +294,7 @@ def main():
     torch.cuda.set_device(dev)
     ctx = M.Context(0)
 
+    log("generating the 4096x3072 workload")
     t0 = time.time()
     frame, coef, qt = workloads.large_420_fancy()
     gen_s = time.time() - t0
@@ -83,6 +321,7 @@ def main():
         M.mjd_decode(ctx, frame, c_sets[k], q_dev, M.MJD_UPSAMPLE_FANCY, o_sets[k], 3 * W, 0, g["mcus_y"],
                      stream)
 
+    log("timing the headline decode")
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -106,6 +345,7 @@ def main():
         extras["autotune"] = tuned
     cpu = None
     if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
         import oracle
         reps = 0
         t_cpu = 0.0
@@ -120,24 +360,23 @@ def main():
         gpu_out = o_sets[(args.steps - 1) % args.sets].cpu().numpy()
         extras["bit_exact_vs_oracle"] = bool(np.array_equal(gpu_out, ref))
 
-    if True:
-        # copy-kernel bandwidth over the same byte count (read coef-size, write coef-size)
-        n = (algo_bytes // 2) // 16 * 16
-        src = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(args.sets)]
-        dst = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(args.sets)]
-        for i in range(10):
-            M.mjd_copy(ctx, dst[i % args.sets], src[i % args.sets], n, stream)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for i in range(100):
-            M.mjd_copy(ctx, dst[i % args.sets], src[i % args.sets], n, stream)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        copy_ms = e0.elapsed_time(e1) / 100
-        extras["copy_GBps"] = round(2 * n / (copy_ms * 1e-3) / 1e9, 1)
-        extras["copy_bytes_per_launch"] = 2 * n
-        del src, dst
+    # copy-kernel bandwidth over the same byte count (read half, write half)
+    n = (algo_bytes // 2) // 16 * 16
+    src = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(args.sets)]
+    dst = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(args.sets)]
+    for i in range(10):
+        M.mjd_copy(ctx, dst[i % args.sets], src[i % args.sets], n, stream)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(100):
+        M.mjd_copy(ctx, dst[i % args.sets], src[i % args.sets], n, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / 100
+    extras["copy_GBps"] = round(2 * n / (copy_ms * 1e-3) / 1e9, 1)
+    extras["copy_bytes_per_launch"] = 2 * n
+    del src, dst
     if not args.no_latency:
         # small-image latency: 256x256 4:2:0 simple, kernel-only, per call
         f1, c1, q1 = workloads.small_420_simple()
@@ -155,6 +394,14 @@ def main():
         lat = np.array([a.elapsed_time(b) * 1e3 for a, b in evs])
         extras["small_256x256_420_simple_us"] = {"p50": round(float(np.percentile(lat, 50)), 2),
                                                  "p99": round(float(np.percentile(lat, 99)), 2)}
+
+    if not args.no_batch:
+        del c_sets, o_sets
+        torch.cuda.empty_cache()
+        extras["batch"] = batch_workload(args, M, ctx, dev, stream)
+        torch.cuda.empty_cache()
+    if not args.no_pipeline:
+        extras["pipeline"] = pipeline_workload(args, M, ctx, dev)
 
     out = {
         "metric": METRIC,
@@ -174,7 +421,7 @@ def main():
                    "width": W, "height": H, "sampling": "4:2:0", "upsample": "fancy",
                    "rotating_sets": args.sets},
         "roofline": {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": profiled_traffic()},
         "cpu_baseline": cpu,
         "extras": extras,
     }

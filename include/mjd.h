@@ -252,6 +252,72 @@ int mjd_restart_index(const uint8_t* h_jpg, size_t len, const mjd_scan* scan, ui
 int mjd_entropy_decode(const uint8_t* h_jpg, size_t len, const mjd_scan* scan, const uint64_t* h_offsets,
                        int16_t* h_coef, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads);
 
+/* ---------------------------------------------------------------------
+ * Pipelined end-to-end decode: bitstreams in host memory -> RGB8 in host
+ * memory.  The paper's pipelined GPU mode (Sec. 4.5, Fig. 6) cuts an image
+ * into horizontal chunks so that the entropy decoding of chunk i+1 on the
+ * CPU overlaps the transfer and the kernels of chunk i on the GPU.  Here the
+ * chunks are MCU-row bands; host worker threads decode the restart
+ * intervals of each band into pinned buffers, and each finished band goes
+ * host->device on one HIP stream, through the fused kernel on a second and
+ * back device->host on a third, while the workers move on to the next band
+ * and the next images.
+ * ------------------------------------------------------------------- */
+
+typedef struct mjd_pipeline mjd_pipeline;
+
+enum {
+  /* Host entropy decoding only, into the pinned slots; nothing is sent to
+   * the device.  Its wall time is the entropy-bound limit of the pipeline. */
+  MJD_PIPELINE_ENTROPY_ONLY = 1
+};
+
+typedef struct mjd_pipeline_config {
+  uint32_t n_threads;     /* entropy worker threads (>= 1) */
+  uint32_t n_slots;       /* images in flight (>= 2): pinned + device buffers each */
+  uint32_t band_mcu_rows; /* MCU rows per band; 0 = about 8 bands per image */
+  uint32_t upsample;      /* MJD_UPSAMPLE_* */
+  uint64_t max_blocks;    /* coefficient blocks of the largest image a slot holds */
+  uint64_t max_pixels;    /* width * height of the largest image a slot holds */
+} mjd_pipeline_config;
+
+/* Totals of one mjd_pipeline_run.  Stage times are sums over bands of
+ * HIP event intervals (the stages overlap, so they do not add up to the
+ * wall time); entropy_ms sums the worker threads' decoding time. */
+typedef struct mjd_pipeline_stats {
+  double wall_ms;
+  double entropy_ms;
+  double parse_ms;
+  double h2d_ms;
+  double kernel_ms;
+  double d2h_ms;
+  uint64_t images;
+  uint64_t pixels;
+  uint64_t bitstream_bytes;
+  uint64_t bands;
+} mjd_pipeline_stats;
+
+/* Create the worker threads, n_slots pinned host coefficient buffers of
+ * max_blocks * 128 bytes, the matching device coefficient and RGB buffers
+ * (max_pixels * 3 bytes) and three streams on the context's device. */
+int mjd_pipeline_create(mjd_ctx* ctx, const mjd_pipeline_config* cfg, mjd_pipeline** out);
+
+/* Decode n bitstreams end to end, in order: image i is parsed (mjd_parse),
+ * its restart intervals are decoded on the workers, and its RGB8 rows land
+ * at h_rgb[i] + y * pitches[i] (pitch >= 3 * width).  Returns when every
+ * output is in host memory.  h_rgb buffers should be pinned
+ * (hipHostMalloc) for the device->host copies to overlap; outputs may share
+ * a buffer, in which case the last image written wins.  flags:
+ * MJD_PIPELINE_ENTROPY_ONLY or 0.  An image larger than the slots gives
+ * MJD_EBUDGET, a corrupt one MJD_ECORRUPT (naming the image); the run stops
+ * at the first failure after draining the work in flight.  stats may be
+ * NULL.  One run at a time per pipeline. */
+int mjd_pipeline_run(mjd_pipeline* pipe, size_t n, const uint8_t* const* h_jpgs, const size_t* lens,
+                     uint8_t* const* h_rgb, const size_t* pitches, uint32_t flags, mjd_pipeline_stats* stats);
+
+/* Stop the workers and free every buffer, stream and event. */
+void mjd_pipeline_destroy(mjd_pipeline* pipe);
+
 /* Device-to-device streaming copy of `bytes` bytes (a multiple of 16; both
  * pointers 16-byte aligned), enqueued on `stream`.  It is the bandwidth
  * reference for the decoder: a plain read+write stream at the rate this

@@ -4,7 +4,7 @@ chroma upsampling -> YCbCr->RGB as one fused HIP kernel behind a C ABI
 """
 from __future__ import annotations
 
-from ._binding import (MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE, Batch, Context, MjdError,  # noqa: F401
+from ._binding import (MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE, Batch, Context, MjdError, Pipeline,  # noqa: F401
                        mjd_batch_create, mjd_batch_destroy, mjd_batch_launch,
                        mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
                        mjd_decode, mjd_entropy_decode, mjd_geometry_of, mjd_last_error, mjd_parse,

@@ -68,6 +68,20 @@ class mjd_scan(ctypes.Structure):
                 ("dc", mjd_huffman * 4), ("ac", mjd_huffman * 4)]
 
 
+class mjd_pipeline_config(ctypes.Structure):
+    _fields_ = [("n_threads", ctypes.c_uint32), ("n_slots", ctypes.c_uint32), ("band_mcu_rows", ctypes.c_uint32),
+                ("upsample", ctypes.c_uint32), ("max_blocks", ctypes.c_uint64), ("max_pixels", ctypes.c_uint64)]
+
+
+class mjd_pipeline_stats(ctypes.Structure):
+    _fields_ = [("wall_ms", ctypes.c_double), ("entropy_ms", ctypes.c_double), ("parse_ms", ctypes.c_double),
+                ("h2d_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double), ("d2h_ms", ctypes.c_double),
+                ("images", ctypes.c_uint64), ("pixels", ctypes.c_uint64), ("bitstream_bytes", ctypes.c_uint64),
+                ("bands", ctypes.c_uint64)]
+
+
+MJD_PIPELINE_ENTROPY_ONLY = 1
+
 _lib = None
 
 
@@ -105,6 +119,12 @@ def lib() -> ctypes.CDLL:
         L.mjd_restart_index.restype = i32
         L.mjd_entropy_decode.argtypes = [vp, sz, ctypes.POINTER(mjd_scan), vp, vp, u32, u32, i32]
         L.mjd_entropy_decode.restype = i32
+        L.mjd_pipeline_create.argtypes = [vp, ctypes.POINTER(mjd_pipeline_config), ctypes.POINTER(vp)]
+        L.mjd_pipeline_create.restype = i32
+        L.mjd_pipeline_run.argtypes = [vp, sz, vp, vp, vp, vp, u32, ctypes.POINTER(mjd_pipeline_stats)]
+        L.mjd_pipeline_run.restype = i32
+        L.mjd_pipeline_destroy.argtypes = [vp]
+        L.mjd_pipeline_destroy.restype = None
         L.mjd_copy.argtypes = [vp, vp, vp, sz, vp]
         L.mjd_copy.restype = i32
         L.mjd_last_error.argtypes = []
@@ -302,3 +322,44 @@ def mjd_entropy_decode(jpg, scan: mjd_scan, offsets, coef, row0: int, row1: int,
 def scan_frame(scan: mjd_scan) -> dict:
     f = scan.frame
     return {"width": f.width, "height": f.height, "h": tuple(f.h), "v": tuple(f.v), "qsel": tuple(f.qsel)}
+
+
+class Pipeline:
+    """Owns an mjd_pipeline*: host entropy workers + pinned slots + three streams."""
+
+    def __init__(self, ctx: Context, n_threads: int, max_blocks: int, max_pixels: int, upsample: int = 1,
+                 n_slots: int = 3, band_mcu_rows: int = 0):
+        cfg = mjd_pipeline_config(n_threads=int(n_threads), n_slots=int(n_slots),
+                                  band_mcu_rows=int(band_mcu_rows), upsample=int(upsample),
+                                  max_blocks=int(max_blocks), max_pixels=int(max_pixels))
+        p = ctypes.c_void_p()
+        _check(lib().mjd_pipeline_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(p)))
+        self.handle = p
+        self.ctx = ctx
+
+    def run(self, jpgs, outs, pitches=None, entropy_only: bool = False) -> dict:
+        """jpgs: sequence of bytes / uint8 arrays; outs: host buffers (numpy or
+        pinned tensors) of H*pitch bytes each.  Returns the run's statistics."""
+        n = len(jpgs)
+        views = [_bytes_view(j) for j in jpgs]
+        ptrs = (ctypes.c_void_p * n)(*[_ptr(a) for a, _ in views])
+        lens = (ctypes.c_size_t * n)(*[ln for _, ln in views])
+        outp = (ctypes.c_void_p * n)(*[_ptr(o) for o in outs])
+        if pitches is None:
+            pitches = [int(o.shape[1]) * int(o.shape[2]) for o in outs]
+        pit = (ctypes.c_size_t * n)(*[int(x) for x in pitches])
+        st = mjd_pipeline_stats()
+        flags = MJD_PIPELINE_ENTROPY_ONLY if entropy_only else 0
+        _check(lib().mjd_pipeline_run(self.handle, n, ptrs, lens, outp, pit, flags, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in mjd_pipeline_stats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().mjd_pipeline_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -63,6 +63,35 @@ def tune(ctx, frame, coef_sets, qt, mode: int, out_sets, reps: int = 20,
     return best, table
 
 
+BATCH_SEG_CANDIDATES = (0, 1, 2, 3, 4, 6, 8, 12)
+
+
+def tune_batch(ctx, jobs, mode: int, reps: int = 5, seg_candidates=BATCH_SEG_CANDIDATES,
+               wg_candidates=WG_CANDIDATES, use_graph: bool = True):
+    """Plan the batch once per (seg_subtiles, max_workgroups) candidate and
+    time its persistent launch.  seg_subtiles 0 is the planner's own choice
+    (about four segments per resident workgroup).  Returns (best, table);
+    the planned Batch objects are released."""
+    saved = B.mjd_ctx_get_tuning(ctx)
+    table = []
+    try:
+        for seg in seg_candidates:
+            for wgs in wg_candidates:
+                B.mjd_ctx_set_tuning(ctx, seg, wgs)
+                b = B.Batch(ctx, jobs, mode)
+                try:
+                    info = b.info()
+                    ms = _time_ms(lambda: b.launch(use_graph=use_graph), reps, warmup=2)
+                finally:
+                    b.close()
+                table.append({"seg_subtiles": seg, "max_workgroups": wgs, "segments": info["segments"],
+                              "workgroups": info["workgroups"], "ms": ms})
+    finally:
+        B.mjd_ctx_set_tuning(ctx, saved["seg_subtiles"], saved["max_workgroups"])
+    best = min(table, key=lambda r: r["ms"])
+    return best, table
+
+
 def size_class(frame) -> str:
     """Power-of-two bucket of the pixel count, with the sampling."""
     px = int(frame["width"]) * int(frame["height"])

@@ -49,6 +49,8 @@ int frame_geometry(const mjd_frame* f, mjd_geometry* g) {
   return MJD_OK;
 }
 
+int ctx_device(const mjd_ctx* ctx) { return ctx->device; }
+
 int job_view(const mjd_job* j, int upsample, ImageView* im, mjd_geometry* g) {
   if (!j) return fail(MJD_EINVAL, "null job");
   int rc = frame_geometry(&j->frame, g);

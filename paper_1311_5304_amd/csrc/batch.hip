@@ -31,13 +31,6 @@ constexpr int kBatchLds =
 
 enum BatchClass : int { kC420F = 0, kC420S = 1, kC422F = 2, kC422S = 3, kC444 = 4 };
 
-struct BatchItem {
-  int img;
-  int cls;
-  int mx0, r0, r1;
-  int pad[3];
-};
-
 __global__ __launch_bounds__(kBatchThreads, 2) void decode_batch(const ImageView* __restrict__ views,
                                                               const BatchItem* __restrict__ items, int n_items,
                                                               unsigned* counters) {
@@ -121,9 +114,6 @@ struct mjd_batch {
 
 namespace mjd {
 
-// Validates one job and fills its view (shared with the single-image entry).
-int job_view(const mjd_job* j, int upsample, ImageView* im, mjd_geometry* g);
-
 static int batch_slots(mjd_ctx* ctx) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_batch, kBatchThreads, 0) != hipSuccess ||
@@ -132,15 +122,19 @@ static int batch_slots(mjd_ctx* ctx) {
   return per_cu * (ctx->cu_count > 0 ? ctx->cu_count : 256);
 }
 
-int batch_build(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, mjd_batch* b) {
+int batch_plan(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, BatchPlan* plan) {
   if (n == 0) return fail(MJD_EINVAL, "empty batch");
   if (n > (1u << 24)) return fail(MJD_EINVAL, "batch of %zu images too large", n);
-  std::vector<ImageView> views(n);
+  if (upsample != MJD_UPSAMPLE_SIMPLE && upsample != MJD_UPSAMPLE_FANCY)
+    return fail(MJD_EINVAL, "upsample mode %d unknown", upsample);
+  plan->views.resize(n);
+  plan->items.clear();
+  plan->pixels = 0;
   std::vector<int> cls(n);
   std::vector<mjd_geometry> geo(n);
   uint64_t subtiles = 0;
   for (size_t i = 0; i < n; ++i) {
-    int rc = job_view(&jobs[i], upsample, &views[i], &geo[i]);
+    int rc = job_view(&jobs[i], upsample, &plan->views[i], &geo[i]);
     if (rc != MJD_OK) {
       const std::string why = mjd_last_error();
       return fail(rc, "job %zu: %s", i, why.c_str());
@@ -151,7 +145,7 @@ int batch_build(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, mjd_b
     int sx, sy;
     class_shape(cls[i], &sx, &sy);
     subtiles += static_cast<uint64_t>((geo[i].mcus_x + sx - 1) / sx) * ((geo[i].mcus_y + sy - 1) / sy);
-    b->pixels += static_cast<uint64_t>(jobs[i].frame.width) * jobs[i].frame.height;
+    plan->pixels += static_cast<uint64_t>(jobs[i].frame.width) * jobs[i].frame.height;
   }
   const int slots = batch_slots(ctx);
   // Segment length: about 4 segments per resident workgroup over the whole
@@ -161,7 +155,6 @@ int batch_build(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, mjd_b
     const uint64_t want = static_cast<uint64_t>(slots) * 4;
     seg_sub = static_cast<int>(std::max<uint64_t>(1, (subtiles + want - 1) / want));
   }
-  std::vector<BatchItem> items;
   for (size_t i = 0; i < n; ++i) {
     int sx, sy;
     class_shape(cls[i], &sx, &sy);
@@ -176,24 +169,42 @@ int batch_build(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, mjd_b
         it.mx0 = s * sx;
         it.r0 = r0;
         it.r1 = std::min(rows, r0 + seg_rows);
-        items.push_back(it);
+        plan->items.push_back(it);
       }
   }
   // longest segments first: the queue then fills the tail with short ones
-  std::stable_sort(items.begin(), items.end(), [](const BatchItem& a, const BatchItem& c) {
+  std::stable_sort(plan->items.begin(), plan->items.end(), [](const BatchItem& a, const BatchItem& c) {
     return (a.r1 - a.r0) > (c.r1 - c.r0);
   });
-  if (items.size() > 0x7FFFFFF0u) return fail(MJD_EINVAL, "batch needs too many segments");
-  b->n_items = static_cast<int>(items.size());
-  int grid = std::min(b->n_items, slots);
+  if (plan->items.size() > 0x7FFFFFF0u) return fail(MJD_EINVAL, "batch needs too many segments");
+  int grid = std::min(static_cast<int>(plan->items.size()), slots);
   if (ctx->tuning.max_workgroups > 0) grid = std::min(grid, static_cast<int>(ctx->tuning.max_workgroups));
-  b->grid = grid;
-  if (hipMalloc(&b->d_views, views.size() * sizeof(ImageView)) != hipSuccess ||
-      hipMalloc(&b->d_items, items.size() * sizeof(BatchItem)) != hipSuccess ||
+  plan->grid = grid;
+  return MJD_OK;
+}
+
+hipError_t batch_enqueue(const ImageView* d_views, const BatchItem* d_items, int n_items, unsigned* d_counters,
+                         int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(decode_batch, dim3(grid), dim3(kBatchThreads), 0, stream, d_views, d_items, n_items,
+                     d_counters);
+  return hipGetLastError();
+}
+
+int batch_build(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, mjd_batch* b) {
+  BatchPlan plan;
+  int rc = batch_plan(ctx, jobs, n, upsample, &plan);
+  if (rc != MJD_OK) return rc;
+  b->pixels = plan.pixels;
+  b->n_items = static_cast<int>(plan.items.size());
+  b->grid = plan.grid;
+  if (hipMalloc(&b->d_views, plan.views.size() * sizeof(ImageView)) != hipSuccess ||
+      hipMalloc(&b->d_items, plan.items.size() * sizeof(BatchItem)) != hipSuccess ||
       hipMalloc(&b->d_counters, 2 * sizeof(unsigned)) != hipSuccess)
     return fail(MJD_ENOMEM, "device allocation for the batch tables failed");
-  if (hipMemcpy(b->d_views, views.data(), views.size() * sizeof(ImageView), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) != hipSuccess ||
+  if (hipMemcpy(b->d_views, plan.views.data(), plan.views.size() * sizeof(ImageView), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(b->d_items, plan.items.data(), plan.items.size() * sizeof(BatchItem), hipMemcpyHostToDevice) !=
+          hipSuccess ||
       hipMemset(b->d_counters, 0, 2 * sizeof(unsigned)) != hipSuccess)
     return fail(MJD_EDEVICE, "uploading the batch tables failed");
   return MJD_OK;
@@ -213,11 +224,7 @@ void batch_free(mjd_batch* b) {
 }
 
 hipError_t batch_launch(mjd_batch* b, bool use_graph, hipStream_t stream) {
-  if (!use_graph) {
-    hipLaunchKernelGGL(decode_batch, dim3(b->grid), dim3(kBatchThreads), 0, stream, b->d_views, b->d_items,
-                       b->n_items, b->d_counters);
-    return hipGetLastError();
-  }
+  if (!use_graph) return batch_enqueue(b->d_views, b->d_items, b->n_items, b->d_counters, b->grid, stream);
   if (!b->exec) {
     hipError_t e = hipGraphCreate(&b->graph, 0);
     if (e != hipSuccess) return e;
@@ -243,10 +250,9 @@ hipError_t batch_launch(mjd_batch* b, bool use_graph, hipStream_t stream) {
 extern "C" {
 
 int mjd_batch_create(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, mjd_batch** out) {
-  if (!ctx || !jobs || !out) return mjd::fail(MJD_EINVAL, "null context, jobs or out-pointer");
+  if (!ctx || !out) return mjd::fail(MJD_EINVAL, "null context or out-pointer");
   *out = nullptr;
-  if (upsample != MJD_UPSAMPLE_SIMPLE && upsample != MJD_UPSAMPLE_FANCY)
-    return mjd::fail(MJD_EINVAL, "upsample mode %d unknown", upsample);
+  if (!jobs && n) return mjd::fail(MJD_EINVAL, "null jobs");
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)

@@ -12,4 +12,7 @@ int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 // Host-only frame validation + geometry (no HIP calls).
 int frame_geometry(const mjd_frame* f, mjd_geometry* g);
 
+// HIP device of a context.
+int ctx_device(const mjd_ctx* ctx);
+
 }  // namespace mjd

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "mjd.h"
 #include "mjd_common.h"
@@ -24,5 +25,32 @@ hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf,
                         const mjd_tuning& tuning, hipStream_t stream);
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+// Validates one job and fills its view (shared by the single-image and batch entries).
+int job_view(const mjd_job* j, int upsample, ImageView* im, mjd_geometry* g);
+
+// One queue entry of the batched kernel: a segment of one image.
+struct BatchItem {
+  int img;
+  int cls;
+  int mx0, r0, r1;
+  int pad[3];
+};
+
+// Host plan of a batch: per-image views and the segment queue (longest
+// first), with the workgroup count of its launch.
+struct BatchPlan {
+  std::vector<ImageView> views;
+  std::vector<BatchItem> items;
+  uint64_t pixels = 0;
+  int grid = 0;
+};
+
+int batch_plan(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, BatchPlan* plan);
+
+// Enqueues the persistent batch kernel over tables already on the device.
+// d_counters (2 words) must be zero; the kernel leaves them zero.
+hipError_t batch_enqueue(const ImageView* d_views, const BatchItem* d_items, int n_items, unsigned* d_counters,
+                         int grid, hipStream_t stream);
 
 }  // namespace mjd

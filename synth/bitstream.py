@@ -139,6 +139,47 @@ def _segment(marker: int, payload: bytes) -> bytes:
     return struct.pack(">HH", 0xFF00 | marker, len(payload) + 2) + payload
 
 
+LUMA_CHROMA_TABLES = (0, 1, 1)  # Huffman table set per component: luma 0, chroma 1
+
+
+def build_tables(dc_counts, ac_counts):
+    """Per-table symbol counts -> ([(class, id, BITS, HUFFVAL)], {(class, id): {symbol: (code, length)}})."""
+    tables = []
+    codes = {}
+    for t in range(2):
+        for cls, counts in ((0, dc_counts[t]), (1, ac_counts[t])):
+            bits, vals = _code_lengths(counts)
+            tables.append((cls, t, bits, vals))
+            codes[(cls, t)] = _canonical(bits, vals)
+    return tables, codes
+
+
+def headers(frame: dict, qt: np.ndarray, tables, restart_interval: int) -> bytearray:
+    """SOI, DQT, SOF0, DHT, optional DRI and SOS: everything before the entropy-coded data."""
+    hs, vs, qsel = frame["h"], frame["v"], frame["qsel"]
+    tbl = LUMA_CHROMA_TABLES
+    out = bytearray(b"\xFF\xD8")
+    for slot in sorted(set(qsel)):
+        zz = np.asarray(qt[slot], dtype=np.int64)[_ZZ]
+        if zz.max() > 255 or zz.min() < 1:
+            raise ValueError("baseline quant tables need entries in 1..255")
+        out += _segment(0xDB, bytes([slot]) + bytes(int(v) for v in zz))
+    sof = struct.pack(">BHHB", 8, frame["height"], frame["width"], 3)
+    for c in range(3):
+        sof += bytes([c + 1, (hs[c] << 4) | vs[c], qsel[c]])
+    out += _segment(0xC0, sof)
+    for cls, t, bits, vals in tables:
+        out += _segment(0xC4, bytes([(cls << 4) | t]) + bytes(bits) + bytes(vals))
+    if restart_interval:
+        out += _segment(0xDD, struct.pack(">H", restart_interval))
+    sos = bytes([3])
+    for c in range(3):
+        sos += bytes([c + 1, (tbl[c] << 4) | tbl[c]])
+    sos += bytes([0, 63, 0])
+    out += _segment(0xDA, sos)
+    return out
+
+
 def write_jpeg(frame: dict, coef: np.ndarray, qt: np.ndarray, restart_interval: int = 0) -> bytes:
     hs, vs, qsel = frame["h"], frame["v"], frame["qsel"]
     hmax, vmax = max(hs), max(vs)
@@ -148,7 +189,7 @@ def write_jpeg(frame: dict, coef: np.ndarray, qt: np.ndarray, restart_interval: 
     n_mcu = mx * my
     coef = np.asarray(coef, dtype=np.int16).reshape(n_mcu, bpm, 64)
     comp_of = [c for c in range(3) for _ in range(hs[c] * vs[c])]
-    tbl = [0, 1, 1]  # luma uses Huffman tables 0, chroma tables 1
+    tbl = LUMA_CHROMA_TABLES
 
     # pass 1: tokens and symbol statistics
     tokens = []
@@ -169,34 +210,8 @@ def write_jpeg(frame: dict, coef: np.ndarray, qt: np.ndarray, restart_interval: 
             mt.append((t, dc_tok, ac_toks))
         tokens.append(mt)
 
-    tables = []
-    codes = {}
-    for t in range(2):
-        for cls, counts in ((0, dc_counts[t]), (1, ac_counts[t])):
-            bits, vals = _code_lengths(counts)
-            tables.append((cls, t, bits, vals))
-            codes[(cls, t)] = _canonical(bits, vals)
-
-    out = bytearray(b"\xFF\xD8")
-    for slot in sorted(set(qsel)):
-        zz = np.asarray(qt[slot], dtype=np.int64)[_ZZ]
-        if zz.max() > 255 or zz.min() < 1:
-            raise ValueError("baseline quant tables need entries in 1..255")
-        out += _segment(0xDB, bytes([slot]) + bytes(int(v) for v in zz))
-    sof = struct.pack(">BHHB", 8, frame["height"], frame["width"], 3)
-    for c in range(3):
-        sof += bytes([c + 1, (hs[c] << 4) | vs[c], qsel[c]])
-    out += _segment(0xC0, sof)
-    for cls, t, bits, vals in tables:
-        out += _segment(0xC4, bytes([(cls << 4) | t]) + bytes(bits) + bytes(vals))
-    if restart_interval:
-        out += _segment(0xDD, struct.pack(">H", restart_interval))
-    sos = bytes([3])
-    for c in range(3):
-        sos += bytes([c + 1, (tbl[c] << 4) | tbl[c]])
-    sos += bytes([0, 63, 0])
-    out += _segment(0xDA, sos)
-
+    tables, codes = build_tables(dc_counts, ac_counts)
+    out = headers(frame, qt, tables, restart_interval)
     w = _BitWriter()
     for m, mt in enumerate(tokens):
         if restart_interval and m and m % restart_interval == 0:

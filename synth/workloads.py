@@ -54,6 +54,24 @@ def batch_specs(n: int = 256, lo: int = 320, hi: int = 4096, workload_id: int = 
     return specs
 
 
+def corpus_specs(n: int = 1000, mp_lo: float = 1.0, mp_hi: float = 24.0, workload_id: int = 4):
+    """Per-image (width, height, sampling, quality, seed) of the bitstream corpus.
+
+    Megapixels uniform in [mp_lo, mp_hi]; aspect ratio 4:3, 3:2 or 16:9 with
+    a random orientation; 4:2:0; quality 85."""
+    rng = np.random.default_rng(seed_of(workload_id, 0xFFFFF))
+    specs = []
+    for i in range(n):
+        mp = float(rng.uniform(mp_lo, mp_hi))
+        a = (4 / 3, 3 / 2, 16 / 9)[int(rng.integers(0, 3))]
+        w = int(round((mp * 1e6 * a) ** 0.5))
+        h = max(1, int(round(mp * 1e6 / w)))
+        if rng.integers(0, 2):
+            w, h = h, w
+        specs.append((w, h, "420", 85, seed_of(workload_id, i)))
+    return specs
+
+
 def batch_image(spec, sigma: float = 8.0):
     w, h, sampling, q, seed = spec
     rgb = gradient_rgb(w, h, seed, sigma=sigma)
@@ -82,5 +100,5 @@ def random_coefficients(frame: dict, seed: int, scale: float = 60.0, density: fl
     return np.clip(c, -1023, 1023).astype(np.int16)
 
 
-__all__ = ["seed_of", "small_420_simple", "large_420_fancy", "batch_specs", "batch_image",
+__all__ = ["seed_of", "small_420_simple", "large_420_fancy", "batch_specs", "corpus_specs", "batch_image",
            "random_coefficients", "make_frame", "mcu_grid"]

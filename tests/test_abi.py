@@ -71,6 +71,38 @@ def test_tuning_rejects_null_context():
     assert B.lib().mjd_ctx_get_tuning(None, ctypes.byref(t)) == B.MJD_EINVAL
 
 
+STRUCTS = [B.mjd_frame, B.mjd_geometry, B.mjd_tuning, B.mjd_job, B.mjd_huffman, B.mjd_scan,
+           B.mjd_pipeline_config, B.mjd_pipeline_stats]
+
+
 def test_frame_struct_layout():
     assert ctypes.sizeof(B.mjd_frame) == 20
     assert ctypes.sizeof(B.mjd_geometry) == 56
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """sizeof/offsetof of every struct of include/mjd.h, as a C compiler
+    lays them out, equal the ctypes declarations of the binding."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mjd.h"', "int main(void) {"]
+    for st in STRUCTS:
+        name = st.__name__
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for field, _ in st._fields_:
+            lines.append(f'printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                                check=True).stdout.split("\n") if line)
+    for st in STRUCTS:
+        name = st.__name__
+        assert int(out[name]) == ctypes.sizeof(st), name
+        for field, _ in st._fields_:
+            assert int(out[f"{name}.{field}"]) == getattr(st, field).offset, (name, field)
