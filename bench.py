@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-pipeline", action="store_true", help="skip the end-to-end bitstream corpus measurement")
     ap.add_argument("--corpus-images", type=int, default=1000)
     ap.add_argument("--pipeline-threads", type=int, default=15, help="entropy worker threads (plus the caller)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--serve-requests", type=int, default=2200, help="requests per trace (the first 200 warm up)")
     return ap.parse_args()
 
 
@@ -252,6 +254,71 @@ def pipeline_workload(args, M, ctx, dev):
     }
 
 
+def serve_workload(args, M, ctx, dev):
+    """Serving loop: Poisson arrivals of requests log-uniform in 0.1..24 MP
+    (mixed samplings, quality 50..95, gradient content), coefficients and
+    RGB8 in pinned host memory, a 16 GiB device budget, continuous batching
+    against the synchronous one-at-a-time server on the same trace.  The
+    arrival rate is 0.7x (and 0.9x) of the batched capacity measured on a
+    saturating trace."""
+    import torch
+
+    import oracle
+    from synth import gpu_encode, workloads
+
+    log("serving: generating the request pool")
+    specs = workloads.serving_pool()
+    pool = []
+    for spec in specs:
+        frame, c, qt = gpu_encode.batch_image_gpu(torch, spec, dev, sigma=8.0)
+        coef = c.cpu().pin_memory()
+        q = torch.from_numpy(qt.view(np.int16).reshape(-1).copy()).pin_memory()
+        out = torch.empty((frame["height"], frame["width"], 3), dtype=torch.uint8).pin_memory()
+        pool.append((frame, coef, q, out, qt))
+    px_of = [f["width"] * f["height"] for f, *_ in pool]
+    budget = 16 << 30
+    warm = 200
+    n = max(args.serve_requests, warm + 100)
+
+    def run(mode, rate):
+        trace = workloads.serving_trace(n, len(pool), rate if rate else 1.0)
+        srv = M.Server(ctx, budget, M.MJD_UPSAMPLE_FANCY, mode=mode, max_batch=256, max_inflight=2)
+        try:
+            t0 = srv.now_ns() + 2_000_000
+            ids = []
+            for (at, k) in trace:
+                f, c, q, o, _ = pool[k]
+                ids.append(srv.submit(f, c, q, o, 3 * f["width"], t0 + (at if rate else 0)))
+            times = [srv.wait(i) for i in ids]
+        finally:
+            srv.close()
+        meas = times[warm:]
+        px = sum(px_of[k] for _, k in trace[warm:])
+        span = (max(t["done_ns"] for t in meas) - min(t["arrival_ns"] for t in meas)) * 1e-9
+        lat = np.array([(t["done_ns"] - t["arrival_ns"]) * 1e-6 for t in meas])
+        return {"MPix_s": round(px / span / 1e6, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_batch": round(float(np.mean([t["batch"] for t in meas])), 2)}
+
+    log("serving: saturating trace (capacity)")
+    cap = run(M.MJD_SERVE_CONTINUOUS, 0)
+    mean_px = float(np.mean(px_of))
+    res = {"pool_images": len(pool), "requests": n, "warmup": warm, "budget_GiB": budget >> 30,
+           "mean_request_MP": round(mean_px / 1e6, 3), "capacity_continuous": cap}
+    for frac in (0.7, 0.9):
+        rate = frac * cap["MPix_s"] * 1e6 / mean_px
+        log(f"serving: Poisson trace at {frac} x capacity ({rate:.0f} requests/s)")
+        res[f"continuous_{frac}x"] = dict(run(M.MJD_SERVE_CONTINUOUS, rate), rate_per_s=round(rate, 1))
+        res[f"sync_{frac}x"] = dict(run(M.MJD_SERVE_SYNC, rate), rate_per_s=round(rate, 1))
+    # bit-exactness: the smallest pool image as served, against the oracle
+    k = min(range(len(pool)), key=lambda i: px_of[i])
+    f, c, q, o, qt = pool[k]
+    res["bit_exact_sample"] = {"pool_image": k, "size": [f["width"], f["height"]],
+                               "equal": bool(np.array_equal(o.numpy(), oracle.decode(
+                                   f, c.numpy().reshape(-1, 64), qt, "fancy")))}
+    return res
+
+
 def batch_samples_match(imgs, mode):
     """Oracle check of the batched outputs: the three smallest images whole,
     and one interior MCU row of the three largest (decoded by the oracle from
@@ -402,6 +469,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_pipeline:
         extras["pipeline"] = pipeline_workload(args, M, ctx, dev)
+    if not args.no_serve:
+        extras["serve"] = serve_workload(args, M, ctx, dev)
 
     out = {
         "metric": METRIC,

@@ -4,7 +4,8 @@ chroma upsampling -> YCbCr->RGB as one fused HIP kernel behind a C ABI
 """
 from __future__ import annotations
 
-from ._binding import (MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE, Batch, Context, MjdError, Pipeline,  # noqa: F401
+from ._binding import (MJD_SERVE_CONTINUOUS, MJD_SERVE_SYNC, MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE,  # noqa: F401
+                       Batch, Context, MjdError, Pipeline, Server,
                        mjd_batch_create, mjd_batch_destroy, mjd_batch_launch,
                        mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
                        mjd_decode, mjd_entropy_decode, mjd_geometry_of, mjd_last_error, mjd_parse,

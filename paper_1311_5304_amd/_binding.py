@@ -81,6 +81,23 @@ class mjd_pipeline_stats(ctypes.Structure):
 
 
 MJD_PIPELINE_ENTROPY_ONLY = 1
+MJD_SERVE_CONTINUOUS = 0
+MJD_SERVE_SYNC = 1
+
+
+class mjd_server_config(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("upsample", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
+
+
+class mjd_request(ctypes.Structure):
+    _fields_ = [("frame", mjd_frame), ("h_coef", ctypes.c_void_p), ("h_qt", ctypes.c_void_p),
+                ("h_rgb", ctypes.c_void_p), ("pitch", ctypes.c_uint64), ("arrival_ns", ctypes.c_uint64)]
+
+
+class mjd_request_times(ctypes.Structure):
+    _fields_ = [("arrival_ns", ctypes.c_uint64), ("admit_ns", ctypes.c_uint64), ("launch_ns", ctypes.c_uint64),
+                ("done_ns", ctypes.c_uint64), ("status", ctypes.c_int32), ("batch", ctypes.c_uint32)]
 
 _lib = None
 
@@ -125,6 +142,18 @@ def lib() -> ctypes.CDLL:
         L.mjd_pipeline_run.restype = i32
         L.mjd_pipeline_destroy.argtypes = [vp]
         L.mjd_pipeline_destroy.restype = None
+        L.mjd_server_create.argtypes = [vp, ctypes.POINTER(mjd_server_config), ctypes.POINTER(vp)]
+        L.mjd_server_create.restype = i32
+        L.mjd_server_now_ns.argtypes = [vp]
+        L.mjd_server_now_ns.restype = ctypes.c_uint64
+        L.mjd_server_submit.argtypes = [vp, ctypes.POINTER(mjd_request), ctypes.POINTER(ctypes.c_uint64)]
+        L.mjd_server_submit.restype = i32
+        L.mjd_server_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(mjd_request_times)]
+        L.mjd_server_wait.restype = i32
+        L.mjd_server_drain.argtypes = [vp]
+        L.mjd_server_drain.restype = i32
+        L.mjd_server_destroy.argtypes = [vp]
+        L.mjd_server_destroy.restype = None
         L.mjd_copy.argtypes = [vp, vp, vp, sz, vp]
         L.mjd_copy.restype = i32
         L.mjd_last_error.argtypes = []
@@ -357,6 +386,55 @@ class Pipeline:
         if self.handle:
             lib().mjd_pipeline_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Owns an mjd_server*: the continuous-batching (or synchronous) request loop."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, upsample: int = 1, mode: int = MJD_SERVE_CONTINUOUS,
+                 max_batch: int = 256, max_inflight: int = 2):
+        cfg = mjd_server_config(budget_bytes=int(budget_bytes), upsample=int(upsample), mode=int(mode),
+                                max_batch=int(max_batch), max_inflight=int(max_inflight))
+        p = ctypes.c_void_p()
+        _check(lib().mjd_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(p)))
+        self.handle = p
+        self._keep = {}
+
+    def now_ns(self) -> int:
+        return int(lib().mjd_server_now_ns(self.handle))
+
+    def submit(self, frame, coef, qt, rgb, pitch: int, arrival_ns: int = 0) -> int:
+        """coef/qt/rgb: host buffers (pinned tensors or numpy arrays) that stay alive until done."""
+        r = mjd_request(frame=make_frame(frame), h_coef=_ptr(coef), h_qt=_ptr(qt), h_rgb=_ptr(rgb),
+                        pitch=int(pitch), arrival_ns=int(arrival_ns))
+        rid = ctypes.c_uint64()
+        _check(lib().mjd_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))
+        self._keep[rid.value] = (coef, qt, rgb)
+        return rid.value
+
+    def wait(self, rid: int) -> dict:
+        t = mjd_request_times()
+        rc = lib().mjd_server_wait(self.handle, int(rid), ctypes.byref(t))
+        self._keep.pop(rid, None)
+        out = {k: getattr(t, k) for k, _ in mjd_request_times._fields_}
+        if rc != MJD_OK:
+            raise MjdError(rc, mjd_last_error())
+        return out
+
+    def drain(self):
+        _check(lib().mjd_server_drain(self.handle))
+
+    def close(self):
+        if self.handle:
+            lib().mjd_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -323,9 +323,14 @@ struct Run {
     const size_t y1 = std::min<size_t>(H, static_cast<size_t>(b.r1) * im.g.mcu_h);
     if ((r = hipStreamWaitEvent(p->s_d2h, e[3], 0)) != hipSuccess) return r;
     if ((r = hipEventRecord(e[4], p->s_d2h)) != hipSuccess) return r;
-    if ((r = hipMemcpy2DAsync(im.h_rgb + y0 * im.pitch, im.pitch, sl.d_rgb + y0 * 3ull * W, 3ull * W, 3ull * W,
-                              y1 - y0, hipMemcpyDeviceToHost, p->s_d2h)) != hipSuccess)
-      return r;
+    // dense host rows take one linear copy; strided ones a 2-D copy
+    if (im.pitch == 3ull * W)
+      r = hipMemcpyAsync(im.h_rgb + y0 * im.pitch, sl.d_rgb + y0 * 3ull * W, (y1 - y0) * 3ull * W,
+                         hipMemcpyDeviceToHost, p->s_d2h);
+    else
+      r = hipMemcpy2DAsync(im.h_rgb + y0 * im.pitch, im.pitch, sl.d_rgb + y0 * 3ull * W, 3ull * W, 3ull * W,
+                           y1 - y0, hipMemcpyDeviceToHost, p->s_d2h);
+    if (r != hipSuccess) return r;
     return hipEventRecord(e[5], p->s_d2h);
   }
 

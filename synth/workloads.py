@@ -72,6 +72,32 @@ def corpus_specs(n: int = 1000, mp_lo: float = 1.0, mp_hi: float = 24.0, workloa
     return specs
 
 
+def serving_pool(n: int = 96, mp_lo: float = 0.1, mp_hi: float = 24.0, workload_id: int = 5):
+    """Distinct request images of the serving trace: megapixels log-uniform in
+    [mp_lo, mp_hi], aspect ratio uniform in [3:4, 4:3], samplings in thirds,
+    quality uniform in 50..95."""
+    rng = np.random.default_rng(seed_of(workload_id, 0xFFFFF))
+    thirds = [n // 3, n // 3, n - 2 * (n // 3)]
+    samplings = ["444"] * thirds[0] + ["422"] * thirds[1] + ["420"] * thirds[2]
+    rng.shuffle(samplings)
+    specs = []
+    for i in range(n):
+        mp = float(np.exp(rng.uniform(np.log(mp_lo), np.log(mp_hi))))
+        a = float(rng.uniform(0.75, 4 / 3))
+        w = max(1, int(round((mp * 1e6 * a) ** 0.5)))
+        h = max(1, int(round(mp * 1e6 / w)))
+        specs.append((w, h, samplings[i], int(rng.integers(50, 96)), seed_of(workload_id, i)))
+    return specs
+
+
+def serving_trace(n_requests: int, pool_size: int, rate_per_s: float, workload_id: int = 5):
+    """Poisson arrivals: (arrival time in ns from the trace start, pool index) per request."""
+    rng = np.random.default_rng(seed_of(workload_id, 0xFFFFE))
+    gaps = rng.exponential(1.0 / rate_per_s, size=n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    return [(int(round(x * 1e9)), int(rng.integers(0, pool_size))) for x in t]
+
+
 def batch_image(spec, sigma: float = 8.0):
     w, h, sampling, q, seed = spec
     rgb = gradient_rgb(w, h, seed, sigma=sigma)
@@ -100,5 +126,6 @@ def random_coefficients(frame: dict, seed: int, scale: float = 60.0, density: fl
     return np.clip(c, -1023, 1023).astype(np.int16)
 
 
-__all__ = ["seed_of", "small_420_simple", "large_420_fancy", "batch_specs", "corpus_specs", "batch_image",
+__all__ = ["seed_of", "small_420_simple", "large_420_fancy", "batch_specs", "corpus_specs", "serving_pool",
+           "serving_trace", "batch_image",
            "random_coefficients", "make_frame", "mcu_grid"]
