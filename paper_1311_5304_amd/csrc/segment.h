@@ -468,8 +468,9 @@ struct SegmentDecoder {
         uint8_t* row = sub_rgb + (mul24(cr_l * VF + dy, pitch24) + 12 * HF * g);
         if (nv == 4 * HF && im.aligned_out) {
           uint32_t* wd = reinterpret_cast<uint32_t*>(row);
+          // streaming stores: RGB is written once and never read back here
 #pragma unroll
-          for (int kk = 0; kk < 3 * HF; ++kk) wd[kk] = w[kk];
+          for (int kk = 0; kk < 3 * HF; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
         } else {
           store_ragged(row, w, 3 * nv);
         }

@@ -168,7 +168,9 @@ static hipError_t copy_in(mjd_server* s, Request& q) {
 
 static hipError_t copy_out(mjd_server* s, Request& q) {
   const uint8_t* rgb = s->d_arena + q.off + q.coef_bytes + kQtBytes;
-  if (q.r.pitch == q.rgb_pitch)  // dense rows on both sides: one linear copy
+  // rows without padding on both sides: one linear copy (with padding, the
+  // host bytes beyond 3 * width must stay untouched)
+  if (q.r.pitch == 3ull * q.r.frame.width && q.rgb_pitch == q.r.pitch)
     return hipMemcpyAsync(q.r.h_rgb, rgb, q.rgb_pitch * q.r.frame.height, hipMemcpyDeviceToHost, s->s_d2h);
   return hipMemcpy2DAsync(q.r.h_rgb, q.r.pitch, rgb, q.rgb_pitch, 3ull * q.r.frame.width, q.r.frame.height,
                           hipMemcpyDeviceToHost, s->s_d2h);
