@@ -86,6 +86,8 @@ struct SegCfg {
   static_assert(P1_LANES <= NT, "one phase-1 round per sub-tile");
   static_assert(NT % 64 == 0 && NT >= 96, "whole waves; quant table load needs 96 lanes");
   static_assert(N_MAIN % 64 == 0, "tile blocks fill whole waves");
+  static_assert(!HALO_Y || (NYB >= 3 && N_TB * 128 <= YROWS * YWD * 4 && N_TB <= N_SLOT),
+                "the neighbour rows' blocks fit the buffers they borrow");
 };
 
 template <class C>
@@ -112,7 +114,8 @@ struct SegmentDecoder {
   __device__ uint32_t* qtab(int c) const { return reinterpret_cast<uint32_t*>(lds + C::OFF_Q) + c * 32; }
   __device__ int* wside() const { return reinterpret_cast<int*>(lds + C::OFF_WS); }
   __device__ int* wtb() const { return reinterpret_cast<int*>(lds + C::OFF_WT); }
-  __device__ static int ring_row(int gy) { return (gy + CROWS) % CROWS; }
+  static_assert((CROWS & (CROWS - 1)) == 0, "chroma ring rows: a power of two");
+  __device__ static int ring_row(int gy) { return gy & (CROWS - 1); }
 
   __device__ int sub_r0(int k) const { return r0 + k * SY; }
   __device__ int sub_rows(int k) const { return min(SY, r1 - (r0 + k * SY)); }
@@ -122,6 +125,8 @@ struct SegmentDecoder {
   }
 
   // Global address of staged block `j` of sub-tile k, or null when absent.
+  // Blocks j < N_MAIN are block j / SM of MCU j % SM of the sub-tile; the
+  // rest are the chroma blocks of the MCUs left and right of the strip.
   __device__ const int16_t* slot_src(int k, int j) const {
     const int my0 = sub_r0(k), nmy = sub_rows(k);
     if (j < N_MAIN) {
@@ -166,23 +171,52 @@ struct SegmentDecoder {
   }
 
   // ---- neighbour blocks above/below the segment (4:2:0 fancy) ----
-  // Step A: lanes (task, column u) read one column straight from global
-  // memory and form the single pass-1 output of the sample row the filter
-  // needs (7 for the block above, 0 for the block below).
+  // The chroma blocks of the MCU row above the segment (fetched with sub-tile
+  // 0, into the luma buffer of sub-tile 2, which is idle until step 2) and
+  // below it (fetched after the last sub-tile, into the then idle staging
+  // buffer) arrive by DMA like the sub-tiles, in the same rotated layout.
+  __device__ uint8_t* tb_area(bool below) const {
+    return below ? stage() : reinterpret_cast<uint8_t*>(ybuf(2));
+  }
+
+  __device__ void dma_tb(bool below) const {
+    const int my = below ? r1 : r0 - 1;
+    if (my < 0 || my >= im.mcus_y) return;
+    constexpr int CHUNKS = N_TB * 8;
+    uint8_t* area = tb_area(below);
+    for (int base = (tid & ~63); base < CHUNKS; base += NT) {
+      const int i = base + (tid & 63);
+      if (i < CHUNKS) {
+        const int t = i >> 3;
+        const int c = ((i & 7) - t) & 7;
+        const int pos = t >> 1;
+        const int mx = mx0 - 1 + pos;
+        if (pos < nmx + 2 && mx >= 0 && mx < im.mcus_x)
+          __builtin_amdgcn_global_load_lds(static_cast<const void*>(block_ptr(my, mx, NY + (t & 1)) + 8 * c),
+                                           (lds_void_t*)(area + base * 16), 16, 0, 0);
+      }
+    }
+  }
+
+  // Step A: lanes (task, column u) read one staged column and form the single
+  // pass-1 output of the sample row the filter needs (7 for the block above,
+  // 0 for the block below).
   __device__ void tb_step_a(bool below) const {
     const int my = below ? r1 : r0 - 1;
     if (my < 0 || my >= im.mcus_y) return;
+    const uint8_t* area = tb_area(below);
     for (int s = tid; s < 8 * N_TB; s += NT) {
       const int t = s >> 3, u = s & 7;
       const int pos = t >> 1;
       const int mx = mx0 - 1 + pos;
       if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) continue;
       const int comp = t & 1;
-      const int16_t* col = block_ptr(my, mx, NY + comp) + u;
+      const uint8_t* blk = area + t * 128 + 2 * u;
       const uint16_t* q = reinterpret_cast<const uint16_t*>(qtab(1 + comp)) + u;
       int x[8];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) x[v] = col[8 * v] * static_cast<int>(q[8 * v]);
+      for (int v = 0; v < 8; ++v)
+        x[v] = *reinterpret_cast<const int16_t*>(blk + (((v + t) & 7) << 4)) * static_cast<int>(q[8 * v]);
       const int o = below ? idct8_edge_raw<false>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias)
                           : idct8_edge_raw<true>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias);
       wtb()[t * 8 + u] = o >> kPass1Shift;
@@ -365,6 +399,37 @@ struct SegmentDecoder {
     }
   }
 
+  // ---- phase 2 helpers: fancy h2v2 on packed 16-bit pairs ----
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+  // Chroma samples c0..c5 around the 4 samples at p[0] (c0 = the one
+  // before, c5 = the one after) as (c0, c1), (c2, c3), (c4, c5).
+  __device__ static void chroma_pairs(const uint32_t* p, u16x2 v[3]) {
+    const uint32_t l = p[-1], m = p[0], r = p[1];
+    v[0] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(m, l, 0x0C040C03u));
+    v[1] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(m, m, 0x0C020C01u));
+    v[2] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(r, m, 0x0C040C03u));
+  }
+
+  // One output row from the vertical sums s0..s5 (as pairs): for sample j
+  // (1..4) the even pixel is (3 s_j + s_{j-1} + 8) >> 4 and the odd one
+  // (3 s_j + s_{j+1} + 7) >> 4, each minus 128; o[] gets the 8 pixels.
+  __device__ static void h2v2_row(const u16x2 s[3], int o[8]) {
+    const u16x2 s12 = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, s[1]),
+                                                                       __builtin_bit_cast(uint32_t, s[0]), 0x05040302u));
+    const u16x2 s34 = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, s[2]),
+                                                                       __builtin_bit_cast(uint32_t, s[1]), 0x05040302u));
+    const u16x2 three = {3, 3}, even_bias = {2040, 2040}, odd_bias = {2041, 2041};
+    const i16x2 four = {4, 4};
+    const i16x2 e01 = __builtin_bit_cast(i16x2, static_cast<u16x2>(s12 * three + s[0] - even_bias)) >> four;
+    const i16x2 e23 = __builtin_bit_cast(i16x2, static_cast<u16x2>(s34 * three + s[1] - even_bias)) >> four;
+    const i16x2 o01 = __builtin_bit_cast(i16x2, static_cast<u16x2>(s12 * three + s[1] - odd_bias)) >> four;
+    const i16x2 o23 = __builtin_bit_cast(i16x2, static_cast<u16x2>(s34 * three + s[2] - odd_bias)) >> four;
+    o[0] = e01.x; o[1] = o01.x; o[2] = e01.y; o[3] = o01.y;
+    o[4] = e23.x; o[5] = o23.x; o[6] = e23.y; o[7] = o23.y;
+  }
+
   // ---- phase 2 of sub-tile k: upsample + colour + store ----
   __device__ void phase2(int k) const {
     const int my0 = sub_r0(k), nmy = sub_rows(k);
@@ -373,7 +438,13 @@ struct SegmentDecoder {
     const uint32_t* ys = ybuf(k);
     uint8_t* const sub_rgb = im.rgb + static_cast<size_t>(gcy0 * VF) * im.pitch + static_cast<size_t>(gcx0 * HF) * 3;
     const int pitch24 = static_cast<int>(im.pitch);
-    for (int uidx = tid; uidx < C::UNITS; uidx += NT) {
+    // For fancy 4:2:2 the lanes that transform a block in phase 1 take one
+    // unit each and the neighbour-column lanes, which have little phase-1
+    // work, share the rest; otherwise all lanes share evenly.
+    constexpr int L1 = (HALO_X && !HALO_Y && NT > N_MAIN) ? N_MAIN : 0;
+    static_assert(C::UNITS >= L1, "one unit for every block lane");
+    const int ustep = tid < L1 ? C::UNITS : NT - L1;
+    for (int uidx = tid; uidx < C::UNITS; uidx += ustep) {
       const int cr_l = uidx / C::UX;
       const int g = uidx - cr_l * C::UX;
       if (g >= 2 * nmx || cr_l >= 8 * nmy) continue;
@@ -397,15 +468,15 @@ struct SegmentDecoder {
 #pragma unroll
               for (int dx = 0; dx < HF; ++dx) out[dy][i * HF + dx] = static_cast<int>(byte_at(w, i)) - 128;
         } else {
-          int cc[6];
-          {
-            const uint32_t l = plane[-1], m = plane[0], r = plane[1];
-            cc[0] = byte_at(l, 3);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) cc[1 + i] = byte_at(m, i);
-            cc[5] = byte_at(r, 0);
-          }
           if constexpr (VF == 1) {
+            int cc[6];
+            {
+              const uint32_t l = plane[-1], m = plane[0], r = plane[1];
+              cc[0] = byte_at(l, 3);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) cc[1 + i] = byte_at(m, i);
+              cc[5] = byte_at(r, 0);
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
               const int m3 = 3 * cc[1 + i];
@@ -413,32 +484,23 @@ struct SegmentDecoder {
               out[0][2 * i + 1] = (m3 + cc[i + 2] - 510) >> 2;  // (3C + Cnext + 2) / 4 - 128
             }
           } else {
-            int su[6], sd[6];
-            {
-              const uint32_t* up = ring + ring_row(gcy0 + cr_l - 1) * CWD + g + 2;
-              const uint32_t* dn = ring + ring_row(gcy0 + cr_l + 1) * CWD + g + 2;
-              const uint32_t ul = up[-1], um = up[0], ur = up[1];
-              const uint32_t dl = dn[-1], dm = dn[0], dr = dn[1];
-              const int cu[6] = {static_cast<int>(byte_at(ul, 3)), static_cast<int>(byte_at(um, 0)),
-                                 static_cast<int>(byte_at(um, 1)), static_cast<int>(byte_at(um, 2)),
-                                 static_cast<int>(byte_at(um, 3)), static_cast<int>(byte_at(ur, 0))};
-              const int cd[6] = {static_cast<int>(byte_at(dl, 3)), static_cast<int>(byte_at(dm, 0)),
-                                 static_cast<int>(byte_at(dm, 1)), static_cast<int>(byte_at(dm, 2)),
-                                 static_cast<int>(byte_at(dm, 3)), static_cast<int>(byte_at(dr, 0))};
+            // h2v2 on packed 16-bit halves: pairs of neighbouring chroma
+            // samples, the unrounded 3:1 vertical sums, then the 3:1
+            // horizontal filter on pairs of outputs (every intermediate is
+            // below 2^12, so the halves never carry into each other)
+            u16x2 pm[3], pu[3], pd[3];
+            chroma_pairs(plane, pm);
+            chroma_pairs(ring + ring_row(gcy0 + cr_l - 1) * CWD + g + 2, pu);
+            chroma_pairs(ring + ring_row(gcy0 + cr_l + 1) * CWD + g + 2, pd);
+            const u16x2 three = {3, 3};
+            u16x2 su[3], sd[3];
 #pragma unroll
-              for (int j = 0; j < 6; ++j) {
-                const int m3 = 3 * cc[j];
-                su[j] = m3 + cu[j];  // unrounded vertical triangle sums
-                sd[j] = m3 + cd[j];
-              }
+            for (int j = 0; j < 3; ++j) {
+              su[j] = pm[j] * three + pu[j];
+              sd[j] = pm[j] * three + pd[j];
             }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              out[0][2 * i] = (3 * su[1 + i] + su[i] - 2040) >> 4;          // (.. + 8) / 16 - 128
-              out[0][2 * i + 1] = (3 * su[1 + i] + su[i + 2] - 2041) >> 4;  // (.. + 7) / 16 - 128
-              out[VF - 1][2 * i] = (3 * sd[1 + i] + sd[i] - 2040) >> 4;
-              out[VF - 1][2 * i + 1] = (3 * sd[1 + i] + sd[i + 2] - 2041) >> 4;
-            }
+            h2v2_row(su, out[0]);
+            h2v2_row(sd, out[VF - 1]);
           }
         }
 #pragma unroll
@@ -500,7 +562,11 @@ struct SegmentDecoder {
     __syncthreads();  // the previous segment's readers are done with every buffer
     load_qtabs();
     dma(0);
-    __syncthreads();  // quant tables visible
+    if constexpr (HALO_Y) {
+      dma_tb(false);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __syncthreads();  // quant tables (and the blocks above) visible
     if constexpr (HALO_Y) tb_step_a(false);
 
     for (int k = 0; k < K + LAG; ++k) {
@@ -512,11 +578,17 @@ struct SegmentDecoder {
         if (k >= 1 && k - 1 < K) vertical_edges(k - 1);
         if (k == K) tb_step_a(true);
       }
-      // stores of the older sub-tile first: they drain while phase 1 computes
-      if (k >= LAG) phase2(k - LAG);
       if (k < K) read_stage(k, h);
       __syncthreads();  // staging free for the next sub-tile
       if (k + 1 < K) dma(k + 1);
+      if constexpr (HALO_Y) {
+        if (k + 1 == K) dma_tb(true);  // staging is idle from here on
+      }
+      // Phase 2 of an older sub-tile and phase 1 of this one use disjoint
+      // luma buffers and chroma ring rows, so they share one barrier
+      // interval; phase 2 goes first so its stores drain while the IDCT
+      // runs, and lanes without a block of their own take most of it.
+      if (k >= LAG) phase2(k - LAG);
       if (k < K) phase1(k, h);
       __syncthreads();
       if (k < K) phase1_finish(k);
