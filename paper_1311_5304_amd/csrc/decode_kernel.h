@@ -103,17 +103,104 @@ __device__ __forceinline__ uint32_t sat_u8x2(int a, int b) {
   return r;
 }
 
-// Same, from the high halves: sat(a >> 16) | sat(b >> 16) << 8 (arithmetic
-// shifts; a and b must lie in +-2^31 with (x >> 16) inside int16).
+// The two saturated bytes of the int16 pair `pair` written into bytes 2..3
+// of `lo`, whose bytes 0..1 are kept (an SDWA word write in place of a
+// shift-or).
+__device__ __forceinline__ uint32_t sat_u8x2_into_hi(uint32_t lo, uint32_t pair) {
+  asm("v_sat_pk_u8_i16_sdwa %0, %1 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:DWORD"
+      : "+v"(lo) : "v"(pair));
+  return lo;
+}
+
+// (a >> 16, b >> 16) as an int16 pair (arithmetic shifts, one byte permute).
+__device__ __forceinline__ uint32_t hi_halves(int a, int b) {
+  return __builtin_amdgcn_perm(static_cast<uint32_t>(b), static_cast<uint32_t>(a), 0x07060302u);
+}
+
+// Same, from the high halves: sat(a >> 16) | sat(b >> 16) << 8 (a and b must
+// lie in +-2^31 with (x >> 16) inside int16).
 __device__ __forceinline__ uint32_t sat_u8x2_hi(int a, int b) {
-  const uint32_t pair = __builtin_amdgcn_perm(static_cast<uint32_t>(b), static_cast<uint32_t>(a), 0x07060302u);
   uint32_t r;
-  asm("v_sat_pk_u8_i16 %0, %1" : "=v"(r) : "v"(pair));
+  asm("v_sat_pk_u8_i16 %0, %1" : "=v"(r) : "v"(hi_halves(a, b)));
   return r;
 }
 
 __device__ __forceinline__ uint32_t pack4(int s0, int s1, int s2, int s3) {
   return sat_u8x2(s0, s1) | (sat_u8x2(s2, s3) << 16);
+}
+
+// Four raw pass-2 sums -> four clamped samples (sum >> kPass2Shift) as bytes.
+// (v >> 16) >> 2 == v >> 18 for arithmetic shifts, so the high halves are
+// gathered first and shifted as int16 pairs.
+__device__ __forceinline__ uint32_t descale_pack4(int s0, int s1, int s2, int s3) {
+  typedef short i16x2 __attribute__((ext_vector_type(2)));
+  const i16x2 sh = {kPass2Shift - 16, kPass2Shift - 16};
+  const uint32_t p01 = __builtin_bit_cast(uint32_t, __builtin_bit_cast(i16x2, hi_halves(s0, s1)) >> sh);
+  const uint32_t p23 = __builtin_bit_cast(uint32_t, __builtin_bit_cast(i16x2, hi_halves(s2, s3)) >> sh);
+  uint32_t r;
+  asm("v_sat_pk_u8_i16 %0, %1" : "=v"(r) : "v"(p01));
+  return sat_u8x2_into_hi(r, p23);
+}
+
+// --- pass 1 as int16 dot products -------------------------------------------
+// Before its descale shift the flowgraph is exact integer arithmetic (sums
+// and multiplications by constants), so each of its outputs is an integer
+// linear form in the 8 inputs.  Expanding the network gives the weights
+// below; all of them, and on the documented domain every dequantised
+// coefficient, fit int16, so v_dot2_i32_i16 forms two terms per instruction
+// with an exact 32-bit sum.  The rows of the weight matrix are
+// y_k = e_k + o_k and y_{7-k} = e_k - o_k.
+constexpr int kE2a = kR + kR2;   // x2 in e0 (and -x2 in e3)
+constexpr int kE6a = kR;         // x6 in e0
+constexpr int kE2b = kR;         // x2 in e1 (and -x2 in e2)
+constexpr int kE6b = kR - kR6;   // x6 in e1
+// odd weights: o_k = sum_j kO[k][j] * x_{2j+1}
+constexpr int kO[4][4] = {
+    {kP1 - kZ1 - kZ4 + kZ5, kZ5, kZ5 - kZ4, kZ5 - kZ1},
+    {kZ5, kP3 - kZ2 - kZ3 + kZ5, kZ5 - kZ2, kZ5 - kZ3},
+    {kZ5 - kZ4, kZ5 - kZ2, kP5 - kZ2 - kZ4 + kZ5, kZ5},
+    {kZ5 - kZ1, kZ5 - kZ3, kZ5, kP7 - kZ1 - kZ3 + kZ5},
+};
+
+constexpr uint32_t wpair(int lo, int hi) {
+  return static_cast<uint32_t>(static_cast<uint16_t>(lo)) | (static_cast<uint32_t>(static_cast<uint16_t>(hi)) << 16);
+}
+
+// lo(a) * lo(w) + hi(a) * hi(w) + c over int16 halves (v_dot2_i32_i16, no
+// clamp); the weight pair travels in an SGPR.
+__device__ __forceinline__ int dot2(uint32_t a, uint32_t w, int c) {
+  int r;
+  asm("v_dot2_i32_i16 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(w), "v"(c));
+  return r;
+}
+__device__ __forceinline__ int dot2z(uint32_t a, uint32_t w) {
+  int r;
+  asm("v_dot2_i32_i16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "s"(w));
+  return r;
+}
+
+// One column of pass 1 from the input pairs (x0, x4), (x2, x6), (x1, x3),
+// (x5, x7); y[] as idct8_raw returns it (bias included, before the shift).
+__device__ __forceinline__ void idct8_dot(uint32_t p04, uint32_t p26, uint32_t p13, uint32_t p57,
+                                          int bias, int y[8]) {
+  const int t0 = dot2(p04, wpair(1 << kConstBits, 1 << kConstBits), bias);
+  const int t1 = dot2(p04, wpair(1 << kConstBits, -(1 << kConstBits)), bias);
+  const int e0 = dot2(p26, wpair(kE2a, kE6a), t0);
+  const int e3 = dot2(p26, wpair(-kE2a, -kE6a), t0);
+  const int e1 = dot2(p26, wpair(kE2b, kE6b), t1);
+  const int e2 = dot2(p26, wpair(-kE2b, -kE6b), t1);
+  const int o0 = dot2(p13, wpair(kO[0][0], kO[0][1]), dot2z(p57, wpair(kO[0][2], kO[0][3])));
+  const int o1 = dot2(p13, wpair(kO[1][0], kO[1][1]), dot2z(p57, wpair(kO[1][2], kO[1][3])));
+  const int o2 = dot2(p13, wpair(kO[2][0], kO[2][1]), dot2z(p57, wpair(kO[2][2], kO[2][3])));
+  const int o3 = dot2(p13, wpair(kO[3][0], kO[3][1]), dot2z(p57, wpair(kO[3][2], kO[3][3])));
+  y[0] = e0 + o0;
+  y[7] = e0 - o0;
+  y[1] = e1 + o1;
+  y[6] = e1 - o1;
+  y[2] = e2 + o2;
+  y[5] = e2 - o2;
+  y[3] = e3 + o3;
+  y[4] = e3 - o3;
 }
 
 // Dequantise + 2-D IDCT of one block (paper Sec. 4.1: columns first, Eq. 1,
@@ -123,9 +210,12 @@ __device__ __forceinline__ uint32_t pack4(int s0, int s1, int s2, int s3) {
 // level-shifted and clamped to 0..255.
 __device__ __forceinline__ void idct_block_regs(const v4i rows[8], const uint32_t* __restrict__ q,
                                                 uint32_t out[16]) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
   int ws[64];
   {
-    int d[64];
+    // dequantised pairs (coefficient row r, columns 2i and 2i + 1): the low
+    // 16 bits of each product, exact as int16 on the documented domain
+    uint32_t d[8][4];
     const v4i* qv = reinterpret_cast<const v4i*>(q);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -134,18 +224,20 @@ __device__ __forceinline__ void idct_block_regs(const v4i rows[8], const uint32_
       const int w[4] = {v.x, v.y, v.z, v.w};
       const int qw[4] = {qq.x, qq.y, qq.z, qq.w};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        d[8 * r + 2 * i] = static_cast<int16_t>(w[i] & 0xFFFF) * (qw[i] & 0xFFFF);
-        d[8 * r + 2 * i + 1] = (w[i] >> 16) * static_cast<int>(static_cast<uint32_t>(qw[i]) >> 16);
-      }
+      for (int i = 0; i < 4; ++i)
+        d[r][i] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, w[i]) * __builtin_bit_cast(u16x2, qw[i]));
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
+      // the column's pairs (row a, row b) from the halves of two row dwords
+      const int i = u >> 1;
+      const uint32_t sel = (u & 1) ? 0x07060302u : 0x05040100u;
       int y[8];
-      idct8_raw(d[u], d[8 + u], d[16 + u], d[24 + u], d[32 + u], d[40 + u], d[48 + u], d[56 + u],
+      idct8_dot(__builtin_amdgcn_perm(d[4][i], d[0][i], sel), __builtin_amdgcn_perm(d[6][i], d[2][i], sel),
+                __builtin_amdgcn_perm(d[3][i], d[1][i], sel), __builtin_amdgcn_perm(d[7][i], d[5][i], sel),
                 kPass1Bias, y);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) ws[8 * i + u] = y[i] >> kPass1Shift;
+      for (int k = 0; k < 8; ++k) ws[8 * k + u] = y[k] >> kPass1Shift;
     }
   }
 #pragma unroll
@@ -153,10 +245,8 @@ __device__ __forceinline__ void idct_block_regs(const v4i rows[8], const uint32_
     int s[8];
     idct8_raw(ws[8 * r], ws[8 * r + 1], ws[8 * r + 2], ws[8 * r + 3], ws[8 * r + 4], ws[8 * r + 5],
               ws[8 * r + 6], ws[8 * r + 7], kPass2Bias, s);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) s[i] >>= kPass2Shift;
-    out[2 * r] = pack4(s[0], s[1], s[2], s[3]);
-    out[2 * r + 1] = pack4(s[4], s[5], s[6], s[7]);
+    out[2 * r] = descale_pack4(s[0], s[1], s[2], s[3]);
+    out[2 * r + 1] = descale_pack4(s[4], s[5], s[6], s[7]);
   }
 }
 
@@ -185,9 +275,9 @@ __device__ __forceinline__ int y16_of(uint32_t ydw, int i) {
 // Four pixels -> 12 RGB bytes as 3 dwords (paper Fig. 5: pixel bytes grouped
 // into 4-byte vectors).
 __device__ __forceinline__ void pack_rgb4(const RGBWide p[4], uint32_t w[3]) {
-  w[0] = sat_u8x2_hi(p[0].r, p[0].g) | (sat_u8x2_hi(p[0].b, p[1].r) << 16);
-  w[1] = sat_u8x2_hi(p[1].g, p[1].b) | (sat_u8x2_hi(p[2].r, p[2].g) << 16);
-  w[2] = sat_u8x2_hi(p[2].b, p[3].r) | (sat_u8x2_hi(p[3].g, p[3].b) << 16);
+  w[0] = sat_u8x2_into_hi(sat_u8x2_hi(p[0].r, p[0].g), hi_halves(p[0].b, p[1].r));
+  w[1] = sat_u8x2_into_hi(sat_u8x2_hi(p[1].g, p[1].b), hi_halves(p[2].r, p[2].g));
+  w[2] = sat_u8x2_into_hi(sat_u8x2_hi(p[2].b, p[3].r), hi_halves(p[3].g, p[3].b));
 }
 
 }  // namespace mjd

@@ -571,7 +571,9 @@ struct SegmentDecoder {
 
     for (int k = 0; k < K + LAG; ++k) {
       Held h{};  // per step, fully defined so it stays in registers
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      // Wait for the DMA of the previous step (the counter also covers the
+      // RGB stores, so the steps with no DMA in flight skip it).
+      if (k < K || (HALO_Y && k == K)) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();  // staging of k landed; last step's LDS writes visible
       if constexpr (HALO_Y) {
         if (k == 0) tb_step_b(false);
