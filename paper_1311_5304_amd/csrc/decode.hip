@@ -19,7 +19,7 @@ struct SegGrid {
 };
 
 template <class C>
-__global__ __launch_bounds__(C::NT, 2) void decode_segments(const ImageView im, const SegGrid sg) {
+__global__ __launch_bounds__(C::NT, C::WAVES_PER_SIMD) void decode_segments(const ImageView im, const SegGrid sg) {
   __shared__ __align__(16) uint8_t lds[C::LDS_BYTES];
   // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
   // contiguous run of segments (row-major over strips) so neighbouring

@@ -205,10 +205,10 @@ __device__ __forceinline__ void idct8_dot(uint32_t p04, uint32_t p26, uint32_t p
 
 // Dequantise + 2-D IDCT of one block (paper Sec. 4.1: columns first, Eq. 1,
 // then rows, Eq. 2).  rows: the block's 8 coefficient rows (8 int16 each, in
-// registers); q: the 64 uint16 factors as 32 dwords (LDS, 16-byte aligned).
+// registers); q: the 64 uint16 factors as 32 dwords (in LDS, 16-byte aligned).
 // out: 16 dwords, two per sample row (x order, little endian), samples
 // level-shifted and clamped to 0..255.
-__device__ __forceinline__ void idct_block_regs(const v4i rows[8], const uint32_t* __restrict__ q,
+__device__ __forceinline__ void idct_block_regs(const v4i rows[8], const __attribute__((address_space(3))) uint32_t* q,
                                                 uint32_t out[16]) {
   typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
   int ws[64];
@@ -216,7 +216,7 @@ __device__ __forceinline__ void idct_block_regs(const v4i rows[8], const uint32_
     // dequantised pairs (coefficient row r, columns 2i and 2i + 1): the low
     // 16 bits of each product, exact as int16 on the documented domain
     uint32_t d[8][4];
-    const v4i* qv = reinterpret_cast<const v4i*>(q);
+    const __attribute__((address_space(3))) v4i* qv = reinterpret_cast<const __attribute__((address_space(3))) v4i*>(q);
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       const v4i v = rows[r];

@@ -28,6 +28,12 @@
 namespace mjd {
 
 typedef __attribute__((address_space(3))) void lds_void_t;
+// LDS pointers proper (32-bit addresses, so index arithmetic stays 32-bit)
+typedef __attribute__((address_space(3))) uint8_t lds8;
+typedef __attribute__((address_space(3))) uint32_t lds32;
+typedef __attribute__((address_space(3))) int ldsi;
+typedef __attribute__((address_space(3))) int16_t lds16;
+typedef __attribute__((address_space(3))) uint16_t ldsu16;
 
 constexpr int round64c(int n) { return (n + 63) & ~63; }
 
@@ -60,6 +66,10 @@ struct SegCfg {
   static constexpr int BPM = NY + 2;
   static constexpr bool HALO_X = FANCY && HF == 2;
   static constexpr bool HALO_Y = FANCY && VF == 2;
+  // Steps by which the last phase 2 trails the last phase 1.  For the 4:2:0
+  // fancy filter a sub-tile's rows are upsampled one step after its
+  // transform, except its last chroma row, which needs the next sub-tile's
+  // first row and waits one step more.
   static constexpr int LAG = HALO_Y ? 2 : 1;
   static constexpr int SM = SX * SY;                       // MCUs per sub-tile
   static constexpr int N_MAIN = BPM * SM;                  // blocks per sub-tile
@@ -70,24 +80,35 @@ struct SegCfg {
   static constexpr int N_TB = HALO_Y ? 2 * (SX + 2) : 0;   // above or below neighbour blocks
   static constexpr int YWD = SX * 2 * HF;                  // luma sub-tile row, dwords
   static constexpr int YROWS = SY * 8 * VF;
-  static constexpr int NYB = LAG + 1;                      // luma buffers in flight
+  static constexpr int CR = 8 * SY;                        // chroma rows per sub-tile
+  // Luma: two sub-tile buffers in flight, or (4:2:0 fancy) one ring of a
+  // sub-tile plus one block row, which also keeps the previous sub-tile's
+  // last two rows while the next is transformed.
+  static constexpr int NYB = 2;
+  static constexpr int YRING = YROWS + 8;
+  static constexpr int Y_BYTES = (HALO_Y ? YRING : NYB * YROWS) * YWD * 4;
   static constexpr int CWD = (SX + 2) * 2;                 // chroma ring row, dwords (8-sample margins)
-  static constexpr int CROWS = (HALO_Y ? 4 : 2) * 8 * SY;  // chroma ring rows
+  static constexpr int CROWS = (HALO_Y ? 3 : 2) * CR;      // chroma ring rows
   static constexpr int UX = 2 * SX;                        // phase-2 units per chroma row
   static constexpr int UNITS = UX * 8 * SY;
   // LDS carve-up (bytes, 16-byte aligned pieces)
   static constexpr int OFF_STAGE = 0;
   static constexpr int OFF_Y = OFF_STAGE + N_SLOT * 128;
-  static constexpr int OFF_C = OFF_Y + NYB * YROWS * YWD * 4;
+  static constexpr int OFF_C = OFF_Y + Y_BYTES;
   static constexpr int OFF_Q = OFF_C + 2 * CROWS * CWD * 4;
   static constexpr int OFF_WS = OFF_Q + 3 * 128;
   static constexpr int OFF_WT = OFF_WS + (N_SIDE > 0 ? N_SIDE * 256 : 16);
   static constexpr int LDS_BYTES = OFF_WT + (N_TB > 0 ? N_TB * 32 : 16);
+  // Waves per SIMD that the LDS footprint allows (160 KB per CU, at most 3
+  // asked of the register allocator).
+  static constexpr int WAVES_PER_SIMD_LDS = (160 * 1024 / LDS_BYTES) * (NT / 64) / 4;
+  static constexpr int WAVES_PER_SIMD = WAVES_PER_SIMD_LDS < 1 ? 1 : (WAVES_PER_SIMD_LDS > 3 ? 3 : WAVES_PER_SIMD_LDS);
   static_assert(P1_LANES <= NT, "one phase-1 round per sub-tile");
   static_assert(NT % 64 == 0 && NT >= 96, "whole waves; quant table load needs 96 lanes");
   static_assert(N_MAIN % 64 == 0, "tile blocks fill whole waves");
-  static_assert(!HALO_Y || (NYB >= 3 && N_TB * 128 <= YROWS * YWD * 4 && N_TB <= N_SLOT),
+  static_assert(!HALO_Y || (N_TB * 128 <= Y_BYTES && N_TB <= N_SLOT),
                 "the neighbour rows' blocks fit the buffers they borrow");
+  static_assert(YROWS % 8 == 0 && CROWS % CR == 0, "blocks never straddle a ring's wrap");
 };
 
 template <class C>
@@ -95,27 +116,43 @@ struct SegmentDecoder {
   static constexpr int HF = C::HF, VF = C::VF, SX = C::SX, SY = C::SY, NT = C::NT;
   static constexpr int NY = C::NY, BPM = C::BPM, SM = C::SM, N_MAIN = C::N_MAIN;
   static constexpr int N_SIDE = C::N_SIDE, N_SLOT = C::N_SLOT, N_TB = C::N_TB;
-  static constexpr int YWD = C::YWD, YROWS = C::YROWS, NYB = C::NYB, CWD = C::CWD, CROWS = C::CROWS;
+  static constexpr int YWD = C::YWD, YROWS = C::YROWS, NYB = C::NYB, YRING = C::YRING;
+  static constexpr int CR = C::CR, CWD = C::CWD, CROWS = C::CROWS;
   static constexpr int LAG = C::LAG;
   static constexpr bool FANCY = C::FANCY, HALO_X = C::HALO_X, HALO_Y = C::HALO_Y;
 
-  uint8_t* lds;
+  lds8* lds;
   const ImageView& im;
   int tid;
   // segment geometry
   int mx0, nmx, r0, r1, K;
   int gcx0;  // global chroma column of the strip's first sample
 
-  __device__ SegmentDecoder(uint8_t* lds_, const ImageView& im_, int tid_) : lds(lds_), im(im_), tid(tid_) {}
+  __device__ SegmentDecoder(uint8_t* lds_, const ImageView& im_, int tid_)
+      : lds((lds8*)lds_), im(im_), tid(tid_) {}
 
-  __device__ uint8_t* stage() const { return lds + C::OFF_STAGE; }
-  __device__ uint32_t* ybuf(int k) const { return reinterpret_cast<uint32_t*>(lds + C::OFF_Y) + (k % NYB) * (YROWS * YWD); }
-  __device__ uint32_t* cring(int c) const { return reinterpret_cast<uint32_t*>(lds + C::OFF_C) + c * (CROWS * CWD); }
-  __device__ uint32_t* qtab(int c) const { return reinterpret_cast<uint32_t*>(lds + C::OFF_Q) + c * 32; }
-  __device__ int* wside() const { return reinterpret_cast<int*>(lds + C::OFF_WS); }
-  __device__ int* wtb() const { return reinterpret_cast<int*>(lds + C::OFF_WT); }
-  static_assert((CROWS & (CROWS - 1)) == 0, "chroma ring rows: a power of two");
-  __device__ static int ring_row(int gy) { return gy & (CROWS - 1); }
+  __device__ lds8* stage() const { return lds + C::OFF_STAGE; }
+  __device__ lds32* luma() const { return reinterpret_cast<lds32*>(lds + C::OFF_Y); }
+  __device__ lds32* cring(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_C) + c * (CROWS * CWD); }
+  __device__ lds32* qtab(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q) + c * 32; }
+  __device__ ldsi* wside() const { return reinterpret_cast<ldsi*>(lds + C::OFF_WS); }
+  __device__ ldsi* wtb() const { return reinterpret_cast<ldsi*>(lds + C::OFF_WT); }
+
+  // Luma row r (0 <= r < YROWS) of sub-tile k lives in row ybase(k) + r of
+  // the luma area, taken modulo YRING for the ring.  ybase is uniform.
+  __device__ static int ybase(int k) { return HALO_Y ? (YROWS * k) % YRING : (k % NYB) * YROWS; }
+  __device__ lds32* yrow(int base, int r) const {
+    int i = base + r;
+    if constexpr (HALO_Y) i = i >= YRING ? i - YRING : i;
+    return luma() + i * YWD;
+  }
+  // Chroma row r (0 <= r < CR) of sub-tile k is ring row cbase(k) + r (CROWS
+  // is a multiple of CR, so a sub-tile never wraps).  The row above the
+  // segment is ring row CROWS - 1, the row below it ring row below_row().
+  __device__ static int cbase(int k) { return (CR * k) % CROWS; }
+  __device__ int below_row() const { return (8 * (r1 - r0)) % CROWS; }
+  __device__ static int ring_prev(int rc) { return rc == 0 ? CROWS - 1 : rc - 1; }
+  __device__ static int ring_next(int rc) { return rc == CROWS - 1 ? 0 : rc + 1; }
 
   __device__ int sub_r0(int k) const { return r0 + k * SY; }
   __device__ int sub_rows(int k) const { return min(SY, r1 - (r0 + k * SY)); }
@@ -124,40 +161,49 @@ struct SegmentDecoder {
     return im.coef + (static_cast<size_t>(my) * im.mcus_x + mx) * (BPM * 64) + b * 64;
   }
 
-  // Global address of staged block `j` of sub-tile k, or null when absent.
-  // Blocks j < N_MAIN are block j / SM of MCU j % SM of the sub-tile; the
-  // rest are the chroma blocks of the MCUs left and right of the strip.
-  __device__ const int16_t* slot_src(int k, int j) const {
-    const int my0 = sub_r0(k), nmy = sub_rows(k);
+  // ---- coefficient DMA ----
+  // 16-byte chunk i of the staging buffer holds row ((i & 7) - j) & 7 of
+  // staged block j = i / 8: blocks j < N_MAIN are block j / SM of MCU j % SM
+  // of the sub-tile, the rest the chroma blocks of the MCUs left and right of
+  // the strip.  Row c of block j lands at ((c + j) & 7) * 16, so lanes that
+  // read whole blocks later hit distinct banks, while the 8 lanes of a block
+  // still read one 128-byte line.
+  static constexpr int DMA_CHUNKS = N_SLOT * 8;
+  static constexpr int kNoChunk = -0x7FFFFFFF - 1;
+
+  // Byte offset of chunk i from the sub-tile's first MCU (negative for the
+  // MCU left of the strip), or kNoChunk when the chunk lies outside the
+  // image or below the sub-tile's nmy MCU rows.  All products stay far
+  // inside 32 bits (a sub-tile spans SY MCU rows).
+  __device__ int chunk_offset(int i, int nmy, int row_bytes) const {
+    const int j = i >> 3;
+    const int c = ((i & 7) - j) & 7;
     if (j < N_MAIN) {
       const int b = j / SM;
       const int m = j - b * SM;
       const int lmy = m / SX, lmx = m - (m / SX) * SX;
-      if (lmx >= nmx || lmy >= nmy) return nullptr;
-      return block_ptr(my0 + lmy, mx0 + lmx, b);
+      if (lmx >= nmx || lmy >= nmy) return kNoChunk;
+      return lmy * row_bytes + lmx * (BPM * 128) + b * 128 + c * 16;
     }
     const int t = j - N_MAIN;  // (row << 2) | (right << 1) | chroma component
     const int pos = t >> 2;
-    const int mx = ((t >> 1) & 1) ? mx0 + nmx : mx0 - 1;
-    if (pos >= nmy || mx < 0 || mx >= im.mcus_x) return nullptr;
-    return block_ptr(my0 + pos, mx, NY + (t & 1));
+    const int dx = ((t >> 1) & 1) ? nmx : -1;
+    const int mx = mx0 + dx;
+    if (pos >= nmy || mx < 0 || mx >= im.mcus_x) return kNoChunk;
+    return pos * row_bytes + dx * (BPM * 128) + (NY + (t & 1)) * 128 + c * 16;
   }
 
-  // Copy sub-tile k's blocks into the staging buffer.  16-byte chunk i lands
-  // at LDS i*16: block j = i/8 keeps its 8 rows rotated by j (row c at
-  // position (c + j) & 7), so that lanes reading whole blocks later hit
-  // distinct banks; the 8 lanes of a block still read one 128-byte line.
+  // Copy sub-tile k's blocks into the staging buffer.
   __device__ void dma(int k) const {
-    constexpr int CHUNKS = N_SLOT * 8;
-    for (int base = (tid & ~63); base < CHUNKS; base += NT) {
+    const uint8_t* src0 = reinterpret_cast<const uint8_t*>(block_ptr(sub_r0(k), mx0, 0));
+    const int nmy = sub_rows(k);
+    const int row_bytes = im.mcus_x * (BPM * 128);
+    for (int base = (tid & ~63); base < DMA_CHUNKS; base += NT) {
       const int i = base + (tid & 63);
-      if (i < CHUNKS) {
-        const int j = i >> 3;
-        const int c = ((i & 7) - j) & 7;
-        const int16_t* src = slot_src(k, j);
-        if (src) __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + 8 * c),
-                                                 (lds_void_t*)(stage() + base * 16), 16, 0, 0);
-      }
+      const int off = i < DMA_CHUNKS ? chunk_offset(i, nmy, row_bytes) : kNoChunk;
+      if (off != kNoChunk)
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(src0 + off), (lds_void_t*)(stage() + base * 16),
+                                         16, 0, 0);
     }
   }
 
@@ -172,18 +218,18 @@ struct SegmentDecoder {
 
   // ---- neighbour blocks above/below the segment (4:2:0 fancy) ----
   // The chroma blocks of the MCU row above the segment (fetched with sub-tile
-  // 0, into the luma buffer of sub-tile 2, which is idle until step 2) and
+  // 0, into the luma ring, which phase 1 first writes after they are read) and
   // below it (fetched after the last sub-tile, into the then idle staging
   // buffer) arrive by DMA like the sub-tiles, in the same rotated layout.
-  __device__ uint8_t* tb_area(bool below) const {
-    return below ? stage() : reinterpret_cast<uint8_t*>(ybuf(2));
+  __device__ lds8* tb_area(bool below) const {
+    return below ? stage() : reinterpret_cast<lds8*>(luma());
   }
 
   __device__ void dma_tb(bool below) const {
     const int my = below ? r1 : r0 - 1;
     if (my < 0 || my >= im.mcus_y) return;
     constexpr int CHUNKS = N_TB * 8;
-    uint8_t* area = tb_area(below);
+    lds8* area = tb_area(below);
     for (int base = (tid & ~63); base < CHUNKS; base += NT) {
       const int i = base + (tid & 63);
       if (i < CHUNKS) {
@@ -204,19 +250,19 @@ struct SegmentDecoder {
   __device__ void tb_step_a(bool below) const {
     const int my = below ? r1 : r0 - 1;
     if (my < 0 || my >= im.mcus_y) return;
-    const uint8_t* area = tb_area(below);
+    const lds8* area = tb_area(below);
     for (int s = tid; s < 8 * N_TB; s += NT) {
       const int t = s >> 3, u = s & 7;
       const int pos = t >> 1;
       const int mx = mx0 - 1 + pos;
       if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) continue;
       const int comp = t & 1;
-      const uint8_t* blk = area + t * 128 + 2 * u;
-      const uint16_t* q = reinterpret_cast<const uint16_t*>(qtab(1 + comp)) + u;
+      const lds8* blk = area + t * 128 + 2 * u;
+      const ldsu16* q = reinterpret_cast<const ldsu16*>(qtab(1 + comp)) + u;
       int x[8];
 #pragma unroll
       for (int v = 0; v < 8; ++v)
-        x[v] = *reinterpret_cast<const int16_t*>(blk + (((v + t) & 7) << 4)) * static_cast<int>(q[8 * v]);
+        x[v] = *reinterpret_cast<const lds16*>(blk + (((v + t) & 7) << 4)) * static_cast<int>(q[8 * v]);
       const int o = below ? idct8_edge_raw<false>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias)
                           : idct8_edge_raw<true>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias);
       wtb()[t * 8 + u] = o >> kPass1Shift;
@@ -233,15 +279,15 @@ struct SegmentDecoder {
     const int t = tid, pos = t >> 1;
     const int mx = mx0 - 1 + pos;
     if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) return;
-    const int* w = wtb() + t * 8;
+    const ldsi* w = wtb() + t * 8;
     int y[8];
     idct8_raw(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias, y);
 #pragma unroll
     for (int i = 0; i < 8; ++i) y[i] >>= kPass2Shift;
-    uint32_t* row = cring(t & 1) + ring_row(below ? 8 * r1 : 8 * r0 - 1) * CWD;
+    lds32* row = cring(t & 1) + (below ? below_row() : CROWS - 1) * CWD;
     row[2 * pos] = pack4(y[0], y[1], y[2], y[3]);
     row[2 * pos + 1] = pack4(y[4], y[5], y[6], y[7]);
-    uint8_t* row8 = reinterpret_cast<uint8_t*>(row);
+    lds8* row8 = reinterpret_cast<lds8*>(row);
     // the strip starts at the image's left edge: x = -1 repeats x = 0
     if (mx0 == 0 && mx == 0) row8[7] = static_cast<uint8_t>(clamp255i(y[0]));
     // the true right chroma edge lies in this strip: x = cw repeats x = cw - 1
@@ -278,17 +324,18 @@ struct SegmentDecoder {
   __device__ void read_stage(int k, Held& h) const {
     if (tid < N_MAIN) {
       const int j = tid;
-      const uint8_t* blk = stage() + j * 128;
+      const lds8* blk = stage() + j * 128;
 #pragma unroll
-      for (int c = 0; c < 8; ++c) h.set(c, *reinterpret_cast<const v4i*>(blk + (((c + j) & 7) << 4)));
+      for (int c = 0; c < 8; ++c)
+        h.set(c, *reinterpret_cast<const __attribute__((address_space(3))) v4i*>(blk + (((c + j) & 7) << 4)));
     } else if constexpr (HALO_X) {
       if (tid >= C::SIDE_LANE0 && tid < C::P1_LANES) {
         const int t = (tid - C::SIDE_LANE0) >> 3, u = tid & 7;
         const int j = N_MAIN + t;
-        const uint8_t* blk = stage() + j * 128 + 2 * u;
+        const lds8* blk = stage() + j * 128 + 2 * u;
         int x[8];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) x[v] = *reinterpret_cast<const int16_t*>(blk + (((v + j) & 7) << 4));
+        for (int v = 0; v < 8; ++v) x[v] = *reinterpret_cast<const lds16*>(blk + (((v + j) & 7) << 4));
         h.r0 = v4i{x[0], x[1], x[2], x[3]};
         h.r1 = v4i{x[4], x[5], x[6], x[7]};
       }
@@ -297,7 +344,7 @@ struct SegmentDecoder {
   }
 
   __device__ void phase1(int k, const Held& h) const {
-    const int my0 = sub_r0(k), nmy = sub_rows(k);
+    const int nmy = sub_rows(k);
     if (tid < N_MAIN) {
       const int j = tid;
       const int b = j / SM;
@@ -310,14 +357,14 @@ struct SegmentDecoder {
       idct_block_regs(rows, qtab(comp), o);
       if (comp == 0) {
         const int by = b / HF, bx = b - (b / HF) * HF;
-        uint32_t* dst = ybuf(k) + (lmy * 8 * VF + by * 8) * YWD + lmx * 2 * HF + bx * 2;
+        lds32* dst = yrow(ybase(k), lmy * 8 * VF + by * 8) + lmx * 2 * HF + bx * 2;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           dst[r * YWD] = o[2 * r];
           dst[r * YWD + 1] = o[2 * r + 1];
         }
       } else {
-        uint32_t* dst = cring(comp - 1) + ring_row(8 * (my0 + lmy)) * CWD + lmx * 2 + 2;
+        lds32* dst = cring(comp - 1) + (cbase(k) + 8 * lmy) * CWD + lmx * 2 + 2;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
           dst[r * CWD] = o[2 * r];
@@ -330,7 +377,7 @@ struct SegmentDecoder {
         const int pos = t >> 2;
         const int mx = ((t >> 1) & 1) ? mx0 + nmx : mx0 - 1;
         if (pos >= nmy || mx < 0 || mx >= im.mcus_x) return;
-        const uint16_t* q = reinterpret_cast<const uint16_t*>(qtab(1 + (t & 1))) + u;
+        const ldsu16* q = reinterpret_cast<const ldsu16*>(qtab(1 + (t & 1))) + u;
         int x[8] = {h.r0.x, h.r0.y, h.r0.z, h.r0.w, h.r1.x, h.r1.y, h.r1.z, h.r1.w};
 #pragma unroll
         for (int v = 0; v < 8; ++v) x[v] *= static_cast<int>(q[8 * v]);
@@ -346,7 +393,7 @@ struct SegmentDecoder {
   // blocks (one lane per sample row, one output each) and replicate samples
   // beyond the true left/right chroma edges into the ring.
   __device__ void phase1_finish(int k) const {
-    const int my0 = sub_r0(k), nmy = sub_rows(k);
+    const int nmy = sub_rows(k);
     if constexpr (HALO_X) {
       for (int s = tid; s < 8 * N_SIDE; s += NT) {
         const int t = s >> 3, i = s & 7;
@@ -354,10 +401,10 @@ struct SegmentDecoder {
         const bool right = (t >> 1) & 1;
         const int mx = right ? mx0 + nmx : mx0 - 1;
         if (pos >= nmy || mx < 0 || mx >= im.mcus_x) continue;
-        const int* w = wside() + t * 64 + i * 8;
+        const ldsi* w = wside() + t * 64 + i * 8;
         const int v = right ? idct8_edge_raw<false>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias)
                             : idct8_edge_raw<true>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias);
-        uint8_t* row8 = reinterpret_cast<uint8_t*>(cring(t & 1) + ring_row(8 * (my0 + pos) + i) * CWD);
+        lds8* row8 = reinterpret_cast<lds8*>(cring(t & 1) + (cbase(k) + 8 * pos + i) * CWD);
         row8[right ? nmx * 8 + 8 : 7] = static_cast<uint8_t>(clamp255i(v >> kPass2Shift));
       }
       const int cw = im.chroma_w;
@@ -370,31 +417,10 @@ struct SegmentDecoder {
           const bool is_right = (s >> 1) >= rows;
           const int rr = (s >> 1) - (is_right ? rows : 0);
           if (is_right ? !right_edge : !left_edge) continue;
-          uint8_t* row8 = reinterpret_cast<uint8_t*>(cring(c) + ring_row(8 * my0 + rr) * CWD);
+          lds8* row8 = reinterpret_cast<lds8*>(cring(c) + (cbase(k) + rr) * CWD);
           if (is_right) row8[cw - gcx0 + 8] = row8[cw - 1 - gcx0 + 8];
           else row8[7] = row8[8];
         }
-      }
-    }
-  }
-
-  // Rows beyond the true top/bottom chroma edge of sub-tile k (4:2:0 fancy):
-  // copy the edge row, margins included.  Runs one step after phase1_finish.
-  __device__ void vertical_edges(int k) const {
-    if constexpr (HALO_Y) {
-      const int gy0 = 8 * sub_r0(k), rows = 8 * sub_rows(k);
-      const int ch = im.chroma_h;
-      const bool top = gy0 == 0;
-      const bool bottom = ch - 1 < gy0 + rows;
-      if (!top && !bottom) return;
-      for (int s = tid; s < 4 * CWD; s += NT) {
-        const int c = s & 1;
-        const bool is_bottom = (s >> 1) >= CWD;
-        const int d = (s >> 1) - (is_bottom ? CWD : 0);
-        if (is_bottom ? !bottom : !top) continue;
-        uint32_t* ring = cring(c);
-        if (is_bottom) ring[ring_row(ch) * CWD + d] = ring[ring_row(ch - 1) * CWD + d];
-        else ring[ring_row(-1) * CWD + d] = ring[ring_row(0) * CWD + d];
       }
     }
   }
@@ -405,7 +431,7 @@ struct SegmentDecoder {
 
   // Chroma samples c0..c5 around the 4 samples at p[0] (c0 = the one
   // before, c5 = the one after) as (c0, c1), (c2, c3), (c4, c5).
-  __device__ static void chroma_pairs(const uint32_t* p, u16x2 v[3]) {
+  __device__ static void chroma_pairs(const lds32* p, u16x2 v[3]) {
     const uint32_t l = p[-1], m = p[0], r = p[1];
     v[0] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(m, l, 0x0C040C03u));
     v[1] = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(m, m, 0x0C020C01u));
@@ -430,14 +456,39 @@ struct SegmentDecoder {
     o[4] = e23.x; o[5] = o23.x; o[6] = e23.y; o[7] = o23.y;
   }
 
-  // ---- phase 2 of sub-tile k: upsample + colour + store ----
+  // ---- phase 2: upsample + colour + store ----
+  // Uniform facts about one sub-tile that phase 2 needs.
+  struct SubInfo {
+    uint8_t* rgb;  // output pixel of its first chroma row and the strip's first column
+    int gcy0;      // global chroma row of its first row
+    int yb, cb;    // luma and chroma ring bases
+    int rows;      // chroma rows present
+  };
+  __device__ SubInfo sub_info(int k) const {
+    const int gcy0 = 8 * sub_r0(k);
+    return {im.rgb + static_cast<size_t>(gcy0 * VF) * im.pitch + static_cast<size_t>(gcx0 * HF) * 3, gcy0,
+            ybase(k), cbase(k), 8 * sub_rows(k)};
+  }
+
+  // The same values as opaque scalars, so that a per-lane choice between
+  // two sub-tiles selects finished values (the compiler would otherwise fold
+  // the choice into the arithmetic and redo it per lane).
+  __device__ static int opaque(int v) {
+    v = __builtin_amdgcn_readfirstlane(v);
+    asm volatile("" : "+s"(v));
+    return v;
+  }
+  __device__ static SubInfo uniform(const SubInfo& si) {
+    const uint64_t p = reinterpret_cast<uint64_t>(si.rgb);
+    const uint32_t lo = static_cast<uint32_t>(opaque(static_cast<int>(p)));
+    const uint32_t hi = static_cast<uint32_t>(opaque(static_cast<int>(p >> 32)));
+    return {reinterpret_cast<uint8_t*>(static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32)), opaque(si.gcy0),
+            opaque(si.yb), opaque(si.cb), opaque(si.rows)};
+  }
+
+  // All chroma rows of sub-tile k.
   __device__ void phase2(int k) const {
-    const int my0 = sub_r0(k), nmy = sub_rows(k);
-    const int gcy0 = 8 * my0;
-    const int W = im.width, H = im.height;
-    const uint32_t* ys = ybuf(k);
-    uint8_t* const sub_rgb = im.rgb + static_cast<size_t>(gcy0 * VF) * im.pitch + static_cast<size_t>(gcx0 * HF) * 3;
-    const int pitch24 = static_cast<int>(im.pitch);
+    const SubInfo si = sub_info(k);
     // For fancy 4:2:2 the lanes that transform a block in phase 1 take one
     // unit each and the neighbour-column lanes, which have little phase-1
     // work, share the rest; otherwise all lanes share evenly.
@@ -447,17 +498,56 @@ struct SegmentDecoder {
     for (int uidx = tid; uidx < C::UNITS; uidx += ustep) {
       const int cr_l = uidx / C::UX;
       const int g = uidx - cr_l * C::UX;
-      if (g >= 2 * nmx || cr_l >= 8 * nmy) continue;
+      if (g >= 2 * nmx || cr_l >= si.rows) continue;
+      unit(si, cr_l, g);
+    }
+  }
+
+  // 4:2:0 fancy, step k: every chroma row of sub-tile k-1 but its last, and
+  // the last row of sub-tile k-2, whose row below is the first of k-1.
+  __device__ void phase2_split(int k) const {
+    const bool has_a = k >= 1 && k <= K;
+    const bool has_b = k >= 2 && k <= K + 1;
+    if (!has_a && !has_b) return;
+    const SubInfo sa = uniform(sub_info(has_a ? k - 1 : 0)), sb = uniform(sub_info(has_b ? k - 2 : 0));
+    constexpr int V_MAIN = (CR - 1) * C::UX;
+    for (int v = tid; v < C::UNITS; v += NT) {
+      const bool tail = v >= V_MAIN;
+      const int cr_a = v / C::UX;
+      const int g = v - cr_a * C::UX;
+      if (g >= 2 * nmx || (tail ? !has_b : (!has_a || cr_a >= sa.rows - 1))) continue;
+      SubInfo si;
+      si.rgb = tail ? sb.rgb : sa.rgb;
+      si.gcy0 = tail ? sb.gcy0 : sa.gcy0;
+      si.yb = tail ? sb.yb : sa.yb;
+      si.cb = tail ? sb.cb : sa.cb;
+      unit(si, tail ? sb.rows - 1 : cr_a, g);
+    }
+  }
+
+  // One unit: chroma samples 4g..4g+3 of row cr_l of a sub-tile's strip,
+  // i.e. 4*HF x VF pixels.
+  __device__ void unit(const SubInfo& si, const int cr_l, const int g) const {
+    const int W = im.width, H = im.height;
+    const int pitch24 = static_cast<int>(im.pitch);
+    {
       const int px0 = (gcx0 + 4 * g) * HF;
-      const int py0 = (gcy0 + cr_l) * VF;
-      if (px0 >= W || py0 >= H) continue;
+      const int py0 = (si.gcy0 + cr_l) * VF;
+      if (px0 >= W || py0 >= H) return;
 
       int xb[VF][4 * HF], xr[VF][4 * HF];  // chroma - 128 per output pixel
-      const int rc = ring_row(gcy0 + cr_l);
+      const int rc = si.cb + cr_l;
+      // the rows above and below, repeated at the true top and bottom
+      // chroma edges
+      const int gy = si.gcy0 + cr_l;
+      const int ru = gy == 0 ? rc : ring_prev(rc);
+      const int rd = gy == im.chroma_h - 1 ? rc : ring_next(rc);
+      (void)ru;
+      (void)rd;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const uint32_t* ring = cring(c);
-        const uint32_t* plane = ring + rc * CWD + g + 2;
+        const lds32* ring = cring(c);
+        const lds32* plane = ring + (mul24(rc, CWD) + g + 2);
         int out[VF][4 * HF];
         if constexpr (!FANCY || HF == 1) {
           const uint32_t w = plane[0];
@@ -490,8 +580,8 @@ struct SegmentDecoder {
             // below 2^12, so the halves never carry into each other)
             u16x2 pm[3], pu[3], pd[3];
             chroma_pairs(plane, pm);
-            chroma_pairs(ring + ring_row(gcy0 + cr_l - 1) * CWD + g + 2, pu);
-            chroma_pairs(ring + ring_row(gcy0 + cr_l + 1) * CWD + g + 2, pd);
+            chroma_pairs(ring + (mul24(ru, CWD) + g + 2), pu);
+            chroma_pairs(ring + (mul24(rd, CWD) + g + 2), pd);
             const u16x2 three = {3, 3};
             u16x2 su[3], sd[3];
 #pragma unroll
@@ -517,17 +607,17 @@ struct SegmentDecoder {
       for (int dy = 0; dy < VF; ++dy) {
         const int py = py0 + dy;
         if (py >= H) break;
-        const uint32_t* yrow = ys + (cr_l * VF + dy) * YWD + g * HF;
+        const lds32* ysrc = yrow(si.yb, cr_l * VF + dy) + g * HF;
         uint32_t w[3 * HF];
 #pragma unroll
         for (int kk = 0; kk < HF; ++kk) {
-          const uint32_t ydw = yrow[kk];
+          const uint32_t ydw = ysrc[kk];
           RGBWide px[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) px[i] = ycc_wide(y16_of(ydw, i), xb[dy][4 * kk + i], xr[dy][4 * kk + i]);
           pack_rgb4(px, w + 3 * kk);
         }
-        uint8_t* row = sub_rgb + (mul24(cr_l * VF + dy, pitch24) + 12 * HF * g);
+        uint8_t* row = si.rgb + (mul24(cr_l * VF + dy, pitch24) + 12 * HF * g);
         if (nv == 4 * HF && im.aligned_out) {
           uint32_t* wd = reinterpret_cast<uint32_t*>(row);
           // streaming stores: RGB is written once and never read back here
@@ -577,20 +667,26 @@ struct SegmentDecoder {
       __syncthreads();  // staging of k landed; last step's LDS writes visible
       if constexpr (HALO_Y) {
         if (k == 0) tb_step_b(false);
-        if (k >= 1 && k - 1 < K) vertical_edges(k - 1);
         if (k == K) tb_step_a(true);
-      }
-      if (k < K) read_stage(k, h);
-      __syncthreads();  // staging free for the next sub-tile
-      if (k + 1 < K) dma(k + 1);
-      if constexpr (HALO_Y) {
+        if (k < K) read_stage(k, h);
+        // Phase 2 reads the luma rows that phase 1 of k overwrites in the
+        // ring, so it goes first, in the interval that also frees the
+        // staging buffer; its stores drain while the IDCT runs.
+        phase2_split(k);
+        __syncthreads();  // staging free; phase 2's luma rows read
+        if (k + 1 < K) dma(k + 1);
         if (k + 1 == K) dma_tb(true);  // staging is idle from here on
+      } else {
+        if (k < K) read_stage(k, h);
+        __syncthreads();  // staging free for the next sub-tile
+        if (k + 1 < K) dma(k + 1);
+        // Phase 2 of the previous sub-tile and phase 1 of this one use
+        // disjoint luma buffers and chroma ring rows, so they share one
+        // barrier interval; phase 2 goes first so its stores drain while
+        // the IDCT runs, and lanes without a block of their own take most
+        // of it.
+        if (k >= LAG) phase2(k - LAG);
       }
-      // Phase 2 of an older sub-tile and phase 1 of this one use disjoint
-      // luma buffers and chroma ring rows, so they share one barrier
-      // interval; phase 2 goes first so its stores drain while the IDCT
-      // runs, and lanes without a block of their own take most of it.
-      if (k >= LAG) phase2(k - LAG);
       if (k < K) phase1(k, h);
       __syncthreads();
       if (k < K) phase1_finish(k);
