@@ -44,7 +44,10 @@ __global__ __launch_bounds__(kBatchThreads, 2) void decode_batch(const ImageView
     __syncthreads();  // every lane has read s_next before it is overwritten
     if (it >= n_items) break;
     const BatchItem bi = items[it];
-    const ImageView im = views[bi.img];
+    // a reference into the device table (scalar loads), not a local copy,
+    // which would have to live in scratch memory behind the decoder's
+    // reference
+    const ImageView& im = views[bi.img];
     SegmentRange r;
     r.mx0 = bi.mx0;
     r.r0 = bi.r0;

@@ -34,6 +34,9 @@ typedef __attribute__((address_space(3))) uint32_t lds32;
 typedef __attribute__((address_space(3))) int ldsi;
 typedef __attribute__((address_space(3))) int16_t lds16;
 typedef __attribute__((address_space(3))) uint16_t ldsu16;
+// global-memory pointers for the RGB stores (global, not flat, instructions)
+typedef __attribute__((address_space(1))) uint8_t gbl8;
+typedef __attribute__((address_space(1))) uint32_t gbl32;
 
 constexpr int round64c(int n) { return (n + 63) & ~63; }
 
@@ -211,7 +214,12 @@ struct SegmentDecoder {
     if (tid < 96) {
       const int c = tid >> 5;
       const int sel = c == 0 ? im.qsel0 : (c == 1 ? im.qsel1 : im.qsel2);
-      const uint16_t* q = im.qt + sel * 64 + 2 * (tid & 31);
+      // the lane's offset is formed here each time (kept opaque), so the
+      // compiler does not hold a per-lane pointer across the whole walk
+      int idx = sel * 64 + 2 * (tid & 31);
+      asm volatile("" : "+v"(idx));
+      const __attribute__((address_space(1))) uint16_t* q =
+          (const __attribute__((address_space(1))) uint16_t*)im.qt + idx;
       qtab(c)[tid & 31] = static_cast<uint32_t>(q[0]) | (static_cast<uint32_t>(q[1]) << 16);
     }
   }
@@ -459,14 +467,14 @@ struct SegmentDecoder {
   // ---- phase 2: upsample + colour + store ----
   // Uniform facts about one sub-tile that phase 2 needs.
   struct SubInfo {
-    uint8_t* rgb;  // output pixel of its first chroma row and the strip's first column
+    gbl8* rgb;     // output pixel of its first chroma row and the strip's first column
     int gcy0;      // global chroma row of its first row
     int yb, cb;    // luma and chroma ring bases
     int rows;      // chroma rows present
   };
   __device__ SubInfo sub_info(int k) const {
     const int gcy0 = 8 * sub_r0(k);
-    return {im.rgb + static_cast<size_t>(gcy0 * VF) * im.pitch + static_cast<size_t>(gcx0 * HF) * 3, gcy0,
+    return {(gbl8*)(im.rgb + static_cast<size_t>(gcy0 * VF) * im.pitch + static_cast<size_t>(gcx0 * HF) * 3), gcy0,
             ybase(k), cbase(k), 8 * sub_rows(k)};
   }
 
@@ -482,7 +490,7 @@ struct SegmentDecoder {
     const uint64_t p = reinterpret_cast<uint64_t>(si.rgb);
     const uint32_t lo = static_cast<uint32_t>(opaque(static_cast<int>(p)));
     const uint32_t hi = static_cast<uint32_t>(opaque(static_cast<int>(p >> 32)));
-    return {reinterpret_cast<uint8_t*>(static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32)), opaque(si.gcy0),
+    return {reinterpret_cast<gbl8*>(static_cast<uint64_t>(lo) | (static_cast<uint64_t>(hi) << 32)), opaque(si.gcy0),
             opaque(si.yb), opaque(si.cb), opaque(si.rows)};
   }
 
@@ -617,12 +625,14 @@ struct SegmentDecoder {
           for (int i = 0; i < 4; ++i) px[i] = ycc_wide(y16_of(ydw, i), xb[dy][4 * kk + i], xr[dy][4 * kk + i]);
           pack_rgb4(px, w + 3 * kk);
         }
-        uint8_t* row = si.rgb + (mul24(cr_l * VF + dy, pitch24) + 12 * HF * g);
+        gbl8* row = si.rgb + (mul24(cr_l * VF + dy, pitch24) + 12 * HF * g);
         if (nv == 4 * HF && im.aligned_out) {
-          uint32_t* wd = reinterpret_cast<uint32_t*>(row);
+          gbl32* wd = reinterpret_cast<gbl32*>(row);
           // streaming stores: RGB is written once and never read back here
 #pragma unroll
           for (int kk = 0; kk < 3 * HF; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
+        } else if (nv == 4 * HF) {
+          store_shifted(row, w);
         } else {
           store_ragged(row, w, 3 * nv);
         }
@@ -630,9 +640,36 @@ struct SegmentDecoder {
     }
   }
 
+  // A whole unit's 12*HF bytes at a row address that need not be 4-byte
+  // aligned (a pitch or base that is not a multiple of 4): the bytes are
+  // regrouped into the aligned dwords that cover them (one byte permute
+  // each), the dwords wholly inside the run are stored whole and the two
+  // partial end dwords byte by byte, so no byte outside the run is written.
+  __device__ static void store_shifted(gbl8* row, const uint32_t* w) {
+    constexpr int ND = 3 * HF;  // data dwords; the aligned cover has ND + 1
+    const int m = static_cast<int>(reinterpret_cast<uintptr_t>(row) & 3u);
+    gbl8* const a = row - m;  // 4-byte aligned
+    // cover dword j holds data bytes 4j - m .. 4j - m + 3: bytes 4 - m ..
+    // 7 - m of the pair (w[j], w[j - 1])
+    const uint32_t sel = 0x07060504u - static_cast<uint32_t>(m) * 0x01010101u;
+    uint32_t d[ND + 1];
+#pragma unroll
+    for (int j = 0; j <= ND; ++j)
+      d[j] = __builtin_amdgcn_perm(j < ND ? w[j] : 0u, j > 0 ? w[j - 1] : 0u, sel);
+    gbl32* ad = reinterpret_cast<gbl32*>(a);
+#pragma unroll
+    for (int j = 1; j < ND; ++j) __builtin_nontemporal_store(d[j], &ad[j]);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (b >= m) a[b] = static_cast<uint8_t>(d[0] >> (8 * b));
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      if (b < m) a[4 * ND + b] = static_cast<uint8_t>(d[ND] >> (8 * b));
+  }
+
   // Ragged right edge: byte stores of the first nbytes bytes of w (constant
   // register indices; the run is at most 12*HF bytes).
-  __device__ static void store_ragged(uint8_t* row, const uint32_t* w, int nbytes) {
+  __device__ static void store_ragged(gbl8* row, const uint32_t* w, int nbytes) {
 #pragma unroll
     for (int kk = 0; kk < 3 * HF; ++kk)
 #pragma unroll
