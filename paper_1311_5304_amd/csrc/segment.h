@@ -10,17 +10,18 @@
 //   phase 1  dequantise + 8x8 islow IDCT (paper Sec. 4.1), one block per
 //            lane, both passes in registers; samples go to an LDS luma
 //            buffer and an LDS chroma ring.  The neighbour chroma blocks the
-//            fancy filter needs (Sec. 4.2) are split 8 lanes per block and only
-//            the column the filter reads is formed;
-//   phase 2  (LAG sub-tiles later) upsampling + YCbCr->RGB (Sec. 4.3) + RGB8
-//            stores (Fig. 5).
-// For the 4:2:0 fancy filter a sub-tile's bottom chroma row needs the first
-// chroma row of the next sub-tile, so phase 2 runs two sub-tiles behind
-// phase 1 and the rows above and below a sub-tile come from the ring instead
-// of being decoded twice; only the rows above and below the whole segment are
-// decoded as neighbour blocks.  Phase 2 of an older sub-tile is issued before
-// phase 1 of the current one, so its stores drain while the IDCT runs, and the
-// next sub-tile's DMA is in flight during phase 1.
+//            fancy filter needs (Sec. 4.2) are split 8 lanes per block, and
+//            only the one column the filter reads is formed, summed across
+//            the block's lanes in the wave;
+//   phase 2  upsampling + YCbCr->RGB (Sec. 4.3) + RGB8 stores (Fig. 5).
+// For the 4:2:0 fancy filter a sub-tile's last chroma row needs the first
+// chroma row of the next sub-tile: phase 2 of a sub-tile runs one step after
+// its phase 1 and its last row one step later still, so the rows above and
+// below a sub-tile come from the ring instead of being decoded twice; only
+// the rows above and below the whole segment are decoded as neighbour
+// blocks.  Phase 2 is issued before phase 1 of the current sub-tile, so its
+// stores drain while the IDCT runs, and the next sub-tile's DMA is in flight
+// during phase 1.  Each step has two barriers.
 #pragma once
 
 #include "decode_kernel.h"
@@ -99,8 +100,7 @@ struct SegCfg {
   static constexpr int OFF_Y = OFF_STAGE + N_SLOT * 128;
   static constexpr int OFF_C = OFF_Y + Y_BYTES;
   static constexpr int OFF_Q = OFF_C + 2 * CROWS * CWD * 4;
-  static constexpr int OFF_WS = OFF_Q + 3 * 128;
-  static constexpr int OFF_WT = OFF_WS + (N_SIDE > 0 ? N_SIDE * 256 : 16);
+  static constexpr int OFF_WT = OFF_Q + 3 * 128;
   static constexpr int LDS_BYTES = OFF_WT + (N_TB > 0 ? N_TB * 32 : 16);
   // Waves per SIMD that the LDS footprint allows (160 KB per CU, at most 3
   // asked of the register allocator).
@@ -138,7 +138,6 @@ struct SegmentDecoder {
   __device__ lds32* luma() const { return reinterpret_cast<lds32*>(lds + C::OFF_Y); }
   __device__ lds32* cring(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_C) + c * (CROWS * CWD); }
   __device__ lds32* qtab(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q) + c * 32; }
-  __device__ ldsi* wside() const { return reinterpret_cast<ldsi*>(lds + C::OFF_WS); }
   __device__ ldsi* wtb() const { return reinterpret_cast<ldsi*>(lds + C::OFF_WT); }
 
   // Luma row r (0 <= r < YROWS) of sub-tile k lives in row ybase(k) + r of
@@ -378,6 +377,27 @@ struct SegmentDecoder {
           dst[r * CWD] = o[2 * r];
           dst[r * CWD + 1] = o[2 * r + 1];
         }
+        if constexpr (HALO_X) {
+          // Samples beyond the true left/right chroma edge repeat the edge
+          // sample.  The lane that owns the edge sample writes the copy (no
+          // other lane writes that byte: at a true edge there is no
+          // neighbour MCU beyond it).
+          lds8* row8 = reinterpret_cast<lds8*>(dst - lmx * 2 - 2);
+          if (gcx0 == 0 && lmx == 0) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) row8[r * CWD * 4 + 7] = static_cast<uint8_t>(o[2 * r]);
+          }
+          const int e = im.chroma_w - 1 - gcx0;  // the last sample, relative to the strip
+          if (e < 8 * nmx && (e >> 3) == lmx) {
+            // the dword holding sample e & 7, chosen by a mask (not an
+            // index, which would put o[] in scratch memory)
+            const uint32_t hi = 0u - static_cast<uint32_t>((e >> 2) & 1);
+            const int sh = 8 * (e & 3);
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+              row8[r * CWD * 4 + e + 9] = static_cast<uint8_t>((o[2 * r] ^ ((o[2 * r] ^ o[2 * r + 1]) & hi)) >> sh);
+          }
+        }
       }
     } else if constexpr (HALO_X) {
       if (tid >= C::SIDE_LANE0 && tid < C::P1_LANES) {
@@ -391,46 +411,44 @@ struct SegmentDecoder {
         for (int v = 0; v < 8; ++v) x[v] *= static_cast<int>(q[8 * v]);
         int y[8];
         idct8_raw(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias, y);
+        // The row pass at one output column (0 of the block right of the
+        // strip, 7 of the one left of it) is the integer linear form
+        // sum_u M[c][u] w[i][u] that the flowgraph computes before its
+        // descale, with M[7][u] = (-1)^u M[0][u].  Each lane forms its
+        // column's terms; a butterfly over the block's 8 lanes sums them,
+        // and lane u keeps sample row u.
+        const bool right = (t >> 1) & 1;
+        const int wgt = (right || !(u & 1)) ? row0_weight(u) : -row0_weight(u);
+        int sum[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) wside()[t * 64 + i * 8 + u] = y[i] >> kPass1Shift;
+        for (int i = 0; i < 8; ++i) sum[i] = sum8_lanes(mul24(y[i] >> kPass1Shift, wgt));
+        int v = sum[0];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) v = u == i ? sum[i] : v;
+        lds8* row8 = reinterpret_cast<lds8*>(cring(t & 1) + (cbase(k) + 8 * pos + u) * CWD);
+        row8[right ? nmx * 8 + 8 : 7] = static_cast<uint8_t>(clamp255i((v + kPass2Bias) >> kPass2Shift));
       }
     }
   }
 
-  // After phase 1 of k (and a barrier): finish the left/right neighbour
-  // blocks (one lane per sample row, one output each) and replicate samples
-  // beyond the true left/right chroma edges into the ring.
-  __device__ void phase1_finish(int k) const {
-    const int nmy = sub_rows(k);
-    if constexpr (HALO_X) {
-      for (int s = tid; s < 8 * N_SIDE; s += NT) {
-        const int t = s >> 3, i = s & 7;
-        const int pos = t >> 2;
-        const bool right = (t >> 1) & 1;
-        const int mx = right ? mx0 + nmx : mx0 - 1;
-        if (pos >= nmy || mx < 0 || mx >= im.mcus_x) continue;
-        const ldsi* w = wside() + t * 64 + i * 8;
-        const int v = right ? idct8_edge_raw<false>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias)
-                            : idct8_edge_raw<true>(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias);
-        lds8* row8 = reinterpret_cast<lds8*>(cring(t & 1) + (cbase(k) + 8 * pos + i) * CWD);
-        row8[right ? nmx * 8 + 8 : 7] = static_cast<uint8_t>(clamp255i(v >> kPass2Shift));
-      }
-      const int cw = im.chroma_w;
-      const bool left_edge = gcx0 == 0;
-      const bool right_edge = cw - 1 < gcx0 + 8 * nmx;
-      if (left_edge || right_edge) {
-        const int rows = 8 * nmy;
-        for (int s = tid; s < 4 * rows; s += NT) {
-          const int c = s & 1;
-          const bool is_right = (s >> 1) >= rows;
-          const int rr = (s >> 1) - (is_right ? rows : 0);
-          if (is_right ? !right_edge : !left_edge) continue;
-          lds8* row8 = reinterpret_cast<lds8*>(cring(c) + (cbase(k) + rr) * CWD);
-          if (is_right) row8[cw - gcx0 + 8] = row8[cw - 1 - gcx0 + 8];
-          else row8[7] = row8[8];
-        }
-      }
-    }
+  // Weight of input u in output 0 of the flowgraph (its first row):
+  // 8192, 11363, 10703, 9633, 8192, 6437, 4433, 2260.
+  __device__ static int row0_weight(int u) {
+    const int w01 = u & 1 ? kO[0][0] : 1 << kConstBits;
+    const int w23 = u & 1 ? kO[0][1] : kE2a;
+    const int w45 = u & 1 ? kO[0][2] : 1 << kConstBits;
+    const int w67 = u & 1 ? kO[0][3] : kE6a;
+    return u < 4 ? (u < 2 ? w01 : w23) : (u < 6 ? w45 : w67);
+  }
+
+  // Sum over the 8 lanes of an aligned 8-lane group, in every lane of it
+  // (DPP: swap neighbours, swap pairs, mirror the halves of the group).
+  // Integer adds wrap, so the sum is exact whenever the true sum fits 32 bits.
+  __device__ static int sum8_lanes(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    x += __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    x += __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    return x;
   }
 
   // ---- phase 2 helpers: fancy h2v2 on packed 16-bit pairs ----
@@ -711,6 +729,7 @@ struct SegmentDecoder {
         // staging buffer; its stores drain while the IDCT runs.
         phase2_split(k);
         __syncthreads();  // staging free; phase 2's luma rows read
+        if (k == K) tb_step_b(true);   // the row below: phase 2 of the next step reads it
         if (k + 1 < K) dma(k + 1);
         if (k + 1 == K) dma_tb(true);  // staging is idle from here on
       } else {
@@ -724,12 +743,10 @@ struct SegmentDecoder {
         // of it.
         if (k >= LAG) phase2(k - LAG);
       }
+      // Phase 1 also finishes the neighbour-column blocks and the edge
+      // copies in place, so its LDS writes only need to be visible at the
+      // next step's first barrier.
       if (k < K) phase1(k, h);
-      __syncthreads();
-      if (k < K) phase1_finish(k);
-      if constexpr (HALO_Y) {
-        if (k == K) tb_step_b(true);
-      }
     }
   }
 };

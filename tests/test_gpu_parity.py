@@ -107,24 +107,30 @@ def test_band_decode_equals_whole_decode(M, ctx, samp):
         assert np.all(got[:y0] == 7) and np.all(got[y1:] == 7), "band wrote outside its rows"
 
 
-def test_unaligned_output_pitch_and_base(M, ctx):
-    rgb = images.texture_rgb(77, 45, 5, sigma=12)
-    frame, coef, qt = encode.encode_rgb(rgb, "420", 80)
-    exp = oracle.decode(frame, coef, qt, "fancy")
+@pytest.mark.parametrize("samp,mode", [("420", "fancy"), ("420", "simple"), ("422", "fancy"), ("444", "simple")])
+def test_unaligned_output_pitch_and_base(M, ctx, samp, mode):
+    """Every row start alignment (pitch and base offsets 0..3 mod 4) gives
+    the oracle's bytes and leaves the padding and the bytes before the image
+    untouched; widths span several strips and end in a ragged MCU."""
+    rgb = images.texture_rgb(301, 45, 5, sigma=12)
+    frame, coef, qt = encode.encode_rgb(rgb, samp, 80)
+    exp = oracle.decode(frame, coef, qt, mode)
     c, q = to_dev(coef, qt)
     w, h = frame["width"], frame["height"]
-    for pitch, base in ((3 * w + 1, 0), (3 * w + 4, 1), (3 * w + 5, 3)):
-        say(f"pitch {pitch} base offset {base}")
+    for pitch, base in ((3 * w + 1, 0), (3 * w + 2, 2), (3 * w + 4, 1), (3 * w + 5, 3), (3 * w + 3, 0)):
+        say(f"{samp} {mode} pitch {pitch} base offset {base}")
         buf = torch.full((h * pitch + base + 16,), 9, dtype=torch.uint8, device="cuda")
-        M.mjd_decode(ctx, frame, c, q, M.MJD_UPSAMPLE_FANCY, buf.data_ptr() + base, pitch, 0,
+        M.mjd_decode(ctx, frame, c, q, M.UPSAMPLE[mode], buf.data_ptr() + base, pitch, 0,
                      oracle.geometry(frame)["mcus_y"])
         torch.cuda.synchronize()
         host = buf.cpu().numpy()
+        assert np.all(host[:base] == 9), "wrote before the image"
         for y in range(h):
             row = host[base + y * pitch: base + y * pitch + 3 * w].reshape(w, 3)
             assert np.array_equal(row, exp[y]), f"row {y}"
             pad = host[base + y * pitch + 3 * w: base + (y + 1) * pitch] if y < h - 1 else []
             assert np.all(np.asarray(pad) == 9), "wrote into row padding"
+        assert np.all(host[base + (h - 1) * pitch + 3 * w:] == 9), "wrote past the image"
 
 
 def test_large_420_fancy_full_image_bit_exact(M, ctx):
