@@ -11,7 +11,7 @@
 namespace mjd {
 namespace host {
 
-constexpr int kLookBits = 9;  // look-ahead window of the table decoder
+constexpr int kLookBits = 10;  // look-ahead window of the table decoder
 
 struct HuffTable {
   uint16_t lut[1 << kLookBits];   // (length << 8) | symbol for codes of <= kLookBits bits, else 0
