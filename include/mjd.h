@@ -253,6 +253,60 @@ int mjd_entropy_decode(const uint8_t* h_jpg, size_t len, const mjd_scan* scan, c
                        int16_t* h_coef, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads);
 
 /* ---------------------------------------------------------------------
+ * GPU entropy decoding of many baseline scans.  Restart intervals restart
+ * the bit stream and the DC predictions (ITU-T T.81 restart markers), so
+ * each one decodes on its own: one GPU lane decodes one interval.  This
+ * moves the part the paper leaves on the CPU (Sec. 1: variable-length code
+ * words) onto the device whenever a stream has restart markers.  A stream
+ * without them is one interval and decodes on one lane (correct but slow).
+ * ------------------------------------------------------------------- */
+
+/* One scan to decode on the device. */
+typedef struct mjd_entropy_job {
+  const mjd_scan* scan;      /* host: from mjd_parse; read at create time */
+  const uint64_t* h_offsets; /* host: from mjd_restart_index (n_intervals + 1
+                                entries); read at create time */
+  const uint8_t* d_jpg;      /* device: the whole stream, bytes [0, len);
+                                4-byte aligned */
+  uint64_t len;              /* bytes of the stream at d_jpg */
+  int16_t* d_coef;           /* device, 16-byte aligned: n_blocks * 64 int16
+                                in the MCU order mjd_decode reads (natural
+                                order inside a block, DC prediction applied);
+                                every block is written */
+} mjd_entropy_job;
+
+/* Planned GPU entropy decoding of many scans, owned by the library until
+ * mjd_entropy_batch_destroy. */
+typedef struct mjd_entropy_batch mjd_entropy_batch;
+
+/* Check the jobs and plan them: build each scan's Huffman tables in device
+ * form, list the restart intervals (byte ranges from h_offsets, which must
+ * be increasing and inside [0, len)) and upload the tables (synchronous).
+ * An invalid job fails the whole call, naming the job.  The device buffers
+ * are only recorded, not accessed. */
+int mjd_entropy_batch_create(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n, mjd_entropy_batch** out);
+
+/* Enqueue the decoding of every job on `stream`: one persistent kernel whose
+ * workgroups take up to 256 intervals of one job at a time.  Launches of one
+ * batch must be serialised (one stream).  Reads only [d_jpg, d_jpg + len)
+ * of each job and writes only its coefficient blocks. */
+int mjd_entropy_batch_launch(mjd_entropy_batch* batch, void* stream);
+
+/* Synchronise the device and check the last launch: MJD_OK, or
+ * MJD_ECORRUPT naming the first job and restart interval that held an
+ * invalid Huffman code, a coefficient run past the end of a block, or too
+ * few bits for its MCUs (*bad_job receives the job, else -1; may be NULL).
+ * The blocks of a corrupt interval are then unspecified. */
+int mjd_entropy_batch_status(mjd_entropy_batch* batch, int64_t* bad_job);
+
+/* Restart intervals in the batch, workgroups per launch and stream bytes. */
+int mjd_entropy_batch_info(const mjd_entropy_batch* batch, uint32_t* intervals, uint32_t* workgroups,
+                           uint64_t* bytes);
+
+/* Synchronise the device and free the batch's tables. */
+void mjd_entropy_batch_destroy(mjd_entropy_batch* batch);
+
+/* ---------------------------------------------------------------------
  * Pipelined end-to-end decode: bitstreams in host memory -> RGB8 in host
  * memory.  The paper's pipelined GPU mode (Sec. 4.5, Fig. 6) cuts an image
  * into horizontal chunks so that the entropy decoding of chunk i+1 on the

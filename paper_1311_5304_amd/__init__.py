@@ -5,10 +5,12 @@ chroma upsampling -> YCbCr->RGB as one fused HIP kernel behind a C ABI
 from __future__ import annotations
 
 from ._binding import (MJD_SERVE_CONTINUOUS, MJD_SERVE_SYNC, MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE,  # noqa: F401
-                       Batch, Context, MjdError, Pipeline, Server,
+                       Batch, Context, EntropyBatch, MjdError, Pipeline, Server,
                        mjd_batch_create, mjd_batch_destroy, mjd_batch_launch,
                        mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
-                       mjd_decode, mjd_entropy_decode, mjd_geometry_of, mjd_last_error, mjd_parse,
+                       mjd_decode, mjd_entropy_batch_create, mjd_entropy_batch_destroy,
+                       mjd_entropy_batch_info, mjd_entropy_batch_launch, mjd_entropy_batch_status,
+                       mjd_entropy_decode, mjd_geometry_of, mjd_last_error, mjd_parse,
                        mjd_restart_index, scan_frame)
 
 UPSAMPLE = {"simple": MJD_UPSAMPLE_SIMPLE, "fancy": MJD_UPSAMPLE_FANCY}

@@ -68,6 +68,11 @@ class mjd_scan(ctypes.Structure):
                 ("dc", mjd_huffman * 4), ("ac", mjd_huffman * 4)]
 
 
+class mjd_entropy_job(ctypes.Structure):
+    _fields_ = [("scan", ctypes.POINTER(mjd_scan)), ("h_offsets", ctypes.c_void_p), ("d_jpg", ctypes.c_void_p),
+                ("len", ctypes.c_uint64), ("d_coef", ctypes.c_void_p)]
+
+
 class mjd_pipeline_config(ctypes.Structure):
     _fields_ = [("n_threads", ctypes.c_uint32), ("n_slots", ctypes.c_uint32), ("band_mcu_rows", ctypes.c_uint32),
                 ("upsample", ctypes.c_uint32), ("max_blocks", ctypes.c_uint64), ("max_pixels", ctypes.c_uint64)]
@@ -136,6 +141,17 @@ def lib() -> ctypes.CDLL:
         L.mjd_restart_index.restype = i32
         L.mjd_entropy_decode.argtypes = [vp, sz, ctypes.POINTER(mjd_scan), vp, vp, u32, u32, i32]
         L.mjd_entropy_decode.restype = i32
+        L.mjd_entropy_batch_create.argtypes = [vp, ctypes.POINTER(mjd_entropy_job), sz, ctypes.POINTER(vp)]
+        L.mjd_entropy_batch_create.restype = i32
+        L.mjd_entropy_batch_launch.argtypes = [vp, vp]
+        L.mjd_entropy_batch_launch.restype = i32
+        L.mjd_entropy_batch_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        L.mjd_entropy_batch_status.restype = i32
+        L.mjd_entropy_batch_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                             ctypes.POINTER(ctypes.c_uint64)]
+        L.mjd_entropy_batch_info.restype = i32
+        L.mjd_entropy_batch_destroy.argtypes = [vp]
+        L.mjd_entropy_batch_destroy.restype = None
         L.mjd_pipeline_create.argtypes = [vp, ctypes.POINTER(mjd_pipeline_config), ctypes.POINTER(vp)]
         L.mjd_pipeline_create.restype = i32
         L.mjd_pipeline_run.argtypes = [vp, sz, vp, vp, vp, vp, u32, ctypes.POINTER(mjd_pipeline_stats)]
@@ -346,6 +362,77 @@ def mjd_entropy_decode(jpg, scan: mjd_scan, offsets, coef, row0: int, row1: int,
     a, n = _bytes_view(jpg)
     _check(lib().mjd_entropy_decode(_ptr(a), n, ctypes.byref(scan), _ptr(offsets), _ptr(coef),
                                     int(row0), int(row1), int(n_threads)))
+
+
+class EntropyBatch:
+    """Owns an mjd_entropy_batch*: Huffman decoding of many scans on the GPU,
+    one lane per restart interval."""
+
+    def __init__(self, ctx: Context, jobs):
+        """jobs: sequence of (scan, offsets, d_jpg, length, d_coef): the mjd_scan
+        and restart index from mjd_parse / mjd_restart_index, the stream in
+        device memory (tensor or address) with its byte length, and the
+        device coefficient buffer of n_blocks*64 int16."""
+        arr = (mjd_entropy_job * len(jobs))()
+        for i, (scan, off, jpg, n, coef) in enumerate(jobs):
+            arr[i].scan = ctypes.pointer(scan)
+            arr[i].h_offsets = _ptr(off)
+            arr[i].d_jpg = _ptr(jpg)
+            arr[i].len = int(n)
+            arr[i].d_coef = _ptr(coef)
+        p = ctypes.c_void_p()
+        _check(lib().mjd_entropy_batch_create(ctx.handle, arr, len(jobs), ctypes.byref(p)))
+        self.handle = p
+        self._keep = jobs  # the device buffers must outlive the batch
+
+    def info(self) -> dict:
+        iv, wg, nb = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        _check(lib().mjd_entropy_batch_info(self.handle, ctypes.byref(iv), ctypes.byref(wg), ctypes.byref(nb)))
+        return {"intervals": iv.value, "workgroups": wg.value, "bytes": nb.value}
+
+    def launch(self, stream=None):
+        _check(lib().mjd_entropy_batch_launch(self.handle, _stream(stream)))
+
+    def status(self) -> int:
+        """Synchronise; raise MjdError (MJD_ECORRUPT) for corrupt data, else -1."""
+        bad = ctypes.c_int64(-1)
+        rc = lib().mjd_entropy_batch_status(self.handle, ctypes.byref(bad))
+        if rc != MJD_OK:
+            err = MjdError(rc, mjd_last_error())
+            err.bad_job = bad.value
+            raise err
+        return bad.value
+
+    def close(self):
+        if self.handle:
+            lib().mjd_entropy_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mjd_entropy_batch_create(ctx: Context, jobs) -> EntropyBatch:
+    return EntropyBatch(ctx, jobs)
+
+
+def mjd_entropy_batch_launch(batch: EntropyBatch, stream=None):
+    batch.launch(stream)
+
+
+def mjd_entropy_batch_status(batch: EntropyBatch) -> int:
+    return batch.status()
+
+
+def mjd_entropy_batch_info(batch: EntropyBatch) -> dict:
+    return batch.info()
+
+
+def mjd_entropy_batch_destroy(batch: EntropyBatch):
+    batch.close()
 
 
 def scan_frame(scan: mjd_scan) -> dict:

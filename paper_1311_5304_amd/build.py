@@ -14,7 +14,7 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libmjd.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["api.hip", "decode.hip", "batch.hip", "copy.hip", "server.hip"]
+SOURCES = ["api.hip", "decode.hip", "batch.hip", "copy.hip", "server.hip", "entropy.hip"]
 # host-only C++ (no device code): built with the host compiler
 HOST_SOURCES = ["host_jpeg.cpp", "pipeline.cpp"]
 

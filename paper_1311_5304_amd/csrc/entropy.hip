@@ -1,0 +1,341 @@
+// GPU entropy decoding of many baseline scans: one lane per restart interval.
+//
+// The host plans the work:
+// - it checks every job;
+// - it builds each job's Huffman tables in the layout the kernel copies to
+//   LDS;
+// - it lists the restart intervals, and cuts each job's list into items of
+//   at most 256 intervals, so an item never spans two jobs.
+// A persistent kernel pops items from a device counter. A workgroup loads
+// the tables of the item's job into LDS (only when the job changes). Each
+// lane then decodes one interval with the bit reader and block decoder of
+// entropy_lane.h. Blocks are scattered into a per-lane LDS buffer and stored
+// whole (128 B) in MCU order, the layout mjd_decode reads. Each interval's
+// status goes to a device array; the last workgroup out rearms the counter.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "entropy_lane.h"
+#include "host_jpeg.h"
+#include "mjd_internal.h"
+
+namespace mjd {
+namespace gent {
+
+struct GJob {
+  const uint8_t* jpg;
+  int16_t* coef;
+  const GTables* tables;
+  int32_t bpm;
+  uint8_t comp_of[8];
+  int32_t pad;
+};
+
+struct GItem {
+  uint32_t job, first, count, pad;
+};
+
+constexpr int kThreads = 256;
+
+static int table_for(const mjd_huffman& h, bool ac, GHuff* t) {
+  switch (build_gtable(h, ac, t)) {
+    case kTableOk:
+      return MJD_OK;
+    case kTableUndefined:
+      return fail(MJD_ECORRUPT, "scan uses an undefined Huffman table");
+    case kTableTooMany:
+      return fail(MJD_ECORRUPT, "Huffman table with more than 256 symbols");
+    default:
+      return fail(MJD_ECORRUPT, "Huffman code lengths overfill the code space");
+  }
+}
+
+typedef __attribute__((address_space(3))) uint8_t lds8;
+typedef __attribute__((address_space(3))) uint16_t lds16;
+typedef __attribute__((address_space(3))) uint32_t lds32;
+typedef __attribute__((address_space(3))) int32_t ldsi32;
+typedef __attribute__((address_space(1))) const uint8_t gin8;
+typedef __attribute__((address_space(1))) const uint32_t gin32;
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) v4i_t gout128;
+typedef __attribute__((address_space(1))) const v4i_t gin128;
+typedef __attribute__((address_space(3))) v4i_t lds128;
+
+// The lane's view: tables and the zig-zag map in LDS, its 128-byte block
+// buffer in LDS, the stream and the coefficients in global memory.
+struct DevEnv {
+  const __attribute__((address_space(3))) GHuff* tab;
+  const lds8* natural;
+  lds32* blk;  // 32 dwords of this lane
+  gin8* jpg;
+  int16_t* coef;
+
+  __device__ uint32_t lut(int t, int i) const { return tab[t].lut[i]; }
+  __device__ uint32_t fast(int t, int i) const { return tab[t].fast[i]; }
+  __device__ int maxcode(int t, int l) const { return tab[t].maxcode[l]; }
+  __device__ int valoff(int t, int l) const { return tab[t].valoff[l]; }
+  __device__ int val(int t, int i) const { return tab[t].vals[i]; }
+  __device__ int nat(int k) const { return natural[k]; }
+  __device__ uint32_t byte(uint64_t p) const { return jpg[p]; }
+  __device__ uint32_t dword(uint64_t p) const { return *reinterpret_cast<gin32*>(jpg + p); }
+  __device__ void blk_clear() {
+    lds128* b = reinterpret_cast<lds128*>(blk);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = v4i_t{0, 0, 0, 0};
+  }
+  __device__ void blk_put(int idx, int v) { reinterpret_cast<lds16*>(blk)[idx] = static_cast<uint16_t>(v); }
+  __device__ void blk_store(uint64_t block) {
+    const lds128* b = reinterpret_cast<const lds128*>(blk);
+    gout128* dst = (gout128*)(coef + block * 64);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dst[i] = b[i];
+  }
+};
+
+__global__ __launch_bounds__(kThreads) void entropy_kernel(const GJob* __restrict__ jobs,
+                                                           const Interval* __restrict__ ivs,
+                                                           const GItem* __restrict__ items, int n_items,
+                                                           uint32_t* __restrict__ status, unsigned* counters) {
+  __shared__ __align__(16) GTables tabs;
+  __shared__ __align__(16) uint32_t blocks[kThreads * 32];
+  __shared__ int s_next;
+  const int tid = static_cast<int>(threadIdx.x);
+  int cur_job = -1;
+  for (;;) {
+    if (tid == 0) s_next = static_cast<int>(atomicAdd(&counters[0], 1u));
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_next);
+    __syncthreads();  // every lane has read s_next (and finished the last item)
+    if (it >= n_items) break;
+    const GItem item = items[it];
+    const int job = __builtin_amdgcn_readfirstlane(static_cast<int>(item.job));
+    if (job != cur_job) {
+      gin128* src = (gin128*)jobs[job].tables;
+      lds128* dst = (lds128*)&tabs;
+      for (int i = tid; i < static_cast<int>(sizeof(GTables) / 16); i += kThreads) dst[i] = src[i];
+      __syncthreads();
+      cur_job = job;
+    }
+    if (tid < static_cast<int>(item.count)) {
+      const GJob& jb = jobs[job];
+      const Interval iv = ivs[item.first + static_cast<uint32_t>(tid)];
+      DevEnv env{(const __attribute__((address_space(3))) GHuff*)tabs.t, (const lds8*)tabs.nat,
+                 (lds32*)(blocks + tid * 32), (gin8*)jb.jpg, jb.coef};
+      status[item.first + static_cast<uint32_t>(tid)] = decode_interval_lane(env, iv, jb.bpm, jb.comp_of);
+    }
+  }
+  // the last workgroup out rearms the queue for the next launch
+  if (tid == 0) {
+    __threadfence();
+    const unsigned done = atomicAdd(&counters[1], 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(&counters[0], 0u);
+      atomicExch(&counters[1], 0u);
+    }
+  }
+}
+
+}  // namespace gent
+}  // namespace mjd
+
+struct mjd_entropy_batch {
+  mjd_ctx* ctx = nullptr;
+  uint32_t n_jobs = 0;
+  uint32_t n_intervals = 0;
+  uint32_t n_items = 0;
+  int grid = 0;
+  mjd::gent::GJob* d_jobs = nullptr;
+  mjd::gent::GTables* d_tables = nullptr;
+  mjd::gent::Interval* d_ivs = nullptr;
+  mjd::gent::GItem* d_items = nullptr;
+  uint32_t* d_status = nullptr;
+  unsigned* d_counters = nullptr;
+  std::vector<uint32_t> first_interval;  // per job, into the interval list
+  uint64_t pixels = 0, bytes = 0;
+};
+
+namespace mjd {
+namespace gent {
+
+static void free_batch(mjd_entropy_batch* b) {
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_tables) (void)hipFree(b->d_tables);
+  if (b->d_ivs) (void)hipFree(b->d_ivs);
+  if (b->d_items) (void)hipFree(b->d_items);
+  if (b->d_status) (void)hipFree(b->d_status);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+}
+
+static int build(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n, mjd_entropy_batch* b) {
+  if (n == 0) return fail(MJD_EINVAL, "empty entropy batch");
+  if (n > (1u << 24)) return fail(MJD_EINVAL, "entropy batch of %zu jobs too large", n);
+  std::vector<GJob> gj(n);
+  std::vector<GTables> gt(n);
+  std::vector<Interval> ivs;
+  std::vector<GItem> items;
+  b->first_interval.resize(n);
+  for (size_t j = 0; j < n; ++j) {
+    const mjd_entropy_job& J = jobs[j];
+    if (!J.scan || !J.h_offsets || !J.d_jpg || !J.d_coef)
+      return fail(MJD_EINVAL, "job %zu: null scan, offsets, stream or coefficient pointer", j);
+    if ((reinterpret_cast<uintptr_t>(J.d_jpg) & 3) || (reinterpret_cast<uintptr_t>(J.d_coef) & 15))
+      return fail(MJD_EINVAL, "job %zu: stream not 4-byte or coefficients not 16-byte aligned", j);
+    host::ScanLayout L;
+    int rc = host::scan_layout(J.scan, &L);
+    if (rc != MJD_OK) {
+      const std::string why = mjd_last_error();
+      return fail(rc, "job %zu: %s", j, why.c_str());
+    }
+    if (L.bpm > 8) return fail(MJD_EINVAL, "job %zu: %d blocks per MCU", j, L.bpm);
+    for (int c = 0; c < 3; ++c) {
+      rc = table_for(J.scan->dc[J.scan->dc_sel[c]], false, &gt[j].t[c]);
+      if (rc == MJD_OK) rc = table_for(J.scan->ac[J.scan->ac_sel[c]], true, &gt[j].t[3 + c]);
+      if (rc != MJD_OK) {
+        const std::string why = mjd_last_error();
+        return fail(rc, "job %zu: %s", j, why.c_str());
+      }
+    }
+    memcpy(gt[j].nat, host::zigzag_to_natural(), 64);
+    gj[j].jpg = J.d_jpg;
+    gj[j].coef = J.d_coef;
+    gj[j].bpm = L.bpm;
+    for (int i = 0; i < 8; ++i) gj[j].comp_of[i] = static_cast<uint8_t>(i < L.bpm ? L.comp_of[i] : 0);
+    // the intervals: byte ranges from the restart index, checked against the stream
+    const uint32_t ni = J.scan->n_intervals;
+    const uint64_t ri = J.scan->restart_interval ? J.scan->restart_interval : L.n_mcus;
+    const uint64_t* off = J.h_offsets;
+    if (off[ni] > J.len) return fail(MJD_EINVAL, "job %zu: restart index past the stream end", j);
+    b->first_interval[j] = static_cast<uint32_t>(ivs.size());
+    for (uint32_t s = 0; s < ni; ++s) {
+      if (off[s + 1] < off[s] + 2) return fail(MJD_EINVAL, "job %zu: restart index not increasing", j);
+      Interval iv;
+      iv.start = off[s];
+      iv.end = off[s + 1] - 2;
+      iv.mcu0 = s * ri;
+      iv.n_mcus = static_cast<uint32_t>(std::min<uint64_t>(ri, L.n_mcus - iv.mcu0));
+      iv.job = static_cast<uint32_t>(j);
+      ivs.push_back(iv);
+    }
+    for (uint32_t s = 0; s < ni; s += kThreads)
+      items.push_back(GItem{static_cast<uint32_t>(j), b->first_interval[j] + s, std::min<uint32_t>(kThreads, ni - s), 0});
+    b->pixels += static_cast<uint64_t>(J.scan->frame.width) * J.scan->frame.height;
+    b->bytes += J.len;
+    if (ivs.size() > 0x7FFFFFF0u) return fail(MJD_EINVAL, "entropy batch holds too many intervals");
+  }
+  b->n_jobs = static_cast<uint32_t>(n);
+  b->n_intervals = static_cast<uint32_t>(ivs.size());
+  b->n_items = static_cast<uint32_t>(items.size());
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, entropy_kernel, kThreads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  b->grid = std::min<int>(static_cast<int>(items.size()), per_cu * (ctx->cu_count > 0 ? ctx->cu_count : 256));
+  if (hipMalloc(&b->d_tables, n * sizeof(GTables)) != hipSuccess ||
+      hipMalloc(&b->d_jobs, n * sizeof(GJob)) != hipSuccess ||
+      hipMalloc(&b->d_ivs, ivs.size() * sizeof(Interval)) != hipSuccess ||
+      hipMalloc(&b->d_items, items.size() * sizeof(GItem)) != hipSuccess ||
+      hipMalloc(&b->d_status, ivs.size() * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&b->d_counters, 2 * sizeof(unsigned)) != hipSuccess)
+    return fail(MJD_ENOMEM, "device allocation for the entropy batch tables failed");
+  for (size_t j = 0; j < n; ++j) gj[j].tables = b->d_tables + j;
+  if (hipMemcpy(b->d_tables, gt.data(), n * sizeof(GTables), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_jobs, gj.data(), n * sizeof(GJob), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_ivs, ivs.data(), ivs.size() * sizeof(Interval), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_items, items.data(), items.size() * sizeof(GItem), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(b->d_status, 0, ivs.size() * sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(b->d_counters, 0, 2 * sizeof(unsigned)) != hipSuccess)
+    return fail(MJD_EDEVICE, "uploading the entropy batch tables failed");
+  return MJD_OK;
+}
+
+}  // namespace gent
+}  // namespace mjd
+
+extern "C" {
+
+int mjd_entropy_batch_create(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n, mjd_entropy_batch** out) {
+  if (!ctx || !out) return mjd::fail(MJD_EINVAL, "null context or out-pointer");
+  *out = nullptr;
+  if (!jobs && n) return mjd::fail(MJD_EINVAL, "null jobs");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+    return mjd::fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+  mjd_entropy_batch* b = new (std::nothrow) mjd_entropy_batch;
+  if (!b) return mjd::fail(MJD_ENOMEM, "entropy batch allocation failed");
+  b->ctx = ctx;
+  int rc = mjd::gent::build(ctx, jobs, n, b);
+  if (cur != ctx->device) (void)hipSetDevice(cur);
+  if (rc != MJD_OK) {
+    mjd::gent::free_batch(b);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return MJD_OK;
+}
+
+int mjd_entropy_batch_launch(mjd_entropy_batch* b, void* stream) {
+  if (!b) return mjd::fail(MJD_EINVAL, "null entropy batch");
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != b->ctx->device && hipSetDevice(b->ctx->device) != hipSuccess)
+    return mjd::fail(MJD_EDEVICE, "hipSetDevice(%d) failed", b->ctx->device);
+  hipLaunchKernelGGL(mjd::gent::entropy_kernel, dim3(b->grid), dim3(mjd::gent::kThreads), 0,
+                     static_cast<hipStream_t>(stream), b->d_jobs, b->d_ivs, b->d_items, static_cast<int>(b->n_items),
+                     b->d_status, b->d_counters);
+  hipError_t e = hipGetLastError();
+  if (cur != b->ctx->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return mjd::fail(MJD_EDEVICE, "entropy kernel launch failed: %s", hipGetErrorString(e));
+  return MJD_OK;
+}
+
+int mjd_entropy_batch_status(mjd_entropy_batch* b, int64_t* bad_job) {
+  if (!b) return mjd::fail(MJD_EINVAL, "null entropy batch");
+  if (bad_job) *bad_job = -1;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != b->ctx->device && hipSetDevice(b->ctx->device) != hipSuccess)
+    return mjd::fail(MJD_EDEVICE, "hipSetDevice(%d) failed", b->ctx->device);
+  std::vector<uint32_t> st(b->n_intervals);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(st.data(), b->d_status, st.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (cur != b->ctx->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return mjd::fail(MJD_EDEVICE, "reading the entropy status failed: %s", hipGetErrorString(e));
+  for (uint32_t i = 0; i < b->n_intervals; ++i) {
+    if (!st[i]) continue;
+    const auto it = std::upper_bound(b->first_interval.begin(), b->first_interval.end(), i);
+    const int64_t job = static_cast<int64_t>(it - b->first_interval.begin()) - 1;
+    if (bad_job) *bad_job = job;
+    static const char* what[] = {"", "an invalid Huffman code", "a coefficient run past the end of a block",
+                                 "an interval that ends before its last MCU"};
+    return mjd::fail(MJD_ECORRUPT, "job %lld, restart interval %u: %s", static_cast<long long>(job),
+                     i - b->first_interval[static_cast<size_t>(job)], what[st[i] < 4 ? st[i] : 1]);
+  }
+  return MJD_OK;
+}
+
+int mjd_entropy_batch_info(const mjd_entropy_batch* b, uint32_t* intervals, uint32_t* workgroups, uint64_t* bytes) {
+  if (!b) return mjd::fail(MJD_EINVAL, "null entropy batch");
+  if (intervals) *intervals = b->n_intervals;
+  if (workgroups) *workgroups = static_cast<uint32_t>(b->grid);
+  if (bytes) *bytes = b->bytes;
+  return MJD_OK;
+}
+
+void mjd_entropy_batch_destroy(mjd_entropy_batch* b) {
+  if (!b) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != b->ctx->device) (void)hipSetDevice(b->ctx->device);
+  (void)hipDeviceSynchronize();
+  mjd::gent::free_batch(b);
+  if (cur != b->ctx->device) (void)hipSetDevice(cur);
+  delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// Runs the per-lane restart-interval decoder of the GPU entropy kernel on the
+// CPU, through a memory environment that checks every access, so its logic
+// can be compared with the oracle's reader and the host decoder without a
+// GPU.  Usage: entropy_lane_host <in.jpg> <out.bin>
+//   prints "<intervals> <intervals with a nonzero status>" and writes the
+//   n_blocks * 64 int16 coefficients (MCU order) to out.bin.
+// Exit status 3 on any out-of-range access, 2 on a parse error.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "entropy_lane.h"
+#include "mjd.h"
+
+using namespace mjd::gent;
+
+namespace {
+
+[[noreturn]] void out_of_range(const char* what) {
+  fprintf(stderr, "out-of-range %s\n", what);
+  exit(3);
+}
+
+struct CheckedEnv {
+  const GTables* tabs;
+  const uint8_t* jpg;
+  uint64_t lo, hi;  // the interval being decoded: reads stay in [lo, hi)
+  int16_t blk[64];
+  int16_t* coef;
+  uint64_t n_blocks;
+
+  uint32_t lut(int t, int i) const {
+    if (t < 0 || t > 5 || i < 0 || i >= (1 << kGLook)) out_of_range("lut");
+    return tabs->t[t].lut[i];
+  }
+  uint32_t fast(int t, int i) const {
+    if (t < 3 || t > 5 || i < 0 || i >= (1 << kGLook)) out_of_range("fast");
+    return tabs->t[t].fast[i];
+  }
+  int maxcode(int t, int l) const {
+    if (t < 0 || t > 5 || l < 1 || l > 17) out_of_range("maxcode");
+    return tabs->t[t].maxcode[l];
+  }
+  int valoff(int t, int l) const {
+    if (t < 0 || t > 5 || l < 1 || l > 17) out_of_range("valoff");
+    return tabs->t[t].valoff[l];
+  }
+  int val(int t, int i) const {
+    if (t < 0 || t > 5 || i < 0 || i > 255) out_of_range("val");
+    return tabs->t[t].vals[i];
+  }
+  int nat(int k) const {
+    if (k < 0 || k > 63) out_of_range("nat");
+    return tabs->nat[k];
+  }
+  uint32_t byte(uint64_t p) const {
+    if (p < lo || p >= hi) out_of_range("byte");
+    return jpg[p];
+  }
+  uint32_t dword(uint64_t p) const {
+    if (p < lo || p + 4 > hi || (p & 3)) out_of_range("dword");
+    uint32_t d;
+    memcpy(&d, jpg + p, 4);
+    return d;
+  }
+  void blk_clear() { memset(blk, 0, sizeof(blk)); }
+  void blk_put(int i, int v) {
+    if (i < 0 || i > 63) out_of_range("block index");
+    blk[i] = static_cast<int16_t>(v);
+  }
+  void blk_store(uint64_t b) {
+    if (b >= n_blocks) out_of_range("block store");
+    memcpy(coef + b * 64, blk, sizeof(blk));
+  }
+};
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc != 3) return 2;
+  FILE* f = fopen(argv[1], "rb");
+  if (!f) return 2;
+  std::vector<uint8_t> jpg;
+  for (int c; (c = fgetc(f)) != EOF;) jpg.push_back(static_cast<uint8_t>(c));
+  fclose(f);
+  mjd_scan scan;
+  uint16_t qt[4][64];
+  if (mjd_parse(jpg.data(), jpg.size(), &scan, qt) != MJD_OK) {
+    fprintf(stderr, "parse: %s\n", mjd_last_error());
+    return 2;
+  }
+  mjd_geometry g;
+  if (mjd_geometry_of(&scan.frame, &g) != MJD_OK) return 2;
+  std::vector<uint64_t> off(scan.n_intervals + 1);
+  if (mjd_restart_index(jpg.data(), jpg.size(), &scan, off.data()) != MJD_OK) {
+    fprintf(stderr, "restart index: %s\n", mjd_last_error());
+    return 2;
+  }
+  std::vector<GTables> tabs(1);
+  for (int c = 0; c < 3; ++c)
+    if (build_gtable(scan.dc[scan.dc_sel[c]], false, &tabs[0].t[c]) != kTableOk ||
+        build_gtable(scan.ac[scan.ac_sel[c]], true, &tabs[0].t[3 + c]) != kTableOk) {
+      fprintf(stderr, "bad Huffman table\n");
+      return 2;
+    }
+  // zig-zag position -> natural index, walking the anti-diagonals
+  {
+    int k = 0;
+    for (int s = 0; s < 15; ++s)
+      for (int i = 0; i <= s; ++i) {
+        const int r = (s & 1) ? i : s - i, c = s - r;
+        if (r < 8 && c < 8) tabs[0].nat[k++] = static_cast<uint8_t>(8 * r + c);
+      }
+  }
+  uint8_t comp_of[8] = {0};
+  int bpm = 0;
+  for (int c = 0; c < 3; ++c)
+    for (int i = 0; i < scan.frame.h[c] * scan.frame.v[c]; ++i) comp_of[bpm++] = static_cast<uint8_t>(c);
+  const uint64_t n_mcus = static_cast<uint64_t>(g.mcus_x) * g.mcus_y;
+  std::vector<int16_t> coef(g.n_blocks * 64, 0);
+  CheckedEnv env;
+  env.tabs = tabs.data();
+  env.jpg = jpg.data();
+  env.coef = coef.data();
+  env.n_blocks = g.n_blocks;
+  const uint64_t ri = scan.restart_interval ? scan.restart_interval : n_mcus;
+  uint32_t bad = 0;
+  for (uint32_t s = 0; s < scan.n_intervals; ++s) {
+    Interval iv;
+    iv.start = off[s];
+    iv.end = off[s + 1] - 2;
+    iv.mcu0 = s * ri;
+    iv.n_mcus = static_cast<uint32_t>(n_mcus - iv.mcu0 < ri ? n_mcus - iv.mcu0 : ri);
+    iv.job = 0;
+    env.lo = iv.start;
+    env.hi = iv.end;
+    if (decode_interval_lane(env, iv, bpm, comp_of) != kOk) ++bad;
+  }
+  f = fopen(argv[2], "wb");
+  if (!f || fwrite(coef.data(), 2, coef.size(), f) != coef.size()) return 2;
+  fclose(f);
+  printf("%u %u\n", scan.n_intervals, bad);
+  return 0;
+}
