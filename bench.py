@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-pipeline", action="store_true", help="skip the end-to-end bitstream corpus measurement")
     ap.add_argument("--corpus-images", type=int, default=1000)
     ap.add_argument("--pipeline-threads", type=int, default=15, help="entropy worker threads (plus the caller)")
+    ap.add_argument("--no-gpu-entropy", action="store_true",
+                    help="skip the device-resident corpus decode (GPU entropy kernel + batched back half)")
+    ap.add_argument("--gpu-entropy-reps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serve-requests", type=int, default=2200, help="requests per trace (the first 200 warm up)")
     return ap.parse_args()
@@ -237,6 +240,9 @@ def pipeline_workload(args, M, ctx, dev):
     finally:
         pipe.close()
     gpu_ms = full["h2d_ms"] + full["kernel_ms"] + full["d2h_ms"]
+    dev_e2e = None
+    if not args.no_gpu_entropy:
+        dev_e2e = gpu_entropy_workload(args, M, ctx, dev, jpgs, frames, smallest, sample)
     return {
         "images": len(jpgs), "megapixels": round(px / 1e6, 1), "bitstream_MB": round(nbytes / 1e6, 1),
         "bits_per_pixel": round(8 * nbytes / px, 3), "generation_s": round(gen_s, 1),
@@ -251,7 +257,98 @@ def pipeline_workload(args, M, ctx, dev):
         "d2h_ms": round(full["d2h_ms"], 1), "worker_entropy_ms": round(full["entropy_ms"], 1),
         "parse_ms": round(full["parse_ms"], 1), "bands": full["bands"],
         "bit_exact_sample": {"image": smallest, "size": [frame["width"], frame["height"]], "equal": exact},
+        "device_resident": dev_e2e,
     }
+
+
+def gpu_entropy_workload(args, M, ctx, dev, jpgs, frames, sample_idx, sample):
+    """The same corpus decoded on the device end to end: the bitstreams
+    resident in HBM, Huffman decoding by the entropy kernel (one lane per
+    restart interval, all images in one persistent launch), then the batched
+    back half (one persistent launch) into RGB8 buffers in HBM.  Planning
+    (headers, restart index, tables) happens before the timed region; the
+    host->device copy of the bitstreams is timed on its own."""
+    import torch
+
+    import oracle
+
+    log("device-resident corpus decode: planning")
+    stream = torch.cuda.current_stream()
+    offs, total = [], 0
+    for j in jpgs:  # each stream 16-byte aligned and padded to 16
+        offs.append(total)
+        total += -(-len(j) // 16) * 16
+    host = torch.zeros(total, dtype=torch.uint8).pin_memory()
+    hv = host.numpy()
+    for o, j in zip(offs, jpgs):
+        hv[o:o + len(j)] = np.frombuffer(j, dtype=np.uint8)
+    d_all = torch.empty(total, dtype=torch.uint8, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    d_all.copy_(host, non_blocking=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    h2d_ms = e0.elapsed_time(e1)
+    jobs_e, jobs_d = [], []
+    px = 0
+    for i, (j, f) in enumerate(zip(jpgs, frames)):
+        scan, qt = M.mjd_parse(j)
+        off = M.mjd_restart_index(j, scan)
+        g = M.mjd_geometry_of(f)
+        c = torch.empty(g["n_blocks"] * 64, dtype=torch.int16, device=dev)
+        o = torch.empty((f["height"], f["width"], 3), dtype=torch.uint8, device=dev)
+        q = torch.from_numpy(qt.view(np.int16)).to(dev)
+        jobs_e.append((scan, off, d_all[offs[i]:offs[i] + len(j)], len(j), c))
+        jobs_d.append((f, c, q, o, 3 * f["width"]))
+        px += f["width"] * f["height"]
+    eb = M.EntropyBatch(ctx, jobs_e)
+    db = M.Batch(ctx, jobs_d, M.MJD_UPSAMPLE_FANCY)
+    info = eb.info()
+    log("device-resident corpus decode: timing")
+    eb.launch(stream)
+    db.launch(stream=stream)
+    eb.status()
+    reps = max(1, args.gpu_entropy_reps)
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    ent_ms = timed(lambda: eb.launch(stream))
+    back_ms = timed(lambda: db.launch(stream=stream))
+    e2e_ms = timed(lambda: (eb.launch(stream), db.launch(stream=stream)))
+    eb.status()
+    # bit-exactness of the smallest image: its coefficients equal the
+    # encoder's, its RGB equals the oracle's back half on them
+    frame, coef, qt = sample
+    got_c = jobs_d[sample_idx][1].cpu().numpy().reshape(-1, 64)
+    got_rgb = jobs_d[sample_idx][3].cpu().numpy()
+    exact = bool(np.array_equal(got_c, coef.reshape(-1, 64)) and
+                 np.array_equal(got_rgb, oracle.decode(frame, coef.reshape(-1, 64), qt, "fancy")))
+    nbytes = sum(len(j) for j in jpgs)
+    res = {
+        "MPix_s": round(px / (e2e_ms * 1e-3) / 1e6, 1),
+        "ms": round(e2e_ms, 3),
+        "entropy_kernel_ms": round(ent_ms, 3),
+        "entropy_MPix_s": round(px / (ent_ms * 1e-3) / 1e6, 1),
+        "entropy_bitstream_GBps": round(nbytes / (ent_ms * 1e-3) / 1e9, 2),
+        "back_half_ms": round(back_ms, 3),
+        "bitstream_h2d_ms": round(h2d_ms, 2),
+        "MPix_s_with_h2d": round(px / ((e2e_ms + h2d_ms) * 1e-3) / 1e6, 1),
+        "restart_intervals": info["intervals"], "entropy_workgroups": info["workgroups"],
+        "reps": reps,
+        "bit_exact_sample": {"image": sample_idx, "equal": exact},
+    }
+    db.close()
+    eb.close()
+    del jobs_e, jobs_d, d_all
+    torch.cuda.empty_cache()
+    return res
 
 
 def serve_workload(args, M, ctx, dev):

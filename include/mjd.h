@@ -266,8 +266,9 @@ typedef struct mjd_entropy_job {
   const mjd_scan* scan;      /* host: from mjd_parse; read at create time */
   const uint64_t* h_offsets; /* host: from mjd_restart_index (n_intervals + 1
                                 entries); read at create time */
-  const uint8_t* d_jpg;      /* device: the whole stream, bytes [0, len);
-                                4-byte aligned */
+  const uint8_t* d_jpg;      /* device, 16-byte aligned: the whole stream,
+                                bytes [0, len); the buffer must be readable
+                                up to len rounded up to a multiple of 16 */
   uint64_t len;              /* bytes of the stream at d_jpg */
   int16_t* d_coef;           /* device, 16-byte aligned: n_blocks * 64 int16
                                 in the MCU order mjd_decode reads (natural
@@ -288,8 +289,9 @@ int mjd_entropy_batch_create(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n
 
 /* Enqueue the decoding of every job on `stream`: one persistent kernel whose
  * workgroups take up to 256 intervals of one job at a time.  Launches of one
- * batch must be serialised (one stream).  Reads only [d_jpg, d_jpg + len)
- * of each job and writes only its coefficient blocks. */
+ * batch must be serialised (one stream).  Reads only the first len bytes of
+ * each job's stream, rounded up to 16, and writes only its coefficient
+ * blocks. */
 int mjd_entropy_batch_launch(mjd_entropy_batch* batch, void* stream);
 
 /* Synchronise the device and check the last launch: MJD_OK, or

@@ -31,9 +31,10 @@ struct GJob {
   const uint8_t* jpg;
   int16_t* coef;
   const GTables* tables;
-  int32_t bpm;
-  uint8_t comp_of[8];
-  int32_t pad;
+  uint32_t lim;        // stream bytes, rounded up to 16 (chunk loads stay below)
+  int32_t bpm;         // blocks per MCU
+  uint32_t comp_bits;  // component of block b of an MCU in bits 2b..2b+1
+  uint32_t pad;
 };
 
 struct GItem {
@@ -41,6 +42,7 @@ struct GItem {
 };
 
 constexpr int kThreads = 256;
+constexpr uint64_t kMaxStream = 0xFFFFFF00u;  // stream offsets are 32-bit
 
 static int table_for(const mjd_huffman& h, bool ac, GHuff* t) {
   switch (build_gtable(h, ac, t)) {
@@ -58,7 +60,6 @@ static int table_for(const mjd_huffman& h, bool ac, GHuff* t) {
 typedef __attribute__((address_space(3))) uint8_t lds8;
 typedef __attribute__((address_space(3))) uint16_t lds16;
 typedef __attribute__((address_space(3))) uint32_t lds32;
-typedef __attribute__((address_space(3))) int32_t ldsi32;
 typedef __attribute__((address_space(1))) const uint8_t gin8;
 typedef __attribute__((address_space(1))) const uint32_t gin32;
 typedef int v4i_t __attribute__((ext_vector_type(4)));
@@ -66,35 +67,56 @@ typedef __attribute__((address_space(1))) v4i_t gout128;
 typedef __attribute__((address_space(1))) const v4i_t gin128;
 typedef __attribute__((address_space(3))) v4i_t lds128;
 
-// The lane's view: tables and the zig-zag map in LDS, its 128-byte block
-// buffer in LDS, the stream and the coefficients in global memory.
-struct DevEnv {
+// Tables and the zig-zag map, in LDS.
+struct DevTab {
   const __attribute__((address_space(3))) GHuff* tab;
   const lds8* natural;
-  lds32* blk;  // 32 dwords of this lane
-  gin8* jpg;
-  int16_t* coef;
-
-  __device__ uint32_t lut(int t, int i) const { return tab[t].lut[i]; }
   __device__ uint32_t fast(int t, int i) const { return tab[t].fast[i]; }
-  __device__ int maxcode(int t, int l) const { return tab[t].maxcode[l]; }
+  __device__ int lim(int t, int l) const { return tab[t].lim[l]; }
   __device__ int valoff(int t, int l) const { return tab[t].valoff[l]; }
   __device__ int val(int t, int i) const { return tab[t].vals[i]; }
   __device__ int nat(int k) const { return natural[k]; }
-  __device__ uint32_t byte(uint64_t p) const { return jpg[p]; }
-  __device__ uint32_t dword(uint64_t p) const { return *reinterpret_cast<gin32*>(jpg + p); }
-  __device__ void blk_clear() {
-    lds128* b = reinterpret_cast<lds128*>(blk);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) b[i] = v4i_t{0, 0, 0, 0};
+};
+
+// Per-lane LDS buffers of 128 bytes sit 128 bytes apart, so their 16-byte
+// chunks are rotated by the lane number: the lanes of a wave then spread a
+// 16-byte access at the same offset over all banks.
+__device__ inline uint32_t swz(uint32_t off, uint32_t rot) { return (((off >> 4) + rot) & 7u) << 4 | (off & 15u); }
+
+// The block being decoded: 128 bytes of LDS per lane, stored whole (eight
+// 16-byte stores) to the next block of the interval and cleared.
+struct DevBlk {
+  lds8* buf;
+  gout128* dst;
+  uint32_t rot;
+  __device__ void put(int idx, int v) {
+    *reinterpret_cast<lds16*>(buf + swz(static_cast<uint32_t>(idx) * 2, rot)) = static_cast<uint16_t>(v);
   }
-  __device__ void blk_put(int idx, int v) { reinterpret_cast<lds16*>(blk)[idx] = static_cast<uint16_t>(v); }
-  __device__ void blk_store(uint64_t block) {
-    const lds128* b = reinterpret_cast<const lds128*>(blk);
-    gout128* dst = (gout128*)(coef + block * 64);
+  __device__ void finish() {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) dst[i] = b[i];
+    for (int i = 0; i < 8; ++i) dst[i] = *reinterpret_cast<lds128*>(buf + swz(16u * i, rot));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) reinterpret_cast<lds128*>(buf)[i] = v4i_t{0, 0, 0, 0};
+    dst += 8;
   }
+};
+
+// The lane's stream: 16-byte chunk loads from global memory, held in two
+// register slots until the next refill writes them to the lane's 128-byte
+// LDS ring, from which every stream byte is read.
+struct DevMem {
+  gin8* jpg;
+  lds8* ring;
+  uint32_t rot;
+  v4i_t c0, c1;
+  __device__ void g_chunk(uint32_t p, int slot) {
+    const v4i_t v = *reinterpret_cast<gin128*>(jpg + p);
+    if (slot) c1 = v;
+    else c0 = v;
+  }
+  __device__ void commit(int slot, uint32_t off) { *reinterpret_cast<lds128*>(ring + swz(off, rot)) = slot ? c1 : c0; }
+  __device__ uint32_t r_byte(uint32_t off) const { return ring[swz(off, rot)]; }
+  __device__ uint32_t r_dword(uint32_t off) const { return *reinterpret_cast<const lds32*>(ring + swz(off, rot)); }
 };
 
 __global__ __launch_bounds__(kThreads) void entropy_kernel(const GJob* __restrict__ jobs,
@@ -103,8 +125,14 @@ __global__ __launch_bounds__(kThreads) void entropy_kernel(const GJob* __restric
                                                            uint32_t* __restrict__ status, unsigned* counters) {
   __shared__ __align__(16) GTables tabs;
   __shared__ __align__(16) uint32_t blocks[kThreads * 32];
+  __shared__ __align__(16) uint8_t rings[kThreads * kRing];
   __shared__ int s_next;
   const int tid = static_cast<int>(threadIdx.x);
+  {
+    lds128* b = reinterpret_cast<lds128*>((lds8*)blocks + tid * 128);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = v4i_t{0, 0, 0, 0};
+  }
   int cur_job = -1;
   for (;;) {
     if (tid == 0) s_next = static_cast<int>(atomicAdd(&counters[0], 1u));
@@ -124,9 +152,17 @@ __global__ __launch_bounds__(kThreads) void entropy_kernel(const GJob* __restric
     if (tid < static_cast<int>(item.count)) {
       const GJob& jb = jobs[job];
       const Interval iv = ivs[item.first + static_cast<uint32_t>(tid)];
-      DevEnv env{(const __attribute__((address_space(3))) GHuff*)tabs.t, (const lds8*)tabs.nat,
-                 (lds32*)(blocks + tid * 32), (gin8*)jb.jpg, jb.coef};
-      status[item.first + static_cast<uint32_t>(tid)] = decode_interval_lane(env, iv, jb.bpm, jb.comp_of);
+      DevTab tab{(const __attribute__((address_space(3))) GHuff*)tabs.t, (const lds8*)tabs.nat};
+      const uint32_t rot = static_cast<uint32_t>(tid) & 7u;
+      DevBlk blk{(lds8*)blocks + tid * 128, (gout128*)(jb.coef + iv.mcu0 * static_cast<uint64_t>(jb.bpm) * 64), rot};
+      DevMem mem{(gin8*)jb.jpg, (lds8*)rings + tid * kRing, rot, v4i_t{0, 0, 0, 0}, v4i_t{0, 0, 0, 0}};
+      const uint32_t st = decode_interval(tab, blk, mem, jb.lim, iv, jb.bpm, jb.comp_bits);
+      if (st != kOk) {  // leave the block buffer clear for the next interval
+        lds128* b = reinterpret_cast<lds128*>(blk.buf);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) b[i] = v4i_t{0, 0, 0, 0};
+      }
+      status[item.first + static_cast<uint32_t>(tid)] = st;
     }
   }
   // the last workgroup out rearms the queue for the next launch
@@ -183,8 +219,10 @@ static int build(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n, mjd_entrop
     const mjd_entropy_job& J = jobs[j];
     if (!J.scan || !J.h_offsets || !J.d_jpg || !J.d_coef)
       return fail(MJD_EINVAL, "job %zu: null scan, offsets, stream or coefficient pointer", j);
-    if ((reinterpret_cast<uintptr_t>(J.d_jpg) & 3) || (reinterpret_cast<uintptr_t>(J.d_coef) & 15))
-      return fail(MJD_EINVAL, "job %zu: stream not 4-byte or coefficients not 16-byte aligned", j);
+    if ((reinterpret_cast<uintptr_t>(J.d_jpg) & 15) || (reinterpret_cast<uintptr_t>(J.d_coef) & 15))
+      return fail(MJD_EINVAL, "job %zu: stream or coefficients not 16-byte aligned", j);
+    if (J.len > kMaxStream) return fail(MJD_EINVAL, "job %zu: stream of %llu bytes is too long", j,
+                                        static_cast<unsigned long long>(J.len));
     host::ScanLayout L;
     int rc = host::scan_layout(J.scan, &L);
     if (rc != MJD_OK) {
@@ -203,8 +241,10 @@ static int build(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n, mjd_entrop
     memcpy(gt[j].nat, host::zigzag_to_natural(), 64);
     gj[j].jpg = J.d_jpg;
     gj[j].coef = J.d_coef;
+    gj[j].lim = static_cast<uint32_t>((J.len + 15) & ~uint64_t{15});
     gj[j].bpm = L.bpm;
-    for (int i = 0; i < 8; ++i) gj[j].comp_of[i] = static_cast<uint8_t>(i < L.bpm ? L.comp_of[i] : 0);
+    gj[j].comp_bits = 0;
+    for (int i = 0; i < L.bpm; ++i) gj[j].comp_bits |= static_cast<uint32_t>(L.comp_of[i]) << (2 * i);
     // the intervals: byte ranges from the restart index, checked against the stream
     const uint32_t ni = J.scan->n_intervals;
     const uint64_t ri = J.scan->restart_interval ? J.scan->restart_interval : L.n_mcus;
@@ -214,11 +254,11 @@ static int build(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n, mjd_entrop
     for (uint32_t s = 0; s < ni; ++s) {
       if (off[s + 1] < off[s] + 2) return fail(MJD_EINVAL, "job %zu: restart index not increasing", j);
       Interval iv;
-      iv.start = off[s];
-      iv.end = off[s + 1] - 2;
+      iv.start = static_cast<uint32_t>(off[s]);
+      iv.end = static_cast<uint32_t>(off[s + 1] - 2);
+      iv.pad = 0;
       iv.mcu0 = s * ri;
       iv.n_mcus = static_cast<uint32_t>(std::min<uint64_t>(ri, L.n_mcus - iv.mcu0));
-      iv.job = static_cast<uint32_t>(j);
       ivs.push_back(iv);
     }
     for (uint32_t s = 0; s < ni; s += kThreads)

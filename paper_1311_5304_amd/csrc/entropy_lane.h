@@ -1,25 +1,21 @@
 // Huffman decoding of one restart interval of a baseline scan, written once
-// for one GPU lane and, through the memory environment `Env`, for any other
-// caller.  The paper leaves entropy decoding on the CPU because code words
-// have variable length (Sec. 1); restart intervals restart the bit stream
-// and the DC predictions, so each of them decodes on its own (ITU-T T.81
-// restart markers).
+// for one GPU lane and, through small memory interfaces, for a CPU caller
+// too.  The paper leaves entropy decoding on the CPU because code words have
+// variable length (Sec. 1); restart intervals restart the bit stream and the
+// DC predictions, so each of them decodes on its own (ITU-T T.81 restart
+// markers).
 //
-// Env supplies:
-//   uint32_t lut(int t, int i)     (length << 8) | symbol for codes of at most
-//                                  kGLook bits (index: the next kGLook bits),
-//                                  0 for longer codes
-//   uint32_t fast(int t, int i)    AC: (value << 16) | (run << 8) | bits used
-//                                  when code and magnitude fit kGLook bits
-//   int maxcode(int t, int l), valoff(int t, int l), val(int t, int i)
-//                                  the canonical code walk for longer codes
-//   int nat(int k)                 natural index of zig-zag position k
-//   uint32_t byte(uint64_t p)      stream byte p
-//   uint32_t dword(uint64_t p)     stream bytes p..p+3 as a little-endian
-//                                  word (p is a multiple of 4)
-//   void blk_clear(), blk_put(int natural_index, int value),
-//   blk_store(uint64_t block)      the block being decoded and its output
-// Tables t = component (DC) and 3 + component (AC).
+// A lane advances one Huffman symbol per call of lane_step, so that the 64
+// lanes of a wave, each in its own interval, run the same short path:
+// - one 16-bit table entry gives the length, zero run and magnitude size of
+//   any code of at most kGLook bits, and the magnitude bits are read from
+//   the same 32-bit window (T.81 F.1.2.2, F.2.2.1);
+// - longer codes take their length from the left-aligned code-space limits
+//   of the canonical code (T.81 Annex C), without a loop over lengths;
+// - a finished block leaves through the block interface.
+// The stream comes through StreamRing, which serves bytes from a per-lane
+// ring filled ahead of use at points the whole wave reaches together, so
+// that loads are issued well before any lane waits for them.
 #pragma once
 
 #include <stdint.h>
@@ -37,114 +33,51 @@
 namespace mjd {
 namespace gent {
 
-constexpr int kGLook = 9;  // look-ahead window of the GPU tables
+constexpr int kGLook = 10;  // look-ahead bits of the first-level table
 
-enum : uint32_t { kOk = 0, kBadCode = 1, kBadRun = 2, kOverrun = 3 };
+// Interval status; kRunning is internal to lane_step.
+enum : uint32_t { kOk = 0, kBadCode = 1, kBadRun = 2, kOverrun = 3, kRunning = 4 };
 
 // One restart interval: its entropy-coded bytes [start, end) (end is the
 // first byte of the marker that closes it) and its MCUs.
 struct Interval {
-  uint64_t start, end;
-  uint64_t mcu0;
+  uint32_t start, end;
   uint32_t n_mcus;
-  uint32_t job;
+  uint32_t pad;
+  uint64_t mcu0;
 };
 
-// Bit reader over [p, end): MSB-first window w0:w1 with `pos` bits of w0
-// used; stuffed 0x00 after 0xFF dropped; at a marker or at `end` it feeds
-// zero bits.  `fed` counts real bits, `used` consumed bits, so used > fed
-// means the interval ran out of data.
-template <class Env>
-struct LaneBits {
-  Env& env;
-  uint64_t p, end;
-  uint32_t w0 = 0, w1 = 0;
-  uint32_t pos = 0;
-  uint32_t fed = 0, used = 0;
-  bool stop = false;
+// Entry of the first-level table (index: the next kGLook bits):
+//   0                no code of at most kGLook bits starts there
+//   bits 0-4         code length
+//   bits 5-8         magnitude size (AC: low nibble of the symbol; DC: the
+//                    symbol); size 0 in an AC table is EOB, or ZRL with run 15
+//   bits 9-12        zero run (AC: high nibble of the symbol)
+//   kBadSym          a DC symbol above 11
+constexpr uint32_t kBadSym = 1u << 13;
 
-  MJD_HD LaneBits(Env& e, uint64_t start, uint64_t end_) : env(e), p(start), end(end_) {
-    w0 = next32();
-    w1 = next32();
-  }
-
-  MJD_HD uint32_t next_byte() {
-    if (stop || p >= end) {
-      stop = true;
-      return 0;
-    }
-    const uint32_t b = env.byte(p++);
-    if (b == 0xFF) {
-      if (p < end && env.byte(p) == 0x00) {
-        ++p;
-        fed += 8;
-        return 0xFF;
-      }
-      stop = true;
-      return 0;
-    }
-    fed += 8;
-    return b;
-  }
-
-  // The next 32 stream bits, MSB first.
-  MJD_HD uint32_t next32() {
-    if (!stop && (p & 3u) == 0 && p + 4 <= end) {
-      const uint32_t d = env.dword(p);
-      const uint32_t x = ~d;  // 0xFF bytes become zero bytes
-      if (((x - 0x01010101u) & ~x & 0x80808080u) == 0) {
-        p += 4;
-        fed += 32;
-        return (d >> 24) | ((d >> 8) & 0xFF00u) | ((d << 8) & 0xFF0000u) | (d << 24);
-      }
-    }
-    uint32_t r = 0;
-    for (int i = 0; i < 4; ++i) r = (r << 8) | next_byte();
-    return r;
-  }
-
-  // The next n bits (1 <= n <= 16) as an unsigned value, not consumed.
-  MJD_HD uint32_t peek(uint32_t n) const {
-    const uint32_t top = pos ? (w0 << pos) | (w1 >> (32u - pos)) : w0;
-    return top >> (32u - n);
-  }
-
-  MJD_HD void consume(uint32_t n) {
-    used += n;
-    pos += n;
-    if (pos >= 32u) {
-      pos -= 32u;
-      w0 = w1;
-      w1 = next32();
-    }
-  }
-};
-
-MJD_HD inline int extend_value(int raw, int s) { return raw < (1 << (s - 1)) ? raw - (1 << s) + 1 : raw; }
-
-// One Huffman table in the form the lanes read.
 struct GHuff {
-  uint16_t lut[1 << kGLook];
-  uint32_t fast[1 << kGLook];
-  int32_t maxcode[18];
-  int32_t valoff[18];
+  uint16_t fast[1 << kGLook];
+  int32_t lim[17];     // lim[l]: codes of length <= l fill [0, lim[l]) of the 16-bit left-aligned code space
+  int32_t valoff[17];  // symbol index = code + valoff[length]
   uint8_t vals[256];
+  uint8_t pad[8];
 };
 
-// A scan's tables, per component: DC of components 0..2, then AC, and the
-// zig-zag map.
+// A scan's tables: DC of components 0..2, then AC of components 0..2, and
+// the zig-zag map.
 struct GTables {
   GHuff t[6];
   uint8_t nat[64];  // natural index of zig-zag position k
 };
-static_assert(sizeof(GTables) % 16 == 0, "tables copy as 16-byte chunks");
+static_assert(sizeof(GHuff) % 16 == 0 && sizeof(GTables) % 16 == 0, "tables copy as 16-byte chunks");
+
+MJD_HD inline int extend_value(int raw, int s) { return raw < (1 << (s - 1)) ? raw - (1 << s) + 1 : raw; }
 
 enum : int { kTableOk = 0, kTableUndefined = 1, kTableTooMany = 2, kTableOverfull = 3 };
 
 // Builds a table from its DHT code counts and symbols (canonical codes,
-// ITU-T T.81 Annex C): the look-ahead table, the AC fast table (a code and
-// its magnitude bits together within kGLook bits) and the per-length code
-// limits for longer codes.
+// T.81 Annex C).
 inline int build_gtable(const mjd_huffman& h, bool ac, GHuff* t) {
   memset(t, 0, sizeof(*t));
   if (!h.defined) return kTableUndefined;
@@ -159,104 +92,272 @@ inline int build_gtable(const mjd_huffman& h, bool ac, GHuff* t) {
     for (int i = 0; i < h.bits[l - 1]; ++i) {
       if (code >= (1 << l)) return kTableOverfull;
       if (l <= kGLook) {
+        const uint32_t sym = h.vals[k];
+        const uint32_t e = ac ? static_cast<uint32_t>(l) | (sym & 15u) << 5 | (sym >> 4) << 9
+                              : static_cast<uint32_t>(l) | (sym & 15u) << 5 | (sym > 11 ? kBadSym : 0u);
         const int lo = code << (kGLook - l), hi = (code + 1) << (kGLook - l);
-        for (int p = lo; p < hi; ++p) t->lut[p] = static_cast<uint16_t>((l << 8) | h.vals[k]);
+        for (int p = lo; p < hi; ++p) t->fast[p] = static_cast<uint16_t>(e);
       }
       ++code;
       ++k;
     }
-    t->maxcode[l] = h.bits[l - 1] ? code - 1 : -1;
+    t->lim[l] = code << (16 - l);
     code <<= 1;
-  }
-  t->maxcode[17] = -1;
-  if (ac) {
-    for (int p = 0; p < (1 << kGLook); ++p) {
-      const int e = t->lut[p];
-      if (!e) continue;
-      const int l = e >> 8, sym = e & 0xFF, run = sym >> 4, s = sym & 15;
-      if (s == 0 || l + s > kGLook) continue;
-      const int raw = (p >> (kGLook - l - s)) & ((1 << s) - 1);
-      const int v = extend_value(raw, s);
-      t->fast[p] = (static_cast<uint32_t>(static_cast<uint16_t>(static_cast<int16_t>(v))) << 16) |
-                   static_cast<uint32_t>(run << 8) | static_cast<uint32_t>(l + s);
-    }
   }
   return kTableOk;
 }
 
-// The next Huffman symbol of table t, or -1 for a code the table lacks.
-template <class Env>
-MJD_HD inline int lane_symbol(Env& env, LaneBits<Env>& br, int t) {
-  const uint32_t e = env.lut(t, static_cast<int>(br.peek(kGLook)));
-  if (e) {
-    br.consume(e >> 8);
-    return static_cast<int>(e & 0xFFu);
+// Stream bytes of one lane, all read from a ring of kRing bytes that holds
+// stream bytes [lo, have) at offsets p % kRing.  Mem supplies
+//   void g_chunk(uint32_t p, int slot)   start loading stream bytes
+//                                        [p, p + 16) (p a multiple of 16)
+//                                        into slot 0/1
+//   void commit(int slot, uint32_t off)  put that chunk in the ring at off
+//   uint32_t r_byte(uint32_t off), r_dword(uint32_t off)   ring reads
+// refill(p) commits the chunks the previous refill loaded and starts up to
+// two more, each only where the ring bytes it will overwrite lie below p,
+// the next byte the reader needs.  Chunks are loaded while they start
+// below `lim`, the stream length rounded up to 16.  The reader never reads
+// the stream directly: a lane whose ring lacks the next bytes waits for the
+// next refill (ready()).
+constexpr uint32_t kRing = 128;
+
+template <class Mem>
+struct StreamRing {
+  Mem& mem;
+  uint32_t lim;
+  uint32_t lo, have;
+  uint32_t npend = 0;
+
+  MJD_HD StreamRing(Mem& m, uint32_t lim_, uint32_t start) : mem(m), lim(lim_) { lo = have = start & ~15u; }
+
+  MJD_HD uint32_t byte(uint32_t p) { return mem.r_byte(p % kRing); }
+
+  // Stream bytes [a, a + 8) as two little-endian words (a a multiple of 4).
+  MJD_HD void pair(uint32_t a, uint32_t& d0, uint32_t& d1) {
+    d0 = mem.r_dword(a % kRing);
+    d1 = mem.r_dword((a + 4) % kRing);
   }
-  const int w = static_cast<int>(br.peek(16));
-  for (int l = kGLook + 1; l <= 16; ++l) {
-    const int c = w >> (16 - l);
-    if (c <= env.maxcode(t, l)) {
-      br.consume(static_cast<uint32_t>(l));
-      const int idx = c + env.valoff(t, l);
-      return (idx >= 0 && idx < 256) ? env.val(t, idx) : -1;
+
+  // The ring holds every byte one refill of the bit window can read: eight
+  // bytes from p (four data bytes, each possibly stuffed), or up to `end`.
+  MJD_HD bool ready(uint32_t p, uint32_t end) const { return have >= (p + 8 < end ? p + 8 : end); }
+
+  MJD_HD void refill(uint32_t p) {
+    if (npend > 0) {
+      mem.commit(0, have % kRing);
+      have += 16;
+    }
+    if (npend > 1) {
+      mem.commit(1, have % kRing);
+      have += 16;
+    }
+    if (have - lo > kRing) lo = have - kRing;
+    npend = 0;
+    if (have + 16 <= p + kRing && have < lim) {
+      mem.g_chunk(have, 0);
+      npend = 1;
+      if (have + 32 <= p + kRing && have + 16 < lim) {
+        mem.g_chunk(have + 16, 1);
+        npend = 2;
+      }
     }
   }
-  return -1;
+};
+
+// Bytes sh..sh+3 of the little-endian pair (d0, d1), first byte most
+// significant.
+MJD_HD inline uint32_t be32_at(uint32_t d0, uint32_t d1, uint32_t sh) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_perm(d1, d0, 0x00010203u + sh * 0x01010101u);
+#else
+  const uint64_t v = ((static_cast<uint64_t>(d1) << 32) | d0) >> (8 * sh);
+  const uint32_t x = static_cast<uint32_t>(v);
+  return (x >> 24) | ((x >> 8) & 0xFF00u) | ((x << 8) & 0xFF0000u) | (x << 24);
+#endif
 }
 
-// Decodes interval `iv`: every block of its MCUs goes to Env::blk_store in
-// MCU order (block index mcu * bpm + b).  comp_of[b]: component of block b
-// of an MCU.  Returns kOk or the first error; the loops are bounded by the
-// interval's MCU count and 64 coefficients per block.
-template <class Env>
-MJD_HD inline uint32_t decode_interval_lane(Env& env, const Interval& iv, int bpm, const uint8_t* comp_of) {
-  LaneBits<Env> br(env, iv.start, iv.end);
-  int pred[3] = {0, 0, 0};
-  for (uint32_t m = 0; m < iv.n_mcus; ++m) {
-    for (int b = 0; b < bpm; ++b) {
-      const int comp = comp_of[b];
-      env.blk_clear();
-      const int s = lane_symbol(env, br, comp);
-      if (s < 0 || s > 11) return kBadCode;
-      if (s) {
-        const int raw = static_cast<int>(br.peek(static_cast<uint32_t>(s)));
-        br.consume(static_cast<uint32_t>(s));
-        pred[comp] += extend_value(raw, s);
-      }
-      env.blk_put(0, pred[comp]);
-      const int act = 3 + comp;
-      for (int k = 1; k < 64;) {
-        const uint32_t f = env.fast(act, static_cast<int>(br.peek(kGLook)));
-        if (f) {
-          br.consume(f & 0xFFu);
-          k += static_cast<int>((f >> 8) & 0xFFu);
-          if (k > 63) return kBadRun;
-          env.blk_put(env.nat(k), static_cast<int>(static_cast<int16_t>(f >> 16)));
-          ++k;
-          continue;
-        }
-        const int rs = lane_symbol(env, br, act);
-        if (rs < 0) return kBadCode;
-        const int r = rs >> 4, sz = rs & 15;
-        if (sz == 0) {
-          if (r == 15) {  // ZRL: sixteen zeros
-            k += 16;
-            continue;
-          }
-          break;  // EOB
-        }
-        k += r;
-        if (k > 63) return kBadRun;
-        const int raw = static_cast<int>(br.peek(static_cast<uint32_t>(sz)));
-        br.consume(static_cast<uint32_t>(sz));
-        env.blk_put(env.nat(k), extend_value(raw, sz));
-        ++k;
-      }
-      env.blk_store((iv.mcu0 + m) * static_cast<uint64_t>(bpm) + static_cast<uint64_t>(b));
-    }
-    if (br.used > br.fed) return kOverrun;
+// Bit reader over [p, end): MSB-first window w0:w1 with `pos` bits of w0
+// used; stuffed 0x00 after 0xFF dropped; at a marker or at `end` it feeds
+// zero bits.  `fed` counts real bits and `used` consumed bits, so used > fed
+// means the interval ran out of data.
+template <class Ring>
+struct LaneBits {
+  Ring& ring;
+  uint32_t p, end;
+  uint32_t w0 = 0, w1 = 0;
+  uint32_t pos = 0;
+  uint32_t fed = 0, used = 0;
+  bool stop = false;
+
+  MJD_HD LaneBits(Ring& r, uint32_t start, uint32_t end_) : ring(r), p(start), end(end_) {}
+
+  MJD_HD void prime() {
+    w0 = next32();
+    w1 = next32();
   }
-  return kOk;
+
+  MJD_HD uint32_t next_byte() {
+    if (stop || p >= end) {
+      stop = true;
+      return 0;
+    }
+    const uint32_t b = ring.byte(p++);
+    if (b == 0xFF) {
+      if (p < end && ring.byte(p) == 0x00) {
+        ++p;
+        fed += 8;
+        return 0xFF;
+      }
+      stop = true;
+      return 0;
+    }
+    fed += 8;
+    return b;
+  }
+
+  // The next 32 stream bits, MSB first: four bytes at once wherever none
+  // of them is 0xFF, whatever the alignment.
+  MJD_HD uint32_t next32() {
+    if (!stop && p + 4 <= end) {
+      uint32_t d0, d1;
+      ring.pair(p & ~3u, d0, d1);
+      const uint32_t d = be32_at(d0, d1, p & 3u);
+      const uint32_t x = ~d;  // 0xFF bytes become zero bytes
+      if (((x - 0x01010101u) & ~x & 0x80808080u) == 0) {
+        p += 4;
+        fed += 32;
+        return d;
+      }
+    }
+    uint32_t r = 0;
+#if defined(__HIP_DEVICE_COMPILE__)
+#pragma unroll 1
+#endif
+    for (int i = 0; i < 4; ++i) r = (r << 8) | next_byte();
+    return r;
+  }
+
+  // The next 32 bits of the window (at least 33 are held), not consumed.
+  MJD_HD uint32_t peek32() const { return pos ? (w0 << pos) | (w1 >> (32u - pos)) : w0; }
+
+  // Consumes n <= 31 bits.
+  MJD_HD void consume(uint32_t n) {
+    used += n;
+    pos += n;
+    if (pos >= 32u) {
+      pos -= 32u;
+      w0 = w1;
+      w1 = next32();
+    }
+  }
+};
+
+// Decoding position of one lane inside its interval.
+struct LaneState {
+  uint32_t m = 0, n_mcus = 0;
+  int b = 0, k = 0;
+  int pred0 = 0, pred1 = 0, pred2 = 0;
+};
+
+// One symbol of the lane's interval.  Tab supplies
+//   uint32_t fast(int t, int i), int lim(int t, int l), int valoff(int t, int l),
+//   int val(int t, int i), int nat(int k)
+// (table t: DC of component t for t < 3, AC of component t - 3), and Blk
+//   void put(int natural_index, int value), void finish()  (store the block,
+//   clear the buffer for the next one).
+// comp_bits holds the component of block b of an MCU in bits 2b..2b+1.
+// Returns kRunning, kOk after the interval's last MCU, or the first error.
+// The step has one exit and computes every case with the same operations
+// where it can, so that lanes in different cases stay together.
+template <class Tab, class Blk, class Ring>
+MJD_HD inline uint32_t lane_step(const Tab& tab, Blk& blk, LaneBits<Ring>& br, LaneState& st, int bpm,
+                                 uint32_t comp_bits) {
+  if (!br.ring.ready(br.p, br.end)) return kRunning;  // wait for the next refill
+  const int comp = static_cast<int>((comp_bits >> (2 * st.b)) & 3u);
+  const bool dc = st.k == 0;
+  const int t = dc ? comp : 3 + comp;
+  const uint32_t top = br.peek32();
+  const uint32_t e = tab.fast(t, static_cast<int>(top >> (32 - kGLook)));
+  uint32_t len = e & 31u, sz = (e >> 5) & 15u, run = (e >> 9) & 15u;
+  bool bad = (e & kBadSym) != 0;
+  if (e == 0) {
+    // a code longer than kGLook bits: its length is one more than the
+    // number of left-aligned limits the next 16 bits reach
+    const int w = static_cast<int>(top >> 16);
+    int l = kGLook + 1;
+    for (int j = kGLook + 1; j <= 16; ++j) l += w >= tab.lim(t, j) ? 1 : 0;
+    const int lc = l > 16 ? 16 : l;
+    const int idx = (w >> (16 - lc)) + tab.valoff(t, lc);
+    const bool ok = l <= 16 && idx >= 0 && idx <= 255;
+    const uint32_t sym = ok ? static_cast<uint32_t>(tab.val(t, idx)) : 0u;
+    bad = !ok || (dc && sym > 11);
+    len = static_cast<uint32_t>(lc);
+    sz = sym & 15u;
+    run = dc ? 0u : sym >> 4;
+    if (dc && sym > 15) sz = 0;
+  }
+  // the magnitude bits follow the code inside the 32-bit window
+  const int raw = sz ? static_cast<int>((top << len) >> (32 - sz)) : 0;
+  const int half = static_cast<int>((1u << sz) >> 1);
+  int val = raw < half ? raw - 2 * half + 1 : raw;  // EXTEND (T.81 F.2.2.1)
+  br.consume(len + sz);
+  if (dc) {
+    // DC prediction per component (T.81 F.2.1.3), kept in three registers
+    // and chosen by masks (a select would become an indexed stack load)
+    const int m0 = -static_cast<int>(comp == 0), m1 = -static_cast<int>(comp == 1), m2 = -static_cast<int>(comp == 2);
+    const int p = ((st.pred0 & m0) | (st.pred1 & m1) | (st.pred2 & m2)) + val;
+    st.pred0 = (p & m0) | (st.pred0 & ~m0);
+    st.pred1 = (p & m1) | (st.pred1 & ~m1);
+    st.pred2 = (p & m2) | (st.pred2 & ~m2);
+    val = p;
+  }
+  // A coefficient lands at k + run.  EOB (size 0, run below 15) and ZRL
+  // (size 0, run 15) write a zero at a position not yet reached, which is
+  // still zero, so the store stays unconditional.
+  const bool skip = !dc && sz == 0;
+  const int kk = st.k + static_cast<int>(run);
+  blk.put(tab.nat(kk < 63 ? kk : 63), skip ? 0 : val);
+  const bool eob = skip && run != 15;
+  uint32_t status = bad ? kBadCode : (!skip && kk > 63) ? kBadRun : kRunning;
+  st.k = eob ? 64 : kk + 1;
+  if (status == kRunning && st.k >= 64) {
+    blk.finish();
+    st.k = 0;
+    if (++st.b == bpm) {
+      st.b = 0;
+      if (br.used > br.fed) status = kOverrun;
+      else if (++st.m == st.n_mcus) status = kOk;
+    }
+  }
+  return status;
+}
+
+// Every kRefillEvery steps the ring commits and restarts its loads.
+constexpr uint32_t kRefillEvery = 8;
+
+// Decodes interval iv of a stream whose bytes may be loaded up to `lim`
+// (its length rounded up to 16): the ring is filled (two chunks, waited
+// for) and the bit window primed, then one symbol per step until the last
+// MCU or an error.  A step either waits for data, which the next refill
+// brings, or advances the block position by at least one coefficient, so
+// the loop ends within about 64 + 8 steps per block.
+template <class Tab, class Blk, class Mem>
+MJD_HD inline uint32_t decode_interval(const Tab& tab, Blk& blk, Mem& mem, uint32_t lim, const Interval& iv, int bpm,
+                                       uint32_t comp_bits) {
+  StreamRing<Mem> ring(mem, lim, iv.start);
+  LaneBits<StreamRing<Mem>> br(ring, iv.start, iv.end);
+  ring.refill(iv.start);
+  ring.refill(iv.start);
+  br.prime();
+  LaneState st;
+  st.n_mcus = iv.n_mcus;
+  uint32_t s = iv.n_mcus ? kRunning : kOk;
+  for (uint32_t it = 1; s == kRunning; ++it) {
+    if (it % kRefillEvery == 0) ring.refill(br.p);
+    s = lane_step(tab, blk, br, st, bpm, comp_bits);
+  }
+  return s;
 }
 
 }  // namespace gent

@@ -23,28 +23,18 @@ namespace {
   exit(3);
 }
 
-struct CheckedEnv {
+struct CheckedTab {
   const GTables* tabs;
-  const uint8_t* jpg;
-  uint64_t lo, hi;  // the interval being decoded: reads stay in [lo, hi)
-  int16_t blk[64];
-  int16_t* coef;
-  uint64_t n_blocks;
-
-  uint32_t lut(int t, int i) const {
-    if (t < 0 || t > 5 || i < 0 || i >= (1 << kGLook)) out_of_range("lut");
-    return tabs->t[t].lut[i];
-  }
   uint32_t fast(int t, int i) const {
-    if (t < 3 || t > 5 || i < 0 || i >= (1 << kGLook)) out_of_range("fast");
+    if (t < 0 || t > 5 || i < 0 || i >= (1 << kGLook)) out_of_range("fast");
     return tabs->t[t].fast[i];
   }
-  int maxcode(int t, int l) const {
-    if (t < 0 || t > 5 || l < 1 || l > 17) out_of_range("maxcode");
-    return tabs->t[t].maxcode[l];
+  int lim(int t, int l) const {
+    if (t < 0 || t > 5 || l <= kGLook || l > 16) out_of_range("lim");
+    return tabs->t[t].lim[l];
   }
   int valoff(int t, int l) const {
-    if (t < 0 || t > 5 || l < 1 || l > 17) out_of_range("valoff");
+    if (t < 0 || t > 5 || l <= kGLook || l > 16) out_of_range("valoff");
     return tabs->t[t].valoff[l];
   }
   int val(int t, int i) const {
@@ -55,24 +45,49 @@ struct CheckedEnv {
     if (k < 0 || k > 63) out_of_range("nat");
     return tabs->nat[k];
   }
-  uint32_t byte(uint64_t p) const {
-    if (p < lo || p >= hi) out_of_range("byte");
-    return jpg[p];
-  }
-  uint32_t dword(uint64_t p) const {
-    if (p < lo || p + 4 > hi || (p & 3)) out_of_range("dword");
-    uint32_t d;
-    memcpy(&d, jpg + p, 4);
-    return d;
-  }
-  void blk_clear() { memset(blk, 0, sizeof(blk)); }
-  void blk_put(int i, int v) {
+};
+
+struct CheckedBlk {
+  int16_t buf[64];
+  int16_t* coef;
+  uint64_t block, n_blocks;
+  void put(int i, int v) {
     if (i < 0 || i > 63) out_of_range("block index");
-    blk[i] = static_cast<int16_t>(v);
+    buf[i] = static_cast<int16_t>(v);
   }
-  void blk_store(uint64_t b) {
-    if (b >= n_blocks) out_of_range("block store");
-    memcpy(coef + b * 64, blk, sizeof(blk));
+  void finish() {
+    if (block >= n_blocks) out_of_range("block store");
+    memcpy(coef + block * 64, buf, sizeof(buf));
+    memset(buf, 0, sizeof(buf));
+    ++block;
+  }
+};
+
+// Chunk loads must stay inside the stream rounded up to 16 bytes (the
+// buffer is padded with zeros to that length); ring accesses inside the
+// ring.
+struct CheckedMem {
+  const uint8_t* jpg;
+  uint32_t lim;
+  uint8_t ring[kRing];
+  uint8_t pend[2][16];
+  void g_chunk(uint32_t p, int slot) {
+    if ((p & 15) || p + 16 > lim || slot < 0 || slot > 1) out_of_range("chunk");
+    memcpy(pend[slot], jpg + p, 16);
+  }
+  void commit(int slot, uint32_t off) {
+    if ((off & 15) || off + 16 > kRing || slot < 0 || slot > 1) out_of_range("commit");
+    memcpy(ring + off, pend[slot], 16);
+  }
+  uint32_t r_byte(uint32_t off) const {
+    if (off >= kRing) out_of_range("ring byte");
+    return ring[off];
+  }
+  uint32_t r_dword(uint32_t off) const {
+    if ((off & 3) || off + 4 > kRing) out_of_range("ring dword");
+    uint32_t d;
+    memcpy(&d, ring + off, 4);
+    return d;
   }
 };
 
@@ -114,29 +129,34 @@ int main(int argc, char** argv) {
         if (r < 8 && c < 8) tabs[0].nat[k++] = static_cast<uint8_t>(8 * r + c);
       }
   }
-  uint8_t comp_of[8] = {0};
+  uint32_t comp_bits = 0;
   int bpm = 0;
   for (int c = 0; c < 3; ++c)
-    for (int i = 0; i < scan.frame.h[c] * scan.frame.v[c]; ++i) comp_of[bpm++] = static_cast<uint8_t>(c);
+    for (int i = 0; i < scan.frame.h[c] * scan.frame.v[c]; ++i) comp_bits |= static_cast<uint32_t>(c) << (2 * bpm++);
   const uint64_t n_mcus = static_cast<uint64_t>(g.mcus_x) * g.mcus_y;
   std::vector<int16_t> coef(g.n_blocks * 64, 0);
-  CheckedEnv env;
-  env.tabs = tabs.data();
-  env.jpg = jpg.data();
-  env.coef = coef.data();
-  env.n_blocks = g.n_blocks;
+  CheckedTab tab{tabs.data()};
   const uint64_t ri = scan.restart_interval ? scan.restart_interval : n_mcus;
+  std::vector<uint8_t> padded(jpg);
+  padded.resize((jpg.size() + 15) & ~size_t{15}, 0);
   uint32_t bad = 0;
   for (uint32_t s = 0; s < scan.n_intervals; ++s) {
     Interval iv;
-    iv.start = off[s];
-    iv.end = off[s + 1] - 2;
+    iv.start = static_cast<uint32_t>(off[s]);
+    iv.end = static_cast<uint32_t>(off[s + 1] - 2);
     iv.mcu0 = s * ri;
     iv.n_mcus = static_cast<uint32_t>(n_mcus - iv.mcu0 < ri ? n_mcus - iv.mcu0 : ri);
-    iv.job = 0;
-    env.lo = iv.start;
-    env.hi = iv.end;
-    if (decode_interval_lane(env, iv, bpm, comp_of) != kOk) ++bad;
+    iv.pad = 0;
+    CheckedBlk blk;
+    memset(blk.buf, 0, sizeof(blk.buf));
+    blk.coef = coef.data();
+    blk.block = iv.mcu0 * static_cast<uint64_t>(bpm);
+    blk.n_blocks = g.n_blocks;
+    CheckedMem mem;
+    mem.jpg = padded.data();
+    mem.lim = static_cast<uint32_t>(padded.size());
+    memset(mem.ring, 0xA5, sizeof(mem.ring));
+    if (decode_interval(tab, blk, mem, mem.lim, iv, bpm, comp_bits) != kOk) ++bad;
   }
   f = fopen(argv[2], "wb");
   if (!f || fwrite(coef.data(), 2, coef.size(), f) != coef.size()) return 2;

@@ -58,7 +58,9 @@ def streams():
 def device_job(M, data):
     scan, qt = M.mjd_parse(data)
     off = M.mjd_restart_index(data, scan)
-    d_jpg = torch.from_numpy(np.frombuffer(data, dtype=np.uint8).copy()).cuda()
+    # the kernel reads the stream in 16-byte chunks: pad the buffer to 16
+    d_jpg = torch.zeros(-(-len(data) // 16) * 16, dtype=torch.uint8, device="cuda")
+    d_jpg[:len(data)] = torch.from_numpy(np.frombuffer(data, dtype=np.uint8).copy()).cuda()
     n_blocks = M.mjd_geometry_of(M.scan_frame(scan))["n_blocks"]
     d_coef = torch.full((n_blocks * 64,), SENTINEL, dtype=torch.int16, device="cuda")
     return (scan, off, d_jpg, len(data), d_coef), qt
