@@ -115,7 +115,6 @@ struct DevMem {
     else c0 = v;
   }
   __device__ void commit(int slot, uint32_t off) { *reinterpret_cast<lds128*>(ring + swz(off, rot)) = slot ? c1 : c0; }
-  __device__ uint32_t r_byte(uint32_t off) const { return ring[swz(off, rot)]; }
   __device__ uint32_t r_dword(uint32_t off) const { return *reinterpret_cast<const lds32*>(ring + swz(off, rot)); }
 };
 

@@ -113,7 +113,7 @@ inline int build_gtable(const mjd_huffman& h, bool ac, GHuff* t) {
 //                                        [p, p + 16) (p a multiple of 16)
 //                                        into slot 0/1
 //   void commit(int slot, uint32_t off)  put that chunk in the ring at off
-//   uint32_t r_byte(uint32_t off), r_dword(uint32_t off)   ring reads
+//   uint32_t r_dword(uint32_t off)       ring read (off a multiple of 4)
 // refill(p) commits the chunks the previous refill loaded and starts up to
 // two more, each only where the ring bytes it will overwrite lie below p,
 // the next byte the reader needs.  Chunks are loaded while they start
@@ -131,12 +131,12 @@ struct StreamRing {
 
   MJD_HD StreamRing(Mem& m, uint32_t lim_, uint32_t start) : mem(m), lim(lim_) { lo = have = start & ~15u; }
 
-  MJD_HD uint32_t byte(uint32_t p) { return mem.r_byte(p % kRing); }
-
-  // Stream bytes [a, a + 8) as two little-endian words (a a multiple of 4).
-  MJD_HD void pair(uint32_t a, uint32_t& d0, uint32_t& d1) {
+  // Stream bytes [a, a + 12) as three little-endian words (a a multiple of
+  // 4); bytes the ring does not hold yet come back stale and are not used.
+  MJD_HD void triple(uint32_t a, uint32_t& d0, uint32_t& d1, uint32_t& d2) {
     d0 = mem.r_dword(a % kRing);
     d1 = mem.r_dword((a + 4) % kRing);
+    d2 = mem.r_dword((a + 8) % kRing);
   }
 
   // The ring holds every byte one refill of the bit window can read: eight
@@ -177,52 +177,49 @@ MJD_HD inline uint32_t be32_at(uint32_t d0, uint32_t d1, uint32_t sh) {
 #endif
 }
 
-// Bit reader over [p, end): MSB-first window w0:w1 with `pos` bits of w0
+// Byte x (0..11) of the little-endian words d0, d1, d2.
+MJD_HD inline uint32_t byte_of3(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t x) {
+  const uint32_t w = x < 4 ? d0 : (x < 8 ? d1 : d2);
+  return (w >> (8 * (x & 3u))) & 0xFFu;
+}
+
+// Bit reader over [p, end): MSB-first window w0:w1:w2 with `pos` bits of w0
 // used; stuffed 0x00 after 0xFF dropped; at a marker or at `end` it feeds
 // zero bits.  `fed` counts real bits and `used` consumed bits, so used > fed
-// means the interval ran out of data.
+// means the interval ran out of data.  The next stream words (at p) are read
+// from the ring at the start of every step, beside the table lookup, and
+// used when the step's bits cross into w1.
 template <class Ring>
 struct LaneBits {
   Ring& ring;
   uint32_t p, end;
-  uint32_t w0 = 0, w1 = 0;
+  uint32_t w0 = 0, w1 = 0, w2 = 0;
   uint32_t pos = 0;
   uint32_t fed = 0, used = 0;
   bool stop = false;
 
   MJD_HD LaneBits(Ring& r, uint32_t start, uint32_t end_) : ring(r), p(start), end(end_) {}
 
+  MJD_HD void fetch(uint32_t& d0, uint32_t& d1, uint32_t& d2) { ring.triple(p & ~3u, d0, d1, d2); }
+
   MJD_HD void prime() {
-    w0 = next32();
-    w1 = next32();
+    uint32_t d0, d1, d2;
+    fetch(d0, d1, d2);
+    w0 = next32(d0, d1, d2);
+    fetch(d0, d1, d2);
+    w1 = next32(d0, d1, d2);
+    fetch(d0, d1, d2);
+    w2 = next32(d0, d1, d2);
   }
 
-  MJD_HD uint32_t next_byte() {
-    if (stop || p >= end) {
-      stop = true;
-      return 0;
-    }
-    const uint32_t b = ring.byte(p++);
-    if (b == 0xFF) {
-      if (p < end && ring.byte(p) == 0x00) {
-        ++p;
-        fed += 8;
-        return 0xFF;
-      }
-      stop = true;
-      return 0;
-    }
-    fed += 8;
-    return b;
-  }
-
-  // The next 32 stream bits, MSB first: four bytes at once wherever none
-  // of them is 0xFF, whatever the alignment.
-  MJD_HD uint32_t next32() {
+  // The next 32 stream bits, MSB first, from the words read at p & ~3:
+  // four bytes at once wherever none of them is 0xFF, else byte by byte
+  // without branches (stuffed zeros dropped; a marker or `end` stops the
+  // stream).
+  MJD_HD uint32_t next32(uint32_t d0, uint32_t d1, uint32_t d2) {
+    const uint32_t sh = p & 3u;
     if (!stop && p + 4 <= end) {
-      uint32_t d0, d1;
-      ring.pair(p & ~3u, d0, d1);
-      const uint32_t d = be32_at(d0, d1, p & 3u);
+      const uint32_t d = be32_at(d0, d1, sh);
       const uint32_t x = ~d;  // 0xFF bytes become zero bytes
       if (((x - 0x01010101u) & ~x & 0x80808080u) == 0) {
         p += 4;
@@ -230,25 +227,35 @@ struct LaneBits {
         return d;
       }
     }
-    uint32_t r = 0;
-#if defined(__HIP_DEVICE_COMPILE__)
-#pragma unroll 1
-#endif
-    for (int i = 0; i < 4; ++i) r = (r << 8) | next_byte();
+    uint32_t r = 0, q = p;
+    bool st = stop;
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t o = q - (p & ~3u);  // at most 3 + 6
+      const uint32_t b = byte_of3(d0, d1, d2, o), nb = byte_of3(d0, d1, d2, o + 1);
+      const bool ff = b == 0xFFu;
+      const bool stuffed = ff && q + 1 < end && nb == 0;
+      st = st || q >= end || (ff && !stuffed);
+      r = (r << 8) | (st ? 0u : b);
+      q += st ? 0u : (stuffed ? 2u : 1u);
+      fed += st ? 0u : 8u;
+    }
+    p = q;
+    stop = st;
     return r;
   }
 
-  // The next 32 bits of the window (at least 33 are held), not consumed.
+  // The next 32 bits of the window, not consumed.
   MJD_HD uint32_t peek32() const { return pos ? (w0 << pos) | (w1 >> (32u - pos)) : w0; }
 
-  // Consumes n <= 31 bits.
-  MJD_HD void consume(uint32_t n) {
+  // Consumes n <= 31 bits; d0..d2 are the words fetch() read this step.
+  MJD_HD void consume(uint32_t n, uint32_t d0, uint32_t d1, uint32_t d2) {
     used += n;
     pos += n;
     if (pos >= 32u) {
       pos -= 32u;
       w0 = w1;
-      w1 = next32();
+      w1 = w2;
+      w2 = next32(d0, d1, d2);
     }
   }
 };
@@ -277,6 +284,8 @@ MJD_HD inline uint32_t lane_step(const Tab& tab, Blk& blk, LaneBits<Ring>& br, L
   const int comp = static_cast<int>((comp_bits >> (2 * st.b)) & 3u);
   const bool dc = st.k == 0;
   const int t = dc ? comp : 3 + comp;
+  uint32_t d0, d1, d2;
+  br.fetch(d0, d1, d2);
   const uint32_t top = br.peek32();
   const uint32_t e = tab.fast(t, static_cast<int>(top >> (32 - kGLook)));
   uint32_t len = e & 31u, sz = (e >> 5) & 15u, run = (e >> 9) & 15u;
@@ -301,7 +310,7 @@ MJD_HD inline uint32_t lane_step(const Tab& tab, Blk& blk, LaneBits<Ring>& br, L
   const int raw = sz ? static_cast<int>((top << len) >> (32 - sz)) : 0;
   const int half = static_cast<int>((1u << sz) >> 1);
   int val = raw < half ? raw - 2 * half + 1 : raw;  // EXTEND (T.81 F.2.2.1)
-  br.consume(len + sz);
+  br.consume(len + sz, d0, d1, d2);
   if (dc) {
     // DC prediction per component (T.81 F.2.1.3), kept in three registers
     // and chosen by masks (a select would become an indexed stack load)
@@ -337,8 +346,8 @@ MJD_HD inline uint32_t lane_step(const Tab& tab, Blk& blk, LaneBits<Ring>& br, L
 constexpr uint32_t kRefillEvery = 8;
 
 // Decodes interval iv of a stream whose bytes may be loaded up to `lim`
-// (its length rounded up to 16): the ring is filled (two chunks, waited
-// for) and the bit window primed, then one symbol per step until the last
+// (its length rounded up to 16): the ring is filled (four chunks, two waits)
+// and the bit window primed, then one symbol per step until the last
 // MCU or an error.  A step either waits for data, which the next refill
 // brings, or advances the block position by at least one coefficient, so
 // the loop ends within about 64 + 8 steps per block.
@@ -347,6 +356,7 @@ MJD_HD inline uint32_t decode_interval(const Tab& tab, Blk& blk, Mem& mem, uint3
                                        uint32_t comp_bits) {
   StreamRing<Mem> ring(mem, lim, iv.start);
   LaneBits<StreamRing<Mem>> br(ring, iv.start, iv.end);
+  ring.refill(iv.start);
   ring.refill(iv.start);
   ring.refill(iv.start);
   br.prime();

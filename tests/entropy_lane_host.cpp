@@ -79,10 +79,6 @@ struct CheckedMem {
     if ((off & 15) || off + 16 > kRing || slot < 0 || slot > 1) out_of_range("commit");
     memcpy(ring + off, pend[slot], 16);
   }
-  uint32_t r_byte(uint32_t off) const {
-    if (off >= kRing) out_of_range("ring byte");
-    return ring[off];
-  }
   uint32_t r_dword(uint32_t off) const {
     if ((off & 3) || off + 4 > kRing) out_of_range("ring dword");
     uint32_t d;
