@@ -34,7 +34,7 @@ struct GJob {
   uint32_t lim;        // stream bytes, rounded up to 16 (chunk loads stay below)
   int32_t bpm;         // blocks per MCU
   uint32_t comp_bits;  // component of block b of an MCU in bits 2b..2b+1
-  uint32_t pad;
+  uint32_t tsel;       // table slots of each component (plan_gtables)
 };
 
 struct GItem {
@@ -44,14 +44,17 @@ struct GItem {
 constexpr int kThreads = 256;
 constexpr uint64_t kMaxStream = 0xFFFFFF00u;  // stream offsets are 32-bit
 
-static int table_for(const mjd_huffman& h, bool ac, GHuff* t) {
-  switch (build_gtable(h, ac, t)) {
+static int tables_for(const mjd_scan& scan, GTables* g, uint32_t* tsel) {
+  switch (plan_gtables(scan, g, tsel)) {
     case kTableOk:
       return MJD_OK;
     case kTableUndefined:
       return fail(MJD_ECORRUPT, "scan uses an undefined Huffman table");
     case kTableTooMany:
       return fail(MJD_ECORRUPT, "Huffman table with more than 256 symbols");
+    case kPlanTooManyTables:
+      return fail(MJD_EUNSUPPORTED, "scan uses more than %d distinct Huffman tables (baseline uses at most 4); "
+                                    "decode it on the host", kTableSlots);
     default:
       return fail(MJD_ECORRUPT, "Huffman code lengths overfill the code space");
   }
@@ -78,10 +81,14 @@ struct DevTab {
   __device__ int nat(int k) const { return natural[k]; }
 };
 
-// Per-lane LDS buffers of 128 bytes sit 128 bytes apart, so their 16-byte
-// chunks are rotated by the lane number: the lanes of a wave then spread a
-// 16-byte access at the same offset over all banks.
-__device__ inline uint32_t swz(uint32_t off, uint32_t rot) { return (((off >> 4) + rot) & 7u) << 4 | (off & 15u); }
+// Per-lane LDS buffers (128-byte blocks, kRing-byte rings) sit one buffer
+// apart, so their 16-byte chunks are rotated by the lane number: the lanes
+// of a wave then spread a 16-byte access at the same offset over the banks.
+template <uint32_t kBytes>
+__device__ inline uint32_t swz(uint32_t off, uint32_t rot) {
+  static_assert(kBytes >= 16 && (kBytes & (kBytes - 1)) == 0, "buffers of a power-of-two number of chunks");
+  return (((off >> 4) + rot) & (kBytes / 16 - 1)) << 4 | (off & 15u);
+}
 
 // The block being decoded: 128 bytes of LDS per lane, stored whole (eight
 // 16-byte stores) to the next block of the interval and cleared.
@@ -90,11 +97,11 @@ struct DevBlk {
   gout128* dst;
   uint32_t rot;
   __device__ void put(int idx, int v) {
-    *reinterpret_cast<lds16*>(buf + swz(static_cast<uint32_t>(idx) * 2, rot)) = static_cast<uint16_t>(v);
+    *reinterpret_cast<lds16*>(buf + swz<128>(static_cast<uint32_t>(idx) * 2, rot)) = static_cast<uint16_t>(v);
   }
   __device__ void finish() {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) dst[i] = *reinterpret_cast<lds128*>(buf + swz(16u * i, rot));
+    for (int i = 0; i < 8; ++i) dst[i] = *reinterpret_cast<lds128*>(buf + swz<128>(16u * i, rot));
 #pragma unroll
     for (int i = 0; i < 8; ++i) reinterpret_cast<lds128*>(buf)[i] = v4i_t{0, 0, 0, 0};
     dst += 8;
@@ -114,8 +121,8 @@ struct DevMem {
     if (slot) c1 = v;
     else c0 = v;
   }
-  __device__ void commit(int slot, uint32_t off) { *reinterpret_cast<lds128*>(ring + swz(off, rot)) = slot ? c1 : c0; }
-  __device__ uint32_t r_dword(uint32_t off) const { return *reinterpret_cast<const lds32*>(ring + swz(off, rot)); }
+  __device__ void commit(int slot, uint32_t off) { *reinterpret_cast<lds128*>(ring + swz<kRing>(off, rot)) = slot ? c1 : c0; }
+  __device__ uint32_t r_dword(uint32_t off) const { return *reinterpret_cast<const lds32*>(ring + swz<kRing>(off, rot)); }
 };
 
 __global__ __launch_bounds__(kThreads) void entropy_kernel(const GJob* __restrict__ jobs,
@@ -155,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void entropy_kernel(const GJob* __restric
       const uint32_t rot = static_cast<uint32_t>(tid) & 7u;
       DevBlk blk{(lds8*)blocks + tid * 128, (gout128*)(jb.coef + iv.mcu0 * static_cast<uint64_t>(jb.bpm) * 64), rot};
       DevMem mem{(gin8*)jb.jpg, (lds8*)rings + tid * kRing, rot, v4i_t{0, 0, 0, 0}, v4i_t{0, 0, 0, 0}};
-      const uint32_t st = decode_interval(tab, blk, mem, jb.lim, iv, jb.bpm, jb.comp_bits);
+      const uint32_t st = decode_interval(tab, blk, mem, jb.lim, iv, jb.bpm, jb.comp_bits, jb.tsel);
       if (st != kOk) {  // leave the block buffer clear for the next interval
         lds128* b = reinterpret_cast<lds128*>(blk.buf);
 #pragma unroll
@@ -229,13 +236,10 @@ static int build(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n, mjd_entrop
       return fail(rc, "job %zu: %s", j, why.c_str());
     }
     if (L.bpm > 8) return fail(MJD_EINVAL, "job %zu: %d blocks per MCU", j, L.bpm);
-    for (int c = 0; c < 3; ++c) {
-      rc = table_for(J.scan->dc[J.scan->dc_sel[c]], false, &gt[j].t[c]);
-      if (rc == MJD_OK) rc = table_for(J.scan->ac[J.scan->ac_sel[c]], true, &gt[j].t[3 + c]);
-      if (rc != MJD_OK) {
-        const std::string why = mjd_last_error();
-        return fail(rc, "job %zu: %s", j, why.c_str());
-      }
+    rc = tables_for(*J.scan, &gt[j], &gj[j].tsel);
+    if (rc != MJD_OK) {
+      const std::string why = mjd_last_error();
+      return fail(rc, "job %zu: %s", j, why.c_str());
     }
     memcpy(gt[j].nat, host::zigzag_to_natural(), 64);
     gj[j].jpg = J.d_jpg;

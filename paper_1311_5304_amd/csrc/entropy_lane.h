@@ -64,10 +64,13 @@ struct GHuff {
   uint8_t pad[8];
 };
 
-// A scan's tables: DC of components 0..2, then AC of components 0..2, and
-// the zig-zag map.
+// A scan's distinct tables in up to four slots (a baseline scan uses at
+// most two DC and two AC tables, T.81 B.2.4.2) and the zig-zag map.  The
+// slot of each component's tables is packed in a word, four bits per
+// component: DC slot in bits 4c..4c+1, AC slot in bits 4c+2..4c+3.
+constexpr int kTableSlots = 4;
 struct GTables {
-  GHuff t[6];
+  GHuff t[kTableSlots];
   uint8_t nat[64];  // natural index of zig-zag position k
 };
 static_assert(sizeof(GHuff) % 16 == 0 && sizeof(GTables) % 16 == 0, "tables copy as 16-byte chunks");
@@ -107,6 +110,37 @@ inline int build_gtable(const mjd_huffman& h, bool ac, GHuff* t) {
   return kTableOk;
 }
 
+enum : int { kPlanTooManyTables = 4 };
+
+// Builds the distinct tables a scan selects into slots and returns their
+// component map in *tsel; kTableOk or the first table error, or
+// kPlanTooManyTables when the scan needs more than kTableSlots tables.
+inline int plan_gtables(const mjd_scan& scan, GTables* g, uint32_t* tsel) {
+  memset(g, 0, sizeof(*g));
+  int key[kTableSlots];
+  int n = 0;
+  uint32_t sel = 0;
+  for (int c = 0; c < 3; ++c) {
+    for (int ac = 0; ac < 2; ++ac) {
+      const int id = ac ? scan.ac_sel[c] : scan.dc_sel[c];
+      const int k = ac * 4 + id;
+      int slot = -1;
+      for (int i = 0; i < n; ++i)
+        if (key[i] == k) slot = i;
+      if (slot < 0) {
+        if (n == kTableSlots) return kPlanTooManyTables;
+        const int rc = build_gtable(ac ? scan.ac[id] : scan.dc[id], ac != 0, &g->t[n]);
+        if (rc != kTableOk) return rc;
+        key[n] = k;
+        slot = n++;
+      }
+      sel |= static_cast<uint32_t>(slot) << (4 * c + 2 * ac);
+    }
+  }
+  *tsel = sel;
+  return kTableOk;
+}
+
 // Stream bytes of one lane, all read from a ring of kRing bytes that holds
 // stream bytes [lo, have) at offsets p % kRing.  Mem supplies
 //   void g_chunk(uint32_t p, int slot)   start loading stream bytes
@@ -120,7 +154,7 @@ inline int build_gtable(const mjd_huffman& h, bool ac, GHuff* t) {
 // below `lim`, the stream length rounded up to 16.  The reader never reads
 // the stream directly: a lane whose ring lacks the next bytes waits for the
 // next refill (ready()).
-constexpr uint32_t kRing = 128;
+constexpr uint32_t kRing = 32;
 
 template <class Mem>
 struct StreamRing {
@@ -183,7 +217,7 @@ MJD_HD inline uint32_t byte_of3(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t 
   return (w >> (8 * (x & 3u))) & 0xFFu;
 }
 
-// Bit reader over [p, end): MSB-first window w0:w1:w2 with `pos` bits of w0
+// Bit reader over [p, end): MSB-first window w0:w1 with `pos` bits of w0
 // used; stuffed 0x00 after 0xFF dropped; at a marker or at `end` it feeds
 // zero bits.  `fed` counts real bits and `used` consumed bits, so used > fed
 // means the interval ran out of data.  The next stream words (at p) are read
@@ -193,7 +227,7 @@ template <class Ring>
 struct LaneBits {
   Ring& ring;
   uint32_t p, end;
-  uint32_t w0 = 0, w1 = 0, w2 = 0;
+  uint32_t w0 = 0, w1 = 0;
   uint32_t pos = 0;
   uint32_t fed = 0, used = 0;
   bool stop = false;
@@ -208,8 +242,6 @@ struct LaneBits {
     w0 = next32(d0, d1, d2);
     fetch(d0, d1, d2);
     w1 = next32(d0, d1, d2);
-    fetch(d0, d1, d2);
-    w2 = next32(d0, d1, d2);
   }
 
   // The next 32 stream bits, MSB first, from the words read at p & ~3:
@@ -244,7 +276,7 @@ struct LaneBits {
     return r;
   }
 
-  // The next 32 bits of the window, not consumed.
+  // The next 32 bits of the window (at least 33 are held), not consumed.
   MJD_HD uint32_t peek32() const { return pos ? (w0 << pos) | (w1 >> (32u - pos)) : w0; }
 
   // Consumes n <= 31 bits; d0..d2 are the words fetch() read this step.
@@ -254,8 +286,7 @@ struct LaneBits {
     if (pos >= 32u) {
       pos -= 32u;
       w0 = w1;
-      w1 = w2;
-      w2 = next32(d0, d1, d2);
+      w1 = next32(d0, d1, d2);
     }
   }
 };
@@ -270,20 +301,21 @@ struct LaneState {
 // One symbol of the lane's interval.  Tab supplies
 //   uint32_t fast(int t, int i), int lim(int t, int l), int valoff(int t, int l),
 //   int val(int t, int i), int nat(int k)
-// (table t: DC of component t for t < 3, AC of component t - 3), and Blk
+// (t: a table slot), and Blk
 //   void put(int natural_index, int value), void finish()  (store the block,
 //   clear the buffer for the next one).
-// comp_bits holds the component of block b of an MCU in bits 2b..2b+1.
+// comp_bits holds the component of block b of an MCU in bits 2b..2b+1 and
+// tsel the table slots of each component (plan_gtables).
 // Returns kRunning, kOk after the interval's last MCU, or the first error.
 // The step has one exit and computes every case with the same operations
 // where it can, so that lanes in different cases stay together.
 template <class Tab, class Blk, class Ring>
 MJD_HD inline uint32_t lane_step(const Tab& tab, Blk& blk, LaneBits<Ring>& br, LaneState& st, int bpm,
-                                 uint32_t comp_bits) {
+                                 uint32_t comp_bits, uint32_t tsel) {
   if (!br.ring.ready(br.p, br.end)) return kRunning;  // wait for the next refill
   const int comp = static_cast<int>((comp_bits >> (2 * st.b)) & 3u);
   const bool dc = st.k == 0;
-  const int t = dc ? comp : 3 + comp;
+  const int t = static_cast<int>((tsel >> (4 * comp + (dc ? 0 : 2))) & 3u);
   uint32_t d0, d1, d2;
   br.fetch(d0, d1, d2);
   const uint32_t top = br.peek32();
@@ -343,20 +375,19 @@ MJD_HD inline uint32_t lane_step(const Tab& tab, Blk& blk, LaneBits<Ring>& br, L
 }
 
 // Every kRefillEvery steps the ring commits and restarts its loads.
-constexpr uint32_t kRefillEvery = 8;
+constexpr uint32_t kRefillEvery = 4;
 
 // Decodes interval iv of a stream whose bytes may be loaded up to `lim`
-// (its length rounded up to 16): the ring is filled (four chunks, two waits)
-// and the bit window primed, then one symbol per step until the last
+// (its length rounded up to 16): the ring is filled (two chunks, waited
+// for) and the bit window primed, then one symbol per step until the last
 // MCU or an error.  A step either waits for data, which the next refill
 // brings, or advances the block position by at least one coefficient, so
 // the loop ends within about 64 + 8 steps per block.
 template <class Tab, class Blk, class Mem>
 MJD_HD inline uint32_t decode_interval(const Tab& tab, Blk& blk, Mem& mem, uint32_t lim, const Interval& iv, int bpm,
-                                       uint32_t comp_bits) {
+                                       uint32_t comp_bits, uint32_t tsel) {
   StreamRing<Mem> ring(mem, lim, iv.start);
   LaneBits<StreamRing<Mem>> br(ring, iv.start, iv.end);
-  ring.refill(iv.start);
   ring.refill(iv.start);
   ring.refill(iv.start);
   br.prime();
@@ -365,7 +396,7 @@ MJD_HD inline uint32_t decode_interval(const Tab& tab, Blk& blk, Mem& mem, uint3
   uint32_t s = iv.n_mcus ? kRunning : kOk;
   for (uint32_t it = 1; s == kRunning; ++it) {
     if (it % kRefillEvery == 0) ring.refill(br.p);
-    s = lane_step(tab, blk, br, st, bpm, comp_bits);
+    s = lane_step(tab, blk, br, st, bpm, comp_bits, tsel);
   }
   return s;
 }

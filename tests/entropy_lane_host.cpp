@@ -26,19 +26,19 @@ namespace {
 struct CheckedTab {
   const GTables* tabs;
   uint32_t fast(int t, int i) const {
-    if (t < 0 || t > 5 || i < 0 || i >= (1 << kGLook)) out_of_range("fast");
+    if (t < 0 || t >= kTableSlots || i < 0 || i >= (1 << kGLook)) out_of_range("fast");
     return tabs->t[t].fast[i];
   }
   int lim(int t, int l) const {
-    if (t < 0 || t > 5 || l <= kGLook || l > 16) out_of_range("lim");
+    if (t < 0 || t >= kTableSlots || l <= kGLook || l > 16) out_of_range("lim");
     return tabs->t[t].lim[l];
   }
   int valoff(int t, int l) const {
-    if (t < 0 || t > 5 || l <= kGLook || l > 16) out_of_range("valoff");
+    if (t < 0 || t >= kTableSlots || l <= kGLook || l > 16) out_of_range("valoff");
     return tabs->t[t].valoff[l];
   }
   int val(int t, int i) const {
-    if (t < 0 || t > 5 || i < 0 || i > 255) out_of_range("val");
+    if (t < 0 || t >= kTableSlots || i < 0 || i > 255) out_of_range("val");
     return tabs->t[t].vals[i];
   }
   int nat(int k) const {
@@ -110,12 +110,11 @@ int main(int argc, char** argv) {
     return 2;
   }
   std::vector<GTables> tabs(1);
-  for (int c = 0; c < 3; ++c)
-    if (build_gtable(scan.dc[scan.dc_sel[c]], false, &tabs[0].t[c]) != kTableOk ||
-        build_gtable(scan.ac[scan.ac_sel[c]], true, &tabs[0].t[3 + c]) != kTableOk) {
-      fprintf(stderr, "bad Huffman table\n");
-      return 2;
-    }
+  uint32_t tsel = 0;
+  if (plan_gtables(scan, tabs.data(), &tsel) != kTableOk) {
+    fprintf(stderr, "bad Huffman tables\n");
+    return 2;
+  }
   // zig-zag position -> natural index, walking the anti-diagonals
   {
     int k = 0;
@@ -152,7 +151,7 @@ int main(int argc, char** argv) {
     mem.jpg = padded.data();
     mem.lim = static_cast<uint32_t>(padded.size());
     memset(mem.ring, 0xA5, sizeof(mem.ring));
-    if (decode_interval(tab, blk, mem, mem.lim, iv, bpm, comp_bits) != kOk) ++bad;
+    if (decode_interval(tab, blk, mem, mem.lim, iv, bpm, comp_bits, tsel) != kOk) ++bad;
   }
   f = fopen(argv[2], "wb");
   if (!f || fwrite(coef.data(), 2, coef.size(), f) != coef.size()) return 2;
