@@ -4,8 +4,9 @@
 // - it checks every job;
 // - it builds each job's Huffman tables in the layout the kernel copies to
 //   LDS;
-// - it lists the restart intervals, and cuts each job's list into items of
-//   at most 256 intervals, so an item never spans two jobs.
+// - it lists the restart intervals, sorts each job's list by length, and
+//   cuts it into items of at most 256 intervals, so an item never spans two
+//   jobs; items go longest first.
 // A persistent kernel pops items from a device counter. A workgroup loads
 // the tables of the item's job into LDS (only when the job changes). Each
 // lane then decodes one interval with the bit reader and block decoder of
@@ -38,7 +39,8 @@ struct GJob {
 };
 
 struct GItem {
-  uint32_t job, first, count, pad;
+  uint32_t job, first, count;
+  uint32_t bytes;  // stream bytes of its longest interval
 };
 
 constexpr int kThreads = 256;
@@ -198,6 +200,7 @@ struct mjd_entropy_batch {
   uint32_t* d_status = nullptr;
   unsigned* d_counters = nullptr;
   std::vector<uint32_t> first_interval;  // per job, into the interval list
+  std::vector<uint32_t> iv_index;        // per listed interval, its number in its scan
   uint64_t pixels = 0, bytes = 0;
 };
 
@@ -259,17 +262,31 @@ static int build(mjd_ctx* ctx, const mjd_entropy_job* jobs, size_t n, mjd_entrop
       Interval iv;
       iv.start = static_cast<uint32_t>(off[s]);
       iv.end = static_cast<uint32_t>(off[s + 1] - 2);
-      iv.pad = 0;
+      iv.index = s;
       iv.mcu0 = s * ri;
       iv.n_mcus = static_cast<uint32_t>(std::min<uint64_t>(ri, L.n_mcus - iv.mcu0));
       ivs.push_back(iv);
     }
-    for (uint32_t s = 0; s < ni; s += kThreads)
-      items.push_back(GItem{static_cast<uint32_t>(j), b->first_interval[j] + s, std::min<uint32_t>(kThreads, ni - s), 0});
+    // A lane's decode time follows its interval's length, and a wave (and a
+    // workgroup) lasts as long as its longest interval: sort the job's
+    // intervals longest first so that each item holds intervals of similar
+    // length.
+    const auto first = ivs.begin() + b->first_interval[j];
+    std::stable_sort(first, ivs.end(),
+                     [](const Interval& x, const Interval& y) { return x.end - x.start > y.end - y.start; });
+    for (uint32_t s = 0; s < ni; s += kThreads) {
+      const Interval& lead = ivs[b->first_interval[j] + s];
+      items.push_back(GItem{static_cast<uint32_t>(j), b->first_interval[j] + s, std::min<uint32_t>(kThreads, ni - s),
+                            lead.end - lead.start});
+    }
     b->pixels += static_cast<uint64_t>(J.scan->frame.width) * J.scan->frame.height;
     b->bytes += J.len;
     if (ivs.size() > 0x7FFFFFF0u) return fail(MJD_EINVAL, "entropy batch holds too many intervals");
   }
+  // longest items first, so that the last ones to start are short
+  std::stable_sort(items.begin(), items.end(), [](const GItem& x, const GItem& y) { return x.bytes > y.bytes; });
+  b->iv_index.resize(ivs.size());
+  for (size_t i = 0; i < ivs.size(); ++i) b->iv_index[i] = ivs[i].index;
   b->n_jobs = static_cast<uint32_t>(n);
   b->n_intervals = static_cast<uint32_t>(ivs.size());
   b->n_items = static_cast<uint32_t>(items.size());
@@ -357,7 +374,7 @@ int mjd_entropy_batch_status(mjd_entropy_batch* b, int64_t* bad_job) {
     static const char* what[] = {"", "an invalid Huffman code", "a coefficient run past the end of a block",
                                  "an interval that ends before its last MCU"};
     return mjd::fail(MJD_ECORRUPT, "job %lld, restart interval %u: %s", static_cast<long long>(job),
-                     i - b->first_interval[static_cast<size_t>(job)], what[st[i] < 4 ? st[i] : 1]);
+                     b->iv_index[i], what[st[i] < 4 ? st[i] : 1]);
   }
   return MJD_OK;
 }

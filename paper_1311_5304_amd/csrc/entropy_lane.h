@@ -43,7 +43,7 @@ enum : uint32_t { kOk = 0, kBadCode = 1, kBadRun = 2, kOverrun = 3, kRunning = 4
 struct Interval {
   uint32_t start, end;
   uint32_t n_mcus;
-  uint32_t pad;
+  uint32_t index;  // interval number within its scan
   uint64_t mcu0;
 };
 

@@ -141,7 +141,7 @@ int main(int argc, char** argv) {
     iv.end = static_cast<uint32_t>(off[s + 1] - 2);
     iv.mcu0 = s * ri;
     iv.n_mcus = static_cast<uint32_t>(n_mcus - iv.mcu0 < ri ? n_mcus - iv.mcu0 : ri);
-    iv.pad = 0;
+    iv.index = s;
     CheckedBlk blk;
     memset(blk.buf, 0, sizeof(blk.buf));
     blk.coef = coef.data();
