@@ -154,6 +154,68 @@ def test_corrupt_job_is_reported_and_others_decode(M, ctx, streams):
     b.close()
 
 
+def _segments(d):
+    out, i = [], 2
+    while i < len(d):
+        m, L = d[i + 1], d[i + 2] << 8 | d[i + 3]
+        out.append((m, i, L))
+        if m == 0xDA:
+            break
+        i += 2 + L
+    return out
+
+
+def _six_tables(d):
+    """The same scan with its third component on copies (id 2) of the chroma
+    DC and AC tables: six distinct tables, valid for the host decoder."""
+    segs = _segments(d)
+    extra = b""
+    for m, i, L in segs:
+        if m == 0xC4 and d[i + 4] in (0x01, 0x11):
+            pay = bytearray(d[i + 4:i + 2 + L])
+            pay[0] = (pay[0] & 0xF0) | 2
+            extra += b"\xFF\xC4" + (len(pay) + 2).to_bytes(2, "big") + bytes(pay)
+    m, i, L = segs[-1]
+    sos = bytearray(d[i:i + 2 + L])
+    sos[10] = 0x22  # component 3: DC 2, AC 2
+    return d[:i] + extra + bytes(sos) + d[i + 2 + L:]
+
+
+def test_dense_random_streams(M, ctx):
+    """Random large coefficients: long codes, many stuffed bytes and dense
+    intervals in which lanes outrun their stream ring and wait for it."""
+    rng = np.random.default_rng(17)
+    qt = np.ones((4, 64), dtype=np.uint16)
+    jobs, exp = [], []
+    for samp, w, h, ri in (("420", 160, 96, 1), ("422", 120, 40, 3), ("444", 72, 56, 0), ("420", 200, 120, 2)):
+        fr = encode.make_frame(w, h, samp)
+        nb = oracle.geometry(fr)["n_blocks"]
+        size = np.minimum(rng.geometric(0.3, size=(nb, 64)), 10)
+        mag = (1 << (size - 1)) + (rng.random((nb, 64)) * (1 << (size - 1))).astype(np.int64)
+        c = np.where(rng.random((nb, 64)) < 0.5, -mag, mag).astype(np.int16)
+        c[:, 0] = rng.integers(-1023, 1024, size=nb)
+        c[rng.random((nb, 64)) < 0.2] = 0
+        data = bitstream.write_jpeg(fr, c, qt, restart_interval=ri)
+        assert data.count(b"\xFF\x00") > 10
+        jobs.append(device_job(M, data)[0])
+        exp.append(c)
+    b = M.EntropyBatch(ctx, jobs)
+    b.launch()
+    b.status()
+    for j, c in zip(jobs, exp):
+        assert np.array_equal(j[4].cpu().numpy().reshape(-1, 64), c)
+    b.close()
+
+
+def test_scan_with_more_than_four_tables_is_refused(M, ctx, streams):
+    data = _six_tables(streams[0][3])
+    scan, _ = M.mjd_parse(data)
+    assert len({(0, x) for x in scan.dc_sel} | {(1, x) for x in scan.ac_sel}) == 6
+    with pytest.raises(M.MjdError) as ei:
+        M.EntropyBatch(ctx, [device_job(M, data)[0]])
+    assert ei.value.code == -2
+
+
 def test_create_rejects_bad_jobs(M, ctx, streams):
     data = streams[0][3]
     j, _ = device_job(M, data)
