@@ -49,6 +49,7 @@ def parse():
                     help="skip the device-resident corpus decode (GPU entropy kernel + batched back half)")
     ap.add_argument("--gpu-entropy-reps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--no-model", action="store_true", help="skip fitting and checking the performance model")
     ap.add_argument("--serve-requests", type=int, default=2200, help="requests per trace (the first 200 warm up)")
     return ap.parse_args()
 
@@ -258,6 +259,61 @@ def pipeline_workload(args, M, ctx, dev):
         "parse_ms": round(full["parse_ms"], 1), "bands": full["bands"],
         "bit_exact_sample": {"image": smallest, "size": [frame["width"], frame["height"]], "equal": exact},
         "device_resident": dev_e2e,
+    }
+
+
+def model_workload(args, M, ctx, dev):
+    """The paper's performance model (Sec. 5.1) fitted on this machine: a
+    training set of synthetic 4:2:0 bitstreams on a grid of sizes up to 25 MP
+    (qualities 50-95, texture and gradient content, like the paper's crops of
+    a few photographs to many sizes), each timed in its four phases; then a
+    held-out set of 16 other images, predicted and measured."""
+    import torch
+
+    from paper_1311_5304_amd import perfmodel
+    from synth import fast_bitstream, gpu_encode, workloads
+
+    log("performance model: profiling the training set")
+    t0 = time.time()
+    rng = np.random.default_rng(workloads.seed_of(7, 0xFFFFF))
+
+    def bitstream(w, h, q, seed, content):
+        frame, c, qt = gpu_encode.batch_image_gpu(torch, (w, h, "420", q, seed), dev, sigma=12.0, content=content)
+        return fast_bitstream.write_jpeg(frame, c.cpu().numpy(), qt, restart_interval=32)
+
+    train = []
+    k = 0
+    for w in (320, 768, 1280, 2048, 2880, 3840, 4800, 5760):
+        for h in (240, 720, 1200, 1920, 2880, 3600, 4320):
+            if w * h > 25_000_000:
+                continue
+            q = (50, 75, 85, 95)[k % 4]
+            content = "texture" if k % 2 == 0 else "gradient"
+            train.append(perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(7, k), content), reps=2))
+            k += 1
+    model, info = perfmodel.fit(train)
+    log("performance model: held-out images")
+    errs = {"t_huff": [], "p_gpu": [], "total": []}
+    for i in range(16):
+        mp = rng.uniform(1.0, 24.0)
+        aspect = rng.choice([4 / 3, 3 / 2, 16 / 9])
+        w = int(round((mp * 1e6 * aspect) ** 0.5))
+        h = int(round(mp * 1e6 / w))
+        q = int(rng.integers(50, 96))
+        content = "texture" if i % 2 == 0 else "gradient"
+        s = perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(8, i), content), reps=2)
+        p = perfmodel.predict(model, s["width"], s["height"], s["bytes"])
+        meas = {"t_huff": s["t_huff"], "p_gpu": s["o_w"] + s["t_kernel"] + s["o_r"]}
+        meas["total"] = meas["t_huff"] + meas["p_gpu"]
+        for key in errs:
+            errs[key].append(abs(p[key] - meas[key]) / meas[key])
+    return {
+        "training_images": len(train), "held_out_images": 16,
+        "degrees_and_aic": {k: {"degree": v[0], "aic": round(v[1], 1)} for k, v in info.items()},
+        "held_out_abs_rel_error": {k: {"mean": round(float(np.mean(v)), 4), "max": round(float(np.max(v)), 4)}
+                                   for k, v in errs.items()},
+        "profiling_s": round(time.time() - t0, 1),
+        "model": perfmodel.to_dict(model),
     }
 
 
@@ -568,6 +624,8 @@ def main():
         extras["pipeline"] = pipeline_workload(args, M, ctx, dev)
     if not args.no_serve:
         extras["serve"] = serve_workload(args, M, ctx, dev)
+    if not args.no_model:
+        extras["model"] = model_workload(args, M, ctx, dev)
 
     out = {
         "metric": METRIC,

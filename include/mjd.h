@@ -443,6 +443,70 @@ int mjd_server_drain(mjd_server* srv);
 /* Drain, stop the server thread and free everything. */
 void mjd_server_destroy(mjd_server* srv);
 
+/* ---------------------------------------------------------------------
+ * Performance model (paper Sec. 5.1).  Decode times are predicted from
+ * closed forms fitted once, off-line, to times measured on this machine:
+ *   d = file bytes / (w * h)                           (Eq. 3)
+ *   T_huff(w, h, d) = T_huff_per_pixel(d) * w * h      (Eq. 4)
+ *   P_gpu(w, h) = O_w(w, h) + T_kernel(w, h) + O_r(w, h)
+ *                                (host->device, kernel, device->host)
+ *   T_total = T_huff + P_gpu
+ * Each closed form is a polynomial of degree at most 7: in d for the
+ * Huffman rate, in the scaled dimensions (a, b) = (w / 1024, h / 1024) for
+ * the GPU parts.  It is fitted by least squares; its degree is the one of
+ * least Akaike information criterion; it is evaluated in Horner form.
+ * Host code only: these calls touch no device.
+ * ------------------------------------------------------------------- */
+#define MJD_POLY_MAX_DEGREE 7
+#define MJD_POLY2_TERMS 36 /* (7 + 1) * (7 + 2) / 2 */
+
+/* p(x) = sum over i <= degree of c[i] * x^i. */
+typedef struct mjd_poly1 {
+  int32_t degree;
+  int32_t pad;
+  double c[MJD_POLY_MAX_DEGREE + 1];
+} mjd_poly1;
+
+/* p(a, b) = sum over i + j <= degree of c[t(i, j)] * a^i * b^j, with the
+ * terms grouped by the power of a: t(i, j) = i * (2 * degree + 3 - i) / 2 + j. */
+typedef struct mjd_poly2 {
+  int32_t degree;
+  int32_t pad;
+  double c[MJD_POLY2_TERMS];
+} mjd_poly2;
+
+/* Least-squares fits of every degree 0..max_degree whose k terms are fewer
+ * than the n samples; keeps the one of least AIC = n * ln(RSS / n) + 2k.
+ * A residual sum below 1e-24 of sum(y^2) counts as that floor, so that
+ * among exact fits the one with fewest terms wins.  *aic receives the kept
+ * fit's AIC (may be NULL).  MJD_EINVAL for null pointers, max_degree
+ * outside 0..7 or fewer than 2 samples; MJD_EUNSUPPORTED when no degree
+ * could be fitted (every design matrix rank-deficient). */
+int mjd_poly1_fit(const double* x, const double* y, size_t n, int max_degree, mjd_poly1* out, double* aic);
+int mjd_poly2_fit(const double* a, const double* b, const double* y, size_t n, int max_degree, mjd_poly2* out,
+                  double* aic);
+
+/* Horner evaluation (the paper's form for run-time prediction). */
+double mjd_poly1_eval(const mjd_poly1* p, double x);
+double mjd_poly2_eval(const mjd_poly2* p, double a, double b);
+
+/* The fitted model: Huffman seconds per pixel against d (bytes per
+ * pixel), and the three GPU parts in seconds against (w / 1024, h / 1024). */
+typedef struct mjd_model {
+  mjd_poly1 huff_per_pixel;
+  mjd_poly2 o_w, t_kernel, o_r;
+} mjd_model;
+
+/* One prediction, in seconds (d in bytes per pixel). */
+typedef struct mjd_prediction {
+  double d, t_huff, o_w, t_kernel, o_r, p_gpu, total;
+} mjd_prediction;
+
+/* Evaluates the model for one image (Eqs. 3-4 and the sums above).
+ * MJD_EINVAL for null pointers or a zero dimension. */
+int mjd_model_predict(const mjd_model* model, uint32_t width, uint32_t height, uint64_t file_bytes,
+                      mjd_prediction* out);
+
 /* Device-to-device streaming copy of `bytes` bytes (a multiple of 16; both
  * pointers 16-byte aligned), enqueued on `stream`.  It is the bandwidth
  * reference for the decoder: a plain read+write stream at the rate this

@@ -10,7 +10,8 @@ from ._binding import (MJD_SERVE_CONTINUOUS, MJD_SERVE_SYNC, MJD_UPSAMPLE_FANCY,
                        mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
                        mjd_decode, mjd_entropy_batch_create, mjd_entropy_batch_destroy,
                        mjd_entropy_batch_info, mjd_entropy_batch_launch, mjd_entropy_batch_status,
-                       mjd_entropy_decode, mjd_geometry_of, mjd_last_error, mjd_parse,
+                       mjd_entropy_decode, mjd_geometry_of, mjd_model, mjd_model_predict, mjd_poly1, mjd_poly2,
+                       mjd_poly1_eval, mjd_poly1_fit, mjd_poly2_eval, mjd_poly2_fit, mjd_last_error, mjd_parse,
                        mjd_restart_index, scan_frame)
 
 UPSAMPLE = {"simple": MJD_UPSAMPLE_SIMPLE, "fancy": MJD_UPSAMPLE_FANCY}

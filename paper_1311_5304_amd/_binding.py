@@ -15,6 +15,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "_lib", "libmjd.so")
 
 MJD_OK = 0
+MJD_POLY_MAX_DEGREE = 7
 MJD_EINVAL = -1
 MJD_EUNSUPPORTED = -2
 MJD_ENOMEM = -3
@@ -71,6 +72,22 @@ class mjd_scan(ctypes.Structure):
 class mjd_entropy_job(ctypes.Structure):
     _fields_ = [("scan", ctypes.POINTER(mjd_scan)), ("h_offsets", ctypes.c_void_p), ("d_jpg", ctypes.c_void_p),
                 ("len", ctypes.c_uint64), ("d_coef", ctypes.c_void_p)]
+
+
+class mjd_poly1(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("pad", ctypes.c_int32), ("c", ctypes.c_double * 8)]
+
+
+class mjd_poly2(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int32), ("pad", ctypes.c_int32), ("c", ctypes.c_double * 36)]
+
+
+class mjd_model(ctypes.Structure):
+    _fields_ = [("huff_per_pixel", mjd_poly1), ("o_w", mjd_poly2), ("t_kernel", mjd_poly2), ("o_r", mjd_poly2)]
+
+
+class mjd_prediction(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("d", "t_huff", "o_w", "t_kernel", "o_r", "p_gpu", "total")]
 
 
 class mjd_pipeline_config(ctypes.Structure):
@@ -152,6 +169,18 @@ def lib() -> ctypes.CDLL:
         L.mjd_entropy_batch_info.restype = i32
         L.mjd_entropy_batch_destroy.argtypes = [vp]
         L.mjd_entropy_batch_destroy.restype = None
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.mjd_poly1_fit.argtypes = [dp, dp, sz, i32, ctypes.POINTER(mjd_poly1), dp]
+        L.mjd_poly1_fit.restype = i32
+        L.mjd_poly2_fit.argtypes = [dp, dp, dp, sz, i32, ctypes.POINTER(mjd_poly2), dp]
+        L.mjd_poly2_fit.restype = i32
+        L.mjd_poly1_eval.argtypes = [ctypes.POINTER(mjd_poly1), ctypes.c_double]
+        L.mjd_poly1_eval.restype = ctypes.c_double
+        L.mjd_poly2_eval.argtypes = [ctypes.POINTER(mjd_poly2), ctypes.c_double, ctypes.c_double]
+        L.mjd_poly2_eval.restype = ctypes.c_double
+        L.mjd_model_predict.argtypes = [ctypes.POINTER(mjd_model), u32, u32, ctypes.c_uint64,
+                                        ctypes.POINTER(mjd_prediction)]
+        L.mjd_model_predict.restype = i32
         L.mjd_pipeline_create.argtypes = [vp, ctypes.POINTER(mjd_pipeline_config), ctypes.POINTER(vp)]
         L.mjd_pipeline_create.restype = i32
         L.mjd_pipeline_run.argtypes = [vp, sz, vp, vp, vp, vp, u32, ctypes.POINTER(mjd_pipeline_stats)]
@@ -433,6 +462,52 @@ def mjd_entropy_batch_info(batch: EntropyBatch) -> dict:
 
 def mjd_entropy_batch_destroy(batch: EntropyBatch):
     batch.close()
+
+
+# ---- performance model (paper Sec. 5.1) ---------------------------------------------
+
+def _dbl(v):
+    import numpy as np
+    a = np.ascontiguousarray(v, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def mjd_poly1_fit(x, y, max_degree: int = 7):
+    """-> (mjd_poly1, AIC) of the least-AIC least-squares fit."""
+    xa, xp = _dbl(x)
+    ya, yp = _dbl(y)
+    if len(xa) != len(ya):
+        raise ValueError("x and y differ in length")
+    out, aic = mjd_poly1(), ctypes.c_double()
+    _check(lib().mjd_poly1_fit(xp, yp, len(ya), int(max_degree), ctypes.byref(out), ctypes.byref(aic)))
+    return out, aic.value
+
+
+def mjd_poly2_fit(a, b, y, max_degree: int = 7):
+    """-> (mjd_poly2, AIC) of the least-AIC least-squares fit in (a, b)."""
+    aa, ap = _dbl(a)
+    ba, bp = _dbl(b)
+    ya, yp = _dbl(y)
+    if not len(aa) == len(ba) == len(ya):
+        raise ValueError("a, b and y differ in length")
+    out, aic = mjd_poly2(), ctypes.c_double()
+    _check(lib().mjd_poly2_fit(ap, bp, yp, len(ya), int(max_degree), ctypes.byref(out), ctypes.byref(aic)))
+    return out, aic.value
+
+
+def mjd_poly1_eval(p: mjd_poly1, x: float) -> float:
+    return lib().mjd_poly1_eval(ctypes.byref(p), float(x))
+
+
+def mjd_poly2_eval(p: mjd_poly2, a: float, b: float) -> float:
+    return lib().mjd_poly2_eval(ctypes.byref(p), float(a), float(b))
+
+
+def mjd_model_predict(model: mjd_model, width: int, height: int, file_bytes: int) -> dict:
+    out = mjd_prediction()
+    _check(lib().mjd_model_predict(ctypes.byref(model), int(width), int(height), int(file_bytes),
+                                   ctypes.byref(out)))
+    return {k: getattr(out, k) for k, _ in mjd_prediction._fields_}
 
 
 def scan_frame(scan: mjd_scan) -> dict:
