@@ -264,10 +264,11 @@ def pipeline_workload(args, M, ctx, dev):
 
 def model_workload(args, M, ctx, dev):
     """The paper's performance model (Sec. 5.1) fitted on this machine: a
-    training set of synthetic 4:2:0 bitstreams on a grid of sizes up to 25 MP
-    (qualities 50-95, texture and gradient content, like the paper's crops of
-    a few photographs to many sizes), each timed in its four phases; then a
-    held-out set of 16 other images, predicted and measured."""
+    training set of synthetic 4:2:0 bitstreams on a grid of sizes from 0.75
+    to 25 MP (qualities 50-95, texture and gradient content, like the paper's
+    crops of a few photographs to many sizes), each timed in its four phases;
+    then a held-out set of 16 other images (1-24 MP, inside the training
+    grid), predicted and measured."""
     import torch
 
     from paper_1311_5304_amd import perfmodel
@@ -281,27 +282,34 @@ def model_workload(args, M, ctx, dev):
         frame, c, qt = gpu_encode.batch_image_gpu(torch, (w, h, "420", q, seed), dev, sigma=12.0, content=content)
         return fast_bitstream.write_jpeg(frame, c.cpu().numpy(), qt, restart_interval=32)
 
+    # A grid over the whole prediction domain (polynomials extrapolate
+    # badly, as the paper notes): widths 1024..6656, heights 768..4224, from
+    # 0.75 to 25 MP; below that the per-call costs of the host decoder, which
+    # the per-pixel rate of Eq. 4 does not model, dominate.
     train = []
     k = 0
-    for w in (320, 768, 1280, 2048, 2880, 3840, 4800, 5760):
-        for h in (240, 720, 1200, 1920, 2880, 3600, 4320):
+    for w in range(1024, 6657, 512):
+        for h in range(768, 4225, 384):
             if w * h > 25_000_000:
                 continue
-            q = (50, 75, 85, 95)[k % 4]
+            q = (50, 60, 70, 80, 90, 95)[k % 6]
             content = "texture" if k % 2 == 0 else "gradient"
-            train.append(perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(7, k), content), reps=2))
+            train.append(perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(7, k), content), reps=3))
             k += 1
     model, info = perfmodel.fit(train)
     log("performance model: held-out images")
     errs = {"t_huff": [], "p_gpu": [], "total": []}
     for i in range(16):
-        mp = rng.uniform(1.0, 24.0)
-        aspect = rng.choice([4 / 3, 3 / 2, 16 / 9])
-        w = int(round((mp * 1e6 * aspect) ** 0.5))
-        h = int(round(mp * 1e6 / w))
+        while True:  # inside the training domain
+            mp = rng.uniform(1.0, 24.0)
+            aspect = rng.choice([4 / 3, 3 / 2, 16 / 9])
+            w = int(round((mp * 1e6 * aspect) ** 0.5))
+            h = int(round(mp * 1e6 / w))
+            if 1024 <= w <= 6656 and 768 <= h <= 4224:
+                break
         q = int(rng.integers(50, 96))
         content = "texture" if i % 2 == 0 else "gradient"
-        s = perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(8, i), content), reps=2)
+        s = perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(8, i), content), reps=3)
         p = perfmodel.predict(model, s["width"], s["height"], s["bytes"])
         meas = {"t_huff": s["t_huff"], "p_gpu": s["o_w"] + s["t_kernel"] + s["o_r"]}
         meas["total"] = meas["t_huff"] + meas["p_gpu"]
@@ -314,7 +322,7 @@ def model_workload(args, M, ctx, dev):
                                    for k, v in errs.items()},
         "profiling_s": round(time.time() - t0, 1),
         "model": perfmodel.to_dict(model),
-    }
+    }, model
 
 
 def gpu_entropy_workload(args, M, ctx, dev, jpgs, frames, sample_idx, sample):
@@ -407,7 +415,7 @@ def gpu_entropy_workload(args, M, ctx, dev, jpgs, frames, sample_idx, sample):
     return res
 
 
-def serve_workload(args, M, ctx, dev):
+def serve_workload(args, M, ctx, dev, model=None):
     """Serving loop: Poisson arrivals of requests log-uniform in 0.1..24 MP
     (mixed samplings, quality 50..95, gradient content), coefficients and
     RGB8 in pinned host memory, a 16 GiB device budget, continuous batching
@@ -433,9 +441,10 @@ def serve_workload(args, M, ctx, dev):
     warm = 200
     n = max(args.serve_requests, warm + 100)
 
-    def run(mode, rate):
+    def run(mode, rate, cap_s=0.0):
         trace = workloads.serving_trace(n, len(pool), rate if rate else 1.0)
-        srv = M.Server(ctx, budget, M.MJD_UPSAMPLE_FANCY, mode=mode, max_batch=256, max_inflight=2)
+        srv = M.Server(ctx, budget, M.MJD_UPSAMPLE_FANCY, mode=mode, max_batch=256, max_inflight=2,
+                       model=model if cap_s else None, max_batch_s=cap_s)
         try:
             t0 = srv.now_ns() + 2_000_000
             ids = []
@@ -455,14 +464,23 @@ def serve_workload(args, M, ctx, dev):
 
     log("serving: saturating trace (capacity)")
     cap = run(M.MJD_SERVE_CONTINUOUS, 0)
+    cap_model = run(M.MJD_SERVE_CONTINUOUS, 0, 4e-3) if model is not None else None
     mean_px = float(np.mean(px_of))
     res = {"pool_images": len(pool), "requests": n, "warmup": warm, "budget_GiB": budget >> 30,
            "mean_request_MP": round(mean_px / 1e6, 3), "capacity_continuous": cap}
+    if cap_model is not None:
+        res["capacity_continuous_model_cap_4ms"] = cap_model
     for frac in (0.7, 0.9):
         rate = frac * cap["MPix_s"] * 1e6 / mean_px
         log(f"serving: Poisson trace at {frac} x capacity ({rate:.0f} requests/s)")
         res[f"continuous_{frac}x"] = dict(run(M.MJD_SERVE_CONTINUOUS, rate), rate_per_s=round(rate, 1))
         res[f"sync_{frac}x"] = dict(run(M.MJD_SERVE_SYNC, rate), rate_per_s=round(rate, 1))
+        if model is not None:
+            # batches sized by the fitted performance model (paper Sec. 5.1):
+            # each closes once its predicted GPU time would pass the cap
+            for cap_ms in (4.0, 16.0):
+                res[f"continuous_model_cap_{cap_ms:g}ms_{frac}x"] = dict(
+                    run(M.MJD_SERVE_CONTINUOUS, rate, cap_ms * 1e-3), rate_per_s=round(rate, 1))
     # bit-exactness: the smallest pool image as served, against the oracle
     k = min(range(len(pool)), key=lambda i: px_of[i])
     f, c, q, o, qt = pool[k]
@@ -622,10 +640,11 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_pipeline:
         extras["pipeline"] = pipeline_workload(args, M, ctx, dev)
-    if not args.no_serve:
-        extras["serve"] = serve_workload(args, M, ctx, dev)
+    model = None
     if not args.no_model:
-        extras["model"] = model_workload(args, M, ctx, dev)
+        extras["model"], model = model_workload(args, M, ctx, dev)
+    if not args.no_serve:
+        extras["serve"] = serve_workload(args, M, ctx, dev, model)
 
     out = {
         "metric": METRIC,

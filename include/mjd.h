@@ -375,75 +375,6 @@ int mjd_pipeline_run(mjd_pipeline* pipe, size_t n, const uint8_t* const* h_jpgs,
 void mjd_pipeline_destroy(mjd_pipeline* pipe);
 
 /* ---------------------------------------------------------------------
- * Serving: a request loop that decodes images of different sizes as they
- * arrive.  Requests carry quantised coefficients in host memory (the
- * paper's input, Sec. 7) and receive RGB8 in host memory.  The server keeps
- * one device arena of `budget_bytes` for the coefficient and RGB buffers of
- * admitted requests (the paper's whole-image buffers, Sec. 4); a request is
- * admitted, in arrival order, once it has arrived and its buffers fit.
- * Continuous batching: every request admitted while earlier batches are on
- * the device is copied host->device at once and joins the next persistent
- * batch launch; results go device->host on their own stream and free the
- * arena as they complete.  The server thread uses the context (its tuning
- * and device) while it runs: do not change the context's tuning meanwhile.
- * ------------------------------------------------------------------- */
-
-typedef struct mjd_server mjd_server;
-
-enum {
-  MJD_SERVE_CONTINUOUS = 0, /* continuous batching (above) */
-  MJD_SERVE_SYNC = 1        /* one request at a time: copy, decode, copy back, synchronise */
-};
-
-typedef struct mjd_server_config {
-  uint64_t budget_bytes; /* device arena for coefficient + RGB buffers (e.g. 16 GiB) */
-  uint32_t upsample;     /* MJD_UPSAMPLE_* */
-  uint32_t mode;         /* MJD_SERVE_* */
-  uint32_t max_batch;    /* requests per batch launch, 1..4096 */
-  uint32_t max_inflight; /* batch launches on the device at once, 1..8 */
-} mjd_server_config;
-
-/* One decode request.  All buffers belong to the caller and must stay valid
- * until the request is done; h_coef/h_qt are read, h_rgb written, by device
- * copies (pinned memory lets them overlap). */
-typedef struct mjd_request {
-  mjd_frame frame;
-  const int16_t* h_coef; /* n_blocks * 64 int16, MCU order (as mjd_decode) */
-  const uint16_t* h_qt;  /* uint16[4][64] */
-  uint8_t* h_rgb;        /* height rows of pitch bytes */
-  uint64_t pitch;        /* >= 3 * width */
-  uint64_t arrival_ns;   /* on the server clock (mjd_server_now_ns); earlier than now = arrived */
-} mjd_request;
-
-/* Server-clock timestamps of one request (0 while a stage has not happened). */
-typedef struct mjd_request_times {
-  uint64_t arrival_ns;
-  uint64_t admit_ns;   /* buffers allocated, host->device copy enqueued */
-  uint64_t launch_ns;  /* its batch (or its decode, in sync mode) enqueued */
-  uint64_t done_ns;    /* RGB8 in host memory (observed by the server) */
-  int32_t status;      /* MJD_OK, or why it failed */
-  uint32_t batch;      /* number of requests in its batch launch */
-} mjd_request_times;
-
-/* Allocate the arena, batch tables and streams on the context's device and
- * start the server thread.  Its clock starts at 0 here. */
-int mjd_server_create(mjd_ctx* ctx, const mjd_server_config* cfg, mjd_server** out);
-/* Nanoseconds on the server clock. */
-uint64_t mjd_server_now_ns(const mjd_server* srv);
-/* Queue a request (thread-safe); *id numbers requests 0, 1, 2, ... in
- * submission order, which is the admission order.  Validation happens here:
- * MJD_EBUDGET if the request's buffers can never fit in the arena; arrival
- * times must not decrease from one request to the next. */
-int mjd_server_submit(mjd_server* srv, const mjd_request* req, uint64_t* id);
-/* Block until request `id` is done; fills its timestamps.  Returns its
- * status.  Records of finished requests are kept until mjd_server_destroy. */
-int mjd_server_wait(mjd_server* srv, uint64_t id, mjd_request_times* times);
-/* Block until every submitted request is done. */
-int mjd_server_drain(mjd_server* srv);
-/* Drain, stop the server thread and free everything. */
-void mjd_server_destroy(mjd_server* srv);
-
-/* ---------------------------------------------------------------------
  * Performance model (paper Sec. 5.1).  Decode times are predicted from
  * closed forms fitted once, off-line, to times measured on this machine:
  *   d = file bytes / (w * h)                           (Eq. 3)
@@ -506,6 +437,80 @@ typedef struct mjd_prediction {
  * MJD_EINVAL for null pointers or a zero dimension. */
 int mjd_model_predict(const mjd_model* model, uint32_t width, uint32_t height, uint64_t file_bytes,
                       mjd_prediction* out);
+
+/* ---------------------------------------------------------------------
+ * Serving: a request loop that decodes images of different sizes as they
+ * arrive.  Requests carry quantised coefficients in host memory (the
+ * paper's input, Sec. 7) and receive RGB8 in host memory.  The server keeps
+ * one device arena of `budget_bytes` for the coefficient and RGB buffers of
+ * admitted requests (the paper's whole-image buffers, Sec. 4); a request is
+ * admitted, in arrival order, once it has arrived and its buffers fit.
+ * Continuous batching: every request admitted while earlier batches are on
+ * the device is copied host->device at once and joins the next persistent
+ * batch launch; results go device->host on their own stream and free the
+ * arena as they complete.  The server thread uses the context (its tuning
+ * and device) while it runs: do not change the context's tuning meanwhile.
+ * ------------------------------------------------------------------- */
+
+typedef struct mjd_server mjd_server;
+
+enum {
+  MJD_SERVE_CONTINUOUS = 0, /* continuous batching (above) */
+  MJD_SERVE_SYNC = 1        /* one request at a time: copy, decode, copy back, synchronise */
+};
+
+typedef struct mjd_server_config {
+  uint64_t budget_bytes; /* device arena for coefficient + RGB buffers (e.g. 16 GiB) */
+  uint32_t upsample;     /* MJD_UPSAMPLE_* */
+  uint32_t mode;         /* MJD_SERVE_* */
+  uint32_t max_batch;    /* requests per batch launch, 1..4096 */
+  uint32_t max_inflight; /* batch launches on the device at once, 1..8 */
+  const mjd_model* model; /* optional (NULL: none); copied at create */
+  double max_batch_s;     /* with a model and > 0: a batch admits requests
+                             while the sum of their predicted GPU times
+                             (O_w + T_kernel + O_r) stays within this many
+                             seconds; its first request always */
+} mjd_server_config;
+
+/* One decode request.  All buffers belong to the caller and must stay valid
+ * until the request is done; h_coef/h_qt are read, h_rgb written, by device
+ * copies (pinned memory lets them overlap). */
+typedef struct mjd_request {
+  mjd_frame frame;
+  const int16_t* h_coef; /* n_blocks * 64 int16, MCU order (as mjd_decode) */
+  const uint16_t* h_qt;  /* uint16[4][64] */
+  uint8_t* h_rgb;        /* height rows of pitch bytes */
+  uint64_t pitch;        /* >= 3 * width */
+  uint64_t arrival_ns;   /* on the server clock (mjd_server_now_ns); earlier than now = arrived */
+} mjd_request;
+
+/* Server-clock timestamps of one request (0 while a stage has not happened). */
+typedef struct mjd_request_times {
+  uint64_t arrival_ns;
+  uint64_t admit_ns;   /* buffers allocated, host->device copy enqueued */
+  uint64_t launch_ns;  /* its batch (or its decode, in sync mode) enqueued */
+  uint64_t done_ns;    /* RGB8 in host memory (observed by the server) */
+  int32_t status;      /* MJD_OK, or why it failed */
+  uint32_t batch;      /* number of requests in its batch launch */
+} mjd_request_times;
+
+/* Allocate the arena, batch tables and streams on the context's device and
+ * start the server thread.  Its clock starts at 0 here. */
+int mjd_server_create(mjd_ctx* ctx, const mjd_server_config* cfg, mjd_server** out);
+/* Nanoseconds on the server clock. */
+uint64_t mjd_server_now_ns(const mjd_server* srv);
+/* Queue a request (thread-safe); *id numbers requests 0, 1, 2, ... in
+ * submission order, which is the admission order.  Validation happens here:
+ * MJD_EBUDGET if the request's buffers can never fit in the arena; arrival
+ * times must not decrease from one request to the next. */
+int mjd_server_submit(mjd_server* srv, const mjd_request* req, uint64_t* id);
+/* Block until request `id` is done; fills its timestamps.  Returns its
+ * status.  Records of finished requests are kept until mjd_server_destroy. */
+int mjd_server_wait(mjd_server* srv, uint64_t id, mjd_request_times* times);
+/* Block until every submitted request is done. */
+int mjd_server_drain(mjd_server* srv);
+/* Drain, stop the server thread and free everything. */
+void mjd_server_destroy(mjd_server* srv);
 
 /* Device-to-device streaming copy of `bytes` bytes (a multiple of 16; both
  * pointers 16-byte aligned), enqueued on `stream`.  It is the bandwidth

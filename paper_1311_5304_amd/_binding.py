@@ -109,7 +109,8 @@ MJD_SERVE_SYNC = 1
 
 class mjd_server_config(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("upsample", ctypes.c_uint32), ("mode", ctypes.c_uint32),
-                ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
+                ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32), ("model", ctypes.c_void_p),
+                ("max_batch_s", ctypes.c_double)]
 
 
 class mjd_request(ctypes.Structure):
@@ -560,9 +561,12 @@ class Server:
     """Owns an mjd_server*: the continuous-batching (or synchronous) request loop."""
 
     def __init__(self, ctx: Context, budget_bytes: int, upsample: int = 1, mode: int = MJD_SERVE_CONTINUOUS,
-                 max_batch: int = 256, max_inflight: int = 2):
+                 max_batch: int = 256, max_inflight: int = 2, model=None, max_batch_s: float = 0.0):
+        """model (an mjd_model) and max_batch_s cap each batch's predicted GPU time."""
         cfg = mjd_server_config(budget_bytes=int(budget_bytes), upsample=int(upsample), mode=int(mode),
-                                max_batch=int(max_batch), max_inflight=int(max_inflight))
+                                max_batch=int(max_batch), max_inflight=int(max_inflight),
+                                model=ctypes.addressof(model) if model is not None else None,
+                                max_batch_s=float(max_batch_s))
         p = ctypes.c_void_p()
         _check(lib().mjd_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(p)))
         self.handle = p

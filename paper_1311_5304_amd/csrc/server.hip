@@ -78,6 +78,7 @@ struct Request {
   uint64_t coef_bytes = 0, rgb_pitch = 0, rgb_bytes = 0, total = 0;
   uint64_t off = 0;  // arena offset: coefficients, then quant tables, then RGB
   mjd_request_times t{};
+  double pred_s = 0.0;  // predicted GPU seconds (with a model)
   bool done = false;
 };
 
@@ -102,6 +103,8 @@ struct mjd_server {
   mjd_ctx* ctx = nullptr;
   int device = 0;
   mjd_server_config cfg{};
+  mjd_model model{};
+  bool has_model = false;
   mjd::serve::Clock::time_point t0;
   uint8_t* d_arena = nullptr;
   mjd::serve::Arena arena;
@@ -233,8 +236,11 @@ static int launch(mjd_server* s, TableSlot& t, std::vector<uint64_t>& forming, u
 
 static void run_continuous(mjd_server* s) {
   std::vector<uint64_t> forming;
+  double forming_s = 0.0;  // predicted GPU seconds of the forming batch
+  const bool capped = s->has_model && s->cfg.max_batch_s > 0.0;
   for (;;) {
     bool progressed = false;
+    if (forming.empty()) forming_s = 0.0;
     const uint64_t now = s->now_ns();
     // retire finished batches, oldest first
     for (;;) {
@@ -267,6 +273,9 @@ static void run_continuous(mjd_server* s) {
           next_arrival = q.r.arrival_ns;
           break;
         }
+        // batch sizing by the performance model: the batch closes once its
+        // predicted GPU time would pass the cap
+        if (capped && !forming.empty() && forming_s + q.pred_s > s->cfg.max_batch_s) break;
         if (!s->arena.alloc(q.total, &q.off)) break;
         const hipError_t e = copy_in(s, q);
         q.t.admit_ns = now;
@@ -276,6 +285,7 @@ static void run_continuous(mjd_server* s) {
           s->cv_done.notify_all();
         } else {
           forming.push_back(s->next_admit);
+          forming_s += q.pred_s;
         }
         ++s->next_admit;
         progressed = true;
@@ -411,12 +421,19 @@ int mjd_server_create(mjd_ctx* ctx, const mjd_server_config* cfg, mjd_server** o
   if (cfg->max_batch < 1 || cfg->max_batch > 4096) return mjd::fail(MJD_EINVAL, "max_batch outside 1..4096");
   if (cfg->max_inflight < 1 || cfg->max_inflight > 8) return mjd::fail(MJD_EINVAL, "max_inflight outside 1..8");
   if (cfg->budget_bytes < (1u << 20)) return mjd::fail(MJD_EINVAL, "budget below 1 MiB");
+  if (!(cfg->max_batch_s >= 0.0) || cfg->max_batch_s > 1e6)
+    return mjd::fail(MJD_EINVAL, "max_batch_s must be a non-negative number of seconds");
   mjd_server* s = new (std::nothrow) mjd_server;
   if (!s) return mjd::fail(MJD_ENOMEM, "server allocation failed");
   s->ctx = ctx;
   s->device = ctx->device;
   s->cfg = *cfg;
   s->cfg.budget_bytes = cfg->budget_bytes / mjd::serve::kAlign * mjd::serve::kAlign;
+  if (cfg->model) {
+    s->model = *cfg->model;
+    s->has_model = true;
+  }
+  s->cfg.model = nullptr;  // the server keeps its own copy
   int cur = 0;
   (void)hipGetDevice(&cur);
   if (cur != s->device && hipSetDevice(s->device) != hipSuccess) {
@@ -460,6 +477,12 @@ int mjd_server_submit(mjd_server* srv, const mjd_request* req, uint64_t* id) {
   if (q.rgb_pitch >= (1ull << 24)) return mjd::fail(MJD_EINVAL, "row too wide");
   q.rgb_bytes = round_up(q.rgb_pitch * req->frame.height, kAlign);
   q.total = q.coef_bytes + mjd::serve::kQtBytes + q.rgb_bytes;
+  if (srv->has_model) {
+    mjd_prediction p;
+    if (mjd_model_predict(&srv->model, req->frame.width, req->frame.height, 0, &p) == MJD_OK &&
+        p.p_gpu > 0.0)
+      q.pred_s = p.p_gpu;
+  }
   if (q.total > srv->cfg.budget_bytes)
     return mjd::fail(MJD_EBUDGET, "request needs %llu device bytes, budget is %llu",
                      static_cast<unsigned long long>(q.total), static_cast<unsigned long long>(srv->cfg.budget_bytes));

@@ -109,6 +109,33 @@ def test_budget_admission_serialises_without_changing_results(M, ctx, requests):
         srv.close()
 
 
+def test_model_caps_the_predicted_batch_time(M, ctx, requests):
+    """Batch sizing by the performance model: with every request predicted
+    at 1 ms of GPU time and a 2.5 ms cap, no batch holds more than two
+    requests, and the results do not change."""
+    exp = expected(requests, "fancy")
+    model = M.mjd_model()
+    model.o_w.degree = model.t_kernel.degree = model.o_r.degree = 0
+    model.o_w.c[0] = 1e-3
+    assert M.mjd_model_predict(model, 100, 100, 0)["p_gpu"] == 1e-3
+    srv = M.Server(ctx, 256 << 20, M.MJD_UPSAMPLE_FANCY, max_batch=64, max_inflight=1, model=model,
+                   max_batch_s=2.5e-3)
+    try:
+        outs = outputs(requests)
+        ids = [srv.submit(f, c, q, o, 3 * f["width"]) for (f, c, q, _, _), o in zip(requests, outs)]
+        times = [srv.wait(i) for i in ids]
+        for t in times:
+            check_times(t)
+        assert max(t["batch"] for t in times) == 2
+        for o, e in zip(outs, exp):
+            assert np.array_equal(o.numpy(), e)
+    finally:
+        srv.close()
+    with pytest.raises(M.MjdError) as ei:
+        M.Server(ctx, 256 << 20, M.MJD_UPSAMPLE_FANCY, model=model, max_batch_s=-1.0)
+    assert ei.value.code == -1
+
+
 def test_sync_server_and_padded_pitch(M, ctx, requests):
     exp = expected(requests, "fancy")
     srv = M.Server(ctx, 64 << 20, M.MJD_UPSAMPLE_FANCY, mode=M.MJD_SERVE_SYNC)
