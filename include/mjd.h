@@ -145,6 +145,15 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef,
                const uint16_t* d_qt, int upsample, uint8_t* d_rgb, size_t pitch,
                uint32_t mcu_row0, uint32_t mcu_row1, void* stream);
 
+/* The same decode on host cores: the CPU side of the paper's CPU-GPU
+ * partitioning (Sec. 5.2), which gives the CPU the image rows the GPU does
+ * not take.  Same arithmetic and bytes as mjd_decode; host pointers; rows
+ * [mcu_h*row0, min(H, mcu_h*row1)) are written at h_rgb + y*pitch, split
+ * over n_threads (1..256) host threads.  Reads the blocks mjd_decode reads.
+ * It is not a substitute for the device path: no call falls back to it. */
+int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, const uint16_t* h_qt, int upsample,
+                    uint8_t* h_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads);
+
 /* One image of a batch: its frame, device buffers and output pitch, with
  * the same meaning and constraints as the arguments of mjd_decode (whole
  * image: MCU rows [0, mcus_y)). */

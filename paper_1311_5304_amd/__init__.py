@@ -8,7 +8,7 @@ from ._binding import (MJD_SERVE_CONTINUOUS, MJD_SERVE_SYNC, MJD_UPSAMPLE_FANCY,
                        Batch, Context, EntropyBatch, MjdError, Pipeline, Server,
                        mjd_batch_create, mjd_batch_destroy, mjd_batch_launch,
                        mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
-                       mjd_decode, mjd_entropy_batch_create, mjd_entropy_batch_destroy,
+                       mjd_decode, mjd_decode_host, mjd_entropy_batch_create, mjd_entropy_batch_destroy,
                        mjd_entropy_batch_info, mjd_entropy_batch_launch, mjd_entropy_batch_status,
                        mjd_entropy_decode, mjd_geometry_of, mjd_model, mjd_model_predict, mjd_poly1, mjd_poly2,
                        mjd_poly1_eval, mjd_poly1_fit, mjd_poly2_eval, mjd_poly2_fit, mjd_last_error, mjd_parse,

@@ -170,6 +170,8 @@ def lib() -> ctypes.CDLL:
         L.mjd_entropy_batch_info.restype = i32
         L.mjd_entropy_batch_destroy.argtypes = [vp]
         L.mjd_entropy_batch_destroy.restype = None
+        L.mjd_decode_host.argtypes = [ctypes.POINTER(mjd_frame), vp, vp, i32, vp, sz, u32, u32, i32]
+        L.mjd_decode_host.restype = i32
         dp = ctypes.POINTER(ctypes.c_double)
         L.mjd_poly1_fit.argtypes = [dp, dp, sz, i32, ctypes.POINTER(mjd_poly1), dp]
         L.mjd_poly1_fit.restype = i32
@@ -305,6 +307,13 @@ def mjd_decode(ctx: Context, frame, coef, qt, upsample: int, rgb, pitch: int,
     _check(lib().mjd_decode(ctx.handle, ctypes.byref(make_frame(frame)), _ptr(coef), _ptr(qt),
                             int(upsample), _ptr(rgb), int(pitch), int(mcu_row0), int(mcu_row1),
                             _stream(stream)))
+
+
+def mjd_decode_host(frame, coef, qt, upsample: int, rgb, pitch: int, row0: int, row1: int, n_threads: int = 1):
+    """The decode on host cores (host arrays or pinned tensors)."""
+    f = make_frame(frame)
+    _check(lib().mjd_decode_host(ctypes.byref(f), _ptr(coef), _ptr(qt), int(upsample), _ptr(rgb), int(pitch),
+                                 int(row0), int(row1), int(n_threads)))
 
 
 def mjd_copy(ctx: Context, dst, src, nbytes: int, stream=None):
