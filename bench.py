@@ -282,6 +282,10 @@ def model_workload(args, M, ctx, dev):
         frame, c, qt = gpu_encode.batch_image_gpu(torch, (w, h, "420", q, seed), dev, sigma=12.0, content=content)
         return fast_bitstream.write_jpeg(frame, c.cpu().numpy(), qt, restart_interval=32)
 
+    n_threads = args.pipeline_threads + 1
+    hetero = M.Hetero(ctx, max_blocks=25_000_000 * 3 // 128 + 65536, max_pixels=25_000_000 + 65536,
+                      n_threads=n_threads)
+
     # A grid over the whole prediction domain (polynomials extrapolate
     # badly, as the paper notes): widths 1024..6656, heights 768..4224, from
     # 0.75 to 25 MP; below that the per-call costs of the host decoder, which
@@ -294,7 +298,8 @@ def model_workload(args, M, ctx, dev):
                 continue
             q = (50, 60, 70, 80, 90, 95)[k % 6]
             content = "texture" if k % 2 == 0 else "gradient"
-            train.append(perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(7, k), content), reps=3))
+            train.append(perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(7, k), content), reps=3,
+                                           hetero=hetero))
             k += 1
     model, info = perfmodel.fit(train)
     log("performance model: held-out images")
@@ -315,14 +320,74 @@ def model_workload(args, M, ctx, dev):
         meas["total"] = meas["t_huff"] + meas["p_gpu"]
         for key in errs:
             errs[key].append(abs(p[key] - meas[key]) / meas[key])
+    part = partition_experiment(M, model, hetero, n_threads, bitstream, workloads)
+    hetero.close()
     return {
         "training_images": len(train), "held_out_images": 16,
         "degrees_and_aic": {k: {"degree": v[0], "aic": round(v[1], 1)} for k, v in info.items()},
         "held_out_abs_rel_error": {k: {"mean": round(float(np.mean(v)), 4), "max": round(float(np.max(v)), 4)}
                                    for k, v in errs.items()},
         "profiling_s": round(time.time() - t0, 1),
+        "partition": part,
         "model": perfmodel.to_dict(model),
     }, model
+
+
+def partition_experiment(M, model, hetero, n_threads, bitstream, workloads):
+    """The CPU-GPU partitioning (Sec. 5.2) on a 12.6 MP and a 24 MP 4:2:0
+    image (RGB back to pinned host memory, Huffman on the host's threads):
+    GPU alone, host alone, and the SPS and PPS splits the fitted model's
+    Newton solve gives, with the model's predicted sides beside the measured
+    ones; for SPS also half and twice the chosen host share.  Every run's
+    RGB must equal the GPU-only run's bytes.  Times are the best of 5."""
+    import torch
+
+    log("CPU-GPU partitioning")
+    out = []
+    for (w, h, q), seed in zip(((4096, 3072, 85), (6000, 4000, 85)), (11, 12)):
+        jpg = bitstream(w, h, q, workloads.seed_of(9, seed), "texture")
+        mcu_h = 16
+        ref = torch.empty(h * w * 3, dtype=torch.uint8).pin_memory()
+        rgb = torch.empty(h * w * 3, dtype=torch.uint8).pin_memory()
+
+        def run(cpu_rows, scheme, dst):
+            best = None
+            for _ in range(5):
+                t = hetero.decode(jpg, dst, 3 * w, cpu_rows, scheme, M.MJD_UPSAMPLE_FANCY)
+                if best is None or t["total_s"] < best["total_s"]:
+                    best = t
+            return best
+
+        def ms(t):
+            return {k[:-2] + "_ms": round(v * 1e3, 3) for k, v in t.items()}
+
+        gpu_only = run(0, M.MJD_PART_SPS, ref)
+        row = {"image": f"{w}x{h}", "bytes": len(jpg), "huff_threads": n_threads, "gpu_only": ms(gpu_only)}
+        same = True
+        t = run(h, M.MJD_PART_SPS, rgb)
+        same &= bool(torch.equal(rgb, ref))
+        row["cpu_only"] = ms(t)
+        for name, scheme in (("sps", M.MJD_PART_SPS), ("pps", M.MJD_PART_PPS)):
+            p = M.mjd_partition_rows(model, scheme, w, h, mcu_h, len(jpg), n_threads)
+            t = run(p["cpu_rows"], scheme, rgb)
+            same &= bool(torch.equal(rgb, ref))
+            row[name] = {"cpu_rows": p["cpu_rows"], "newton_iterations": p["iterations"],
+                         "predicted_cpu_side_ms": round(p["t_cpu"] * 1e3, 3),
+                         "predicted_gpu_side_ms": round(p["t_gpu"] * 1e3, 3),
+                         "measured_cpu_side_ms": round((t["dispatch_s"] + t["huff_cpu_s"] + t["cpu_s"]) * 1e3, 3),
+                         "measured_gpu_side_ms": round(t["gpu_s"] * 1e3, 3), **ms(t),
+                         "speedup_vs_gpu_only": round(gpu_only["total_s"] / t["total_s"], 3)}
+            if name == "sps":
+                sweep = []
+                for f in (0.5, 2.0):
+                    r = h - min(h, int(round((h - p["cpu_rows"] * f) / mcu_h)) * mcu_h)
+                    r = min(max(r, 0), h)
+                    sweep.append({"cpu_rows": r, "total_ms": round(run(r, scheme, rgb)["total_s"] * 1e3, 3)})
+                    same &= bool(torch.equal(rgb, ref))
+                row["sps_sweep"] = sweep
+        row["all_runs_equal_gpu_only"] = same
+        out.append(row)
+    return out
 
 
 def gpu_entropy_workload(args, M, ctx, dev, jpgs, frames, sample_idx, sample):

@@ -154,6 +154,37 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef,
 int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, const uint16_t* h_qt, int upsample,
                     uint8_t* h_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads);
 
+/* Heterogeneous decode of one bitstream (paper Sec. 5.2): the GPU decodes
+ * the image's first MCU rows while host threads decode the rest, as a
+ * partition (mjd_partition_rows) assigns them.  Owns pinned coefficient
+ * staging, device buffers for the largest image and a stream. */
+typedef struct mjd_hetero mjd_hetero;
+
+/* Seconds spent in each part of one mjd_hetero_decode, on the host clock. */
+typedef struct mjd_hetero_times {
+  double huff_gpu_s; /* Huffman decoding of the rows the GPU needs (SPS: all rows) */
+  double dispatch_s; /* enqueueing the GPU part: copies in, kernel, copies out */
+  double huff_cpu_s; /* PPS: Huffman decoding of the CPU's remaining rows */
+  double cpu_s;      /* mjd_decode_host of the CPU's rows */
+  double gpu_s;      /* device time from the GPU part's first copy in to its last copy out */
+  double total_s;    /* the whole call */
+} mjd_hetero_times;
+
+/* max_blocks / max_pixels: the largest image; n_threads (1..256) host
+ * threads for Huffman decoding and the CPU rows. */
+int mjd_hetero_create(mjd_ctx* ctx, uint64_t max_blocks, uint64_t max_pixels, int n_threads, mjd_hetero** out);
+
+/* Decodes h_jpg into h_rgb (height rows of pitch bytes; pinned memory lets
+ * the GPU rows arrive by DMA).  scheme: MJD_PART_SPS or MJD_PART_PPS.
+ * cpu_rows: 0, the height, or height minus a multiple of the MCU height.
+ * Returns when every row is in h_rgb; times may be NULL.  Bit-exact with
+ * mjd_decode of the whole image. */
+int mjd_hetero_decode(mjd_hetero* h, const uint8_t* h_jpg, size_t len, int upsample, int scheme, uint32_t cpu_rows,
+                      uint8_t* h_rgb, size_t pitch, mjd_hetero_times* times);
+
+/* Synchronise and free. */
+void mjd_hetero_destroy(mjd_hetero* h);
+
 /* One image of a batch: its frame, device buffers and output pitch, with
  * the same meaning and constraints as the arguments of mjd_decode (whole
  * image: MCU rows [0, mcus_y)). */
@@ -431,21 +462,49 @@ double mjd_poly1_eval(const mjd_poly1* p, double x);
 double mjd_poly2_eval(const mjd_poly2* p, double a, double b);
 
 /* The fitted model: Huffman seconds per pixel against d (bytes per
- * pixel), and the three GPU parts in seconds against (w / 1024, h / 1024). */
+ * pixel), and the three GPU parts in seconds against (w / 1024, h / 1024);
+ * for CPU-GPU partitioning also the back half on host cores (P_cpu) and the
+ * host's time to enqueue the GPU part (T_dispatch), against (w / 1024,
+ * rows / 1024). */
 typedef struct mjd_model {
   mjd_poly1 huff_per_pixel;
   mjd_poly2 o_w, t_kernel, o_r;
+  mjd_poly2 p_cpu, t_dispatch;
 } mjd_model;
 
-/* One prediction, in seconds (d in bytes per pixel). */
+/* One prediction, in seconds (d in bytes per pixel); total = t_huff + p_gpu. */
 typedef struct mjd_prediction {
-  double d, t_huff, o_w, t_kernel, o_r, p_gpu, total;
+  double d, t_huff, o_w, t_kernel, o_r, p_gpu, total, p_cpu, t_dispatch;
 } mjd_prediction;
 
 /* Evaluates the model for one image (Eqs. 3-4 and the sums above).
  * MJD_EINVAL for null pointers or a zero dimension. */
 int mjd_model_predict(const mjd_model* model, uint32_t width, uint32_t height, uint64_t file_bytes,
                       mjd_prediction* out);
+
+/* CPU-GPU partitioning of one image (paper Sec. 5.2).  The GPU decodes the
+ * image's first rows and the CPU the last x rows, x chosen so that both
+ * sides finish together (f(x) = 0), by Newton's method on the model's
+ * polynomials, then rounded so that the GPU keeps whole MCU rows.
+ *   SPS (simple): Huffman decoding of the whole image first, then
+ *     f(x) = T_dispatch(w, h-x) + P_cpu(w, x) - P_gpu(w, h-x).
+ *   PPS (pipelined): Huffman decoding of the GPU's rows, the dispatch, then
+ *     the CPU decodes its own rows' Huffman data while the GPU works:
+ *     f(x) = T_dispatch(w, h-x) + T_huff(w, x, d) / huff_threads
+ *            + P_cpu(w, x) - P_gpu(w, h-x).
+ * huff_threads: the speed-up of the host Huffman decoder over the model's
+ * one-thread rate (restart intervals decode in parallel); >= 1. */
+enum { MJD_PART_SPS = 0, MJD_PART_PPS = 1 };
+
+typedef struct mjd_partition {
+  uint32_t cpu_rows;   /* the CPU's rows: height - (GPU's whole MCU rows) * mcu_h */
+  uint32_t iterations; /* Newton steps taken */
+  double x;            /* the unrounded balance point in rows (0 or height when f keeps one sign) */
+  double t_cpu, t_gpu; /* predicted seconds of both sides at cpu_rows, after the common Huffman prefix */
+} mjd_partition;
+
+int mjd_partition_rows(const mjd_model* model, int scheme, uint32_t width, uint32_t height, uint32_t mcu_h,
+                       uint64_t file_bytes, double huff_threads, mjd_partition* out);
 
 /* ---------------------------------------------------------------------
  * Serving: a request loop that decodes images of different sizes as they

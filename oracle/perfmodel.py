@@ -111,3 +111,36 @@ def predict(model, width: int, height: int, file_bytes: int) -> dict:
     out["p_gpu"] = out["o_w"] + out["t_kernel"] + out["o_r"]
     out["total"] = out["t_huff"] + out["p_gpu"]
     return out
+
+
+# ---- CPU-GPU partitioning (Sec. 5.2) --------------------------------------------------------
+# The GPU decodes the first rows, the CPU the last x (reading of the paper's
+# equations, which name x the CPU's rows).  After the Huffman decoding both
+# sides wait for:
+#   SPS: CPU = T_dispatch(w, h - x) + P_cpu(w, x),        GPU = P_gpu(w, h - x)
+#   PPS: CPU = T_dispatch(w, h - x) + T_huff(w, x, d) / n_huff + P_cpu(w, x),
+#        GPU = P_gpu(w, h - x)
+# (PPS: the CPU decodes its own rows' Huffman data while the GPU works; the
+# GPU's Huffman data is decoded before both.)
+
+def sides(model, scheme: str, w: int, h: int, file_bytes: int, huff_threads: float, x: float):
+    a = w / 1024.0
+    gpu = sum(eval2(*model[p], a, (h - x) / 1024.0) for p in ("o_w", "t_kernel", "o_r"))
+    cpu = eval2(*model["t_dispatch"], a, (h - x) / 1024.0) + eval2(*model["p_cpu"], a, x / 1024.0)
+    if scheme == "pps":
+        cpu += eval1(*model["huff_per_pixel"], file_bytes / (w * h)) * w * x / huff_threads
+    return cpu, gpu
+
+
+def best_partition(model, scheme: str, w: int, h: int, mcu_h: int, file_bytes: int, huff_threads: float = 1.0):
+    """Brute force over every split on an MCU-row boundary -> (later finish
+    time, CPU rows) of the split that minimises the later finish."""
+    best = None
+    for r in range(-(-h // mcu_h) + 1):
+        g = min(h, r * mcu_h)
+        x = h - g
+        cpu, gpu = sides(model, scheme, w, h, file_bytes, huff_threads, x)
+        t = max(cpu if x else 0.0, gpu if g else 0.0)
+        if best is None or t < best[0]:
+            best = (t, x)
+    return best

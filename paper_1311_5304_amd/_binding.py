@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_PKG, "_lib", "libmjd.so")
 
 MJD_OK = 0
 MJD_POLY_MAX_DEGREE = 7
+MJD_PART_SPS = 0
+MJD_PART_PPS = 1
 MJD_EINVAL = -1
 MJD_EUNSUPPORTED = -2
 MJD_ENOMEM = -3
@@ -83,11 +85,23 @@ class mjd_poly2(ctypes.Structure):
 
 
 class mjd_model(ctypes.Structure):
-    _fields_ = [("huff_per_pixel", mjd_poly1), ("o_w", mjd_poly2), ("t_kernel", mjd_poly2), ("o_r", mjd_poly2)]
+    _fields_ = [("huff_per_pixel", mjd_poly1), ("o_w", mjd_poly2), ("t_kernel", mjd_poly2), ("o_r", mjd_poly2),
+                ("p_cpu", mjd_poly2), ("t_dispatch", mjd_poly2)]
 
 
 class mjd_prediction(ctypes.Structure):
-    _fields_ = [(k, ctypes.c_double) for k in ("d", "t_huff", "o_w", "t_kernel", "o_r", "p_gpu", "total")]
+    _fields_ = [(k, ctypes.c_double) for k in ("d", "t_huff", "o_w", "t_kernel", "o_r", "p_gpu", "total",
+                                               "p_cpu", "t_dispatch")]
+
+
+class mjd_partition(ctypes.Structure):
+    _fields_ = [("cpu_rows", ctypes.c_uint32), ("iterations", ctypes.c_uint32), ("x", ctypes.c_double),
+                ("t_cpu", ctypes.c_double), ("t_gpu", ctypes.c_double)]
+
+
+class mjd_hetero_times(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("huff_gpu_s", "dispatch_s", "huff_cpu_s", "cpu_s", "gpu_s",
+                                               "total_s")]
 
 
 class mjd_pipeline_config(ctypes.Structure):
@@ -184,6 +198,15 @@ def lib() -> ctypes.CDLL:
         L.mjd_model_predict.argtypes = [ctypes.POINTER(mjd_model), u32, u32, ctypes.c_uint64,
                                         ctypes.POINTER(mjd_prediction)]
         L.mjd_model_predict.restype = i32
+        L.mjd_partition_rows.argtypes = [ctypes.POINTER(mjd_model), i32, u32, u32, u32, ctypes.c_uint64,
+                                         ctypes.c_double, ctypes.POINTER(mjd_partition)]
+        L.mjd_partition_rows.restype = i32
+        L.mjd_hetero_create.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, i32, ctypes.POINTER(vp)]
+        L.mjd_hetero_create.restype = i32
+        L.mjd_hetero_decode.argtypes = [vp, vp, sz, i32, i32, u32, vp, sz, ctypes.POINTER(mjd_hetero_times)]
+        L.mjd_hetero_decode.restype = i32
+        L.mjd_hetero_destroy.argtypes = [vp]
+        L.mjd_hetero_destroy.restype = None
         L.mjd_pipeline_create.argtypes = [vp, ctypes.POINTER(mjd_pipeline_config), ctypes.POINTER(vp)]
         L.mjd_pipeline_create.restype = i32
         L.mjd_pipeline_run.argtypes = [vp, sz, vp, vp, vp, vp, u32, ctypes.POINTER(mjd_pipeline_stats)]
@@ -518,6 +541,43 @@ def mjd_model_predict(model: mjd_model, width: int, height: int, file_bytes: int
     _check(lib().mjd_model_predict(ctypes.byref(model), int(width), int(height), int(file_bytes),
                                    ctypes.byref(out)))
     return {k: getattr(out, k) for k, _ in mjd_prediction._fields_}
+
+
+def mjd_partition_rows(model: mjd_model, scheme: int, width: int, height: int, mcu_h: int, file_bytes: int,
+                       huff_threads: float = 1.0) -> dict:
+    out = mjd_partition()
+    _check(lib().mjd_partition_rows(ctypes.byref(model), int(scheme), int(width), int(height), int(mcu_h),
+                                    int(file_bytes), float(huff_threads), ctypes.byref(out)))
+    return {k: getattr(out, k) for k, _ in mjd_partition._fields_}
+
+
+class Hetero:
+    """Owns an mjd_hetero*: CPU-GPU partitioned decode of one image at a time."""
+
+    def __init__(self, ctx: Context, max_blocks: int, max_pixels: int, n_threads: int = 16):
+        p = ctypes.c_void_p()
+        _check(lib().mjd_hetero_create(ctx.handle, int(max_blocks), int(max_pixels), int(n_threads),
+                                       ctypes.byref(p)))
+        self.handle = p
+
+    def decode(self, jpg, rgb, pitch: int, cpu_rows: int, scheme: int = MJD_PART_SPS,
+               upsample: int = MJD_UPSAMPLE_FANCY) -> dict:
+        a, n = _bytes_view(jpg)
+        t = mjd_hetero_times()
+        _check(lib().mjd_hetero_decode(self.handle, _ptr(a), n, int(upsample), int(scheme), int(cpu_rows),
+                                       _ptr(rgb), int(pitch), ctypes.byref(t)))
+        return {k: getattr(t, k) for k, _ in mjd_hetero_times._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().mjd_hetero_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def scan_frame(scan: mjd_scan) -> dict:

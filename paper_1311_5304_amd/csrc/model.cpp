@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "mjd.h"
@@ -70,6 +71,42 @@ static double aic_of(double rss, double sumsq, size_t n, size_t k) {
 static size_t terms2(int degree) { return static_cast<size_t>((degree + 1) * (degree + 2) / 2); }
 
 static size_t t2(int degree, int i, int j) { return static_cast<size_t>(i * (2 * degree + 3 - i) / 2 + j); }
+
+// d/db of a two-variable polynomial, in Horner form.
+static double poly2_db(const mjd_poly2& p, double a, double b) {
+  const int deg = p.degree;
+  double r = 0.0;
+  for (int i = deg; i >= 0; --i) {
+    double q = 0.0;
+    for (int j = deg - i; j >= 1; --j) q = q * b + j * p.c[t2(deg, i, j)];
+    r = r * a + q;
+  }
+  return r;
+}
+
+// Both sides of a partition with x image rows on the CPU (after the part of
+// Huffman decoding that precedes the split), and f = cpu - gpu with its
+// derivative in x.
+struct Sides {
+  double cpu, gpu, f, df;
+};
+
+static Sides sides(const mjd_model& m, int scheme, double w, double h, double hpp, double huff_threads, double x) {
+  const double a = w / 1024.0, bc = x / 1024.0, bg = (h - x) / 1024.0;
+  Sides s;
+  const double pgpu = mjd_poly2_eval(&m.o_w, a, bg) + mjd_poly2_eval(&m.t_kernel, a, bg) + mjd_poly2_eval(&m.o_r, a, bg);
+  const double dpgpu = poly2_db(m.o_w, a, bg) + poly2_db(m.t_kernel, a, bg) + poly2_db(m.o_r, a, bg);
+  s.cpu = mjd_poly2_eval(&m.t_dispatch, a, bg) + mjd_poly2_eval(&m.p_cpu, a, bc);
+  double dcpu = (-poly2_db(m.t_dispatch, a, bg) + poly2_db(m.p_cpu, a, bc)) / 1024.0;
+  if (scheme == MJD_PART_PPS) {
+    s.cpu += hpp * w * x / huff_threads;
+    dcpu += hpp * w / huff_threads;
+  }
+  s.gpu = pgpu;
+  s.f = s.cpu - s.gpu;
+  s.df = dcpu + dpgpu / 1024.0;  // d/dx P_gpu(w, h - x) = -dP/db / 1024
+  return s;
+}
 
 }  // namespace model
 }  // namespace mjd
@@ -189,6 +226,58 @@ int mjd_model_predict(const mjd_model* m, uint32_t width, uint32_t height, uint6
   out->o_r = mjd_poly2_eval(&m->o_r, a, b);
   out->p_gpu = out->o_w + out->t_kernel + out->o_r;
   out->total = out->t_huff + out->p_gpu;
+  out->p_cpu = mjd_poly2_eval(&m->p_cpu, a, b);
+  out->t_dispatch = mjd_poly2_eval(&m->t_dispatch, a, b);
+  return MJD_OK;
+}
+
+int mjd_partition_rows(const mjd_model* m, int scheme, uint32_t width, uint32_t height, uint32_t mcu_h,
+                       uint64_t file_bytes, double huff_threads, mjd_partition* out) {
+  if (!m || !out) return mjd::fail(MJD_EINVAL, "null model or output pointer");
+  if (!width || !height || (mcu_h != 8 && mcu_h != 16)) return mjd::fail(MJD_EINVAL, "bad image or MCU height");
+  if (scheme != MJD_PART_SPS && scheme != MJD_PART_PPS) return mjd::fail(MJD_EINVAL, "unknown scheme %d", scheme);
+  if (!(huff_threads >= 1.0)) return mjd::fail(MJD_EINVAL, "huff_threads below 1");
+  const double w = width, h = height;
+  const double hpp = mjd_poly1_eval(&m->huff_per_pixel, static_cast<double>(file_bytes) / (w * h));
+  uint32_t it = 0;
+  double x;
+  const Sides s0 = sides(*m, scheme, w, h, hpp, huff_threads, 0.0), sh = sides(*m, scheme, w, h, hpp, huff_threads, h);
+  if (s0.f >= 0.0) {
+    x = 0.0;  // even no rows on the CPU finish no earlier than the GPU's share
+  } else if (sh.f <= 0.0) {
+    x = h;  // the CPU alone finishes first
+  } else {
+    // Newton's method from the middle, kept inside [0, h]; it stops when a
+    // step no longer reduces |f| or moves less than a quarter row
+    x = h / 2;
+    Sides cur = sides(*m, scheme, w, h, hpp, huff_threads, x);
+    for (it = 0; it < 100; ++it) {
+      if (!(cur.df > 0.0)) break;
+      double nx = x - cur.f / cur.df;
+      nx = nx < 0.0 ? 0.0 : (nx > h ? h : nx);
+      const Sides nxt = sides(*m, scheme, w, h, hpp, huff_threads, nx);
+      if (fabs(nxt.f) >= fabs(cur.f)) break;
+      const double step = fabs(nx - x);
+      x = nx;
+      cur = nxt;
+      if (step < 0.25) {
+        ++it;
+        break;
+      }
+    }
+  }
+  // the GPU keeps whole MCU rows: the nearest split on an MCU-row boundary
+  const uint32_t mcus_y = (height + mcu_h - 1) / mcu_h;
+  double gr = (h - x) / mcu_h;
+  uint32_t gpu_mcu_rows = static_cast<uint32_t>(gr + 0.5);
+  if (gpu_mcu_rows > mcus_y) gpu_mcu_rows = mcus_y;
+  const uint32_t gpu_rows = std::min(height, gpu_mcu_rows * mcu_h);
+  out->cpu_rows = height - gpu_rows;
+  out->iterations = it;
+  out->x = x;
+  const Sides fin = sides(*m, scheme, w, h, hpp, huff_threads, static_cast<double>(out->cpu_rows));
+  out->t_cpu = out->cpu_rows ? fin.cpu : 0.0;
+  out->t_gpu = gpu_rows ? fin.gpu : 0.0;
   return MJD_OK;
 }
 

@@ -6,7 +6,10 @@ of images and fits closed forms to the times:
   (w * h) (Eqs. 3-4);
 - the three parts of the GPU time against the image dimensions: the copy of
   the coefficients in, the kernel, and the copy of the RGB out (pinned
-  buffers on both sides, as in the paper).
+  buffers on both sides, as in the paper);
+- for the CPU-GPU partitioning (Sec. 5.2), the host's back half of x rows
+  (P_CPU) and the host's time to enqueue the GPU's rows (T_dispatch), each
+  against the width and the rows of its side.
 `measure` times one bitstream's phases on this machine; `fit` turns a list
 of measurements into an `mjd_model`; `predict` evaluates it (Horner form, in
 the library).  The fits and the evaluation are the library's (include/mjd.h);
@@ -21,12 +24,15 @@ import numpy as np
 from . import _binding as B
 
 PARTS = ("o_w", "t_kernel", "o_r")
+HOST_PARTS = ("p_cpu", "t_dispatch")
 
 
-def measure(ctx, jpg: bytes, reps: int = 3, upsample: int = B.MJD_UPSAMPLE_FANCY) -> dict:
+def measure(ctx, jpg: bytes, reps: int = 3, upsample: int = B.MJD_UPSAMPLE_FANCY, hetero=None) -> dict:
     """Times one bitstream: Huffman decoding on one host thread (the paper's
     sequential phase), then host->device copy of the coefficients, the decode
-    kernel and device->host copy of the RGB (each the best of `reps`)."""
+    kernel and device->host copy of the RGB (each the best of `reps`).  With
+    a heterogeneous decoder (B.Hetero) also the back half on its host threads
+    (p_cpu) and the host's time to enqueue the GPU part (t_dispatch)."""
     import torch
 
     scan, qt = B.mjd_parse(jpg)
@@ -59,7 +65,24 @@ def measure(ctx, jpg: bytes, reps: int = 3, upsample: int = B.MJD_UPSAMPLE_FANCY
         torch.cuda.synchronize()
         for k, (a, b) in zip(PARTS, ((0, 1), (1, 2), (2, 3))):
             best[k] = min(best[k], ev[a].elapsed_time(ev[b]) * 1e-3)
-    return {"width": w, "height": h, "bytes": len(jpg), "t_huff": t_huff, **best}
+    out = {"width": w, "height": h, "bytes": len(jpg), "t_huff": t_huff, **best}
+    if hetero is not None:
+        # split the image at the quarters: the host's time for its x rows
+        # (p_cpu at (w, x)) and the enqueueing of the GPU's h - x rows
+        # (t_dispatch at (w, h - x)), each the best of `reps`
+        host = []
+        for r in sorted({0, g["mcus_y"] // 4, g["mcus_y"] // 2, 3 * g["mcus_y"] // 4, g["mcus_y"]}):
+            cpu_rows = h - min(h, r * g["mcu_h"])
+            cpu_s = dispatch_s = float("inf")
+            for _ in range(reps):
+                t = hetero.decode(jpg, rgb_h, 3 * w, cpu_rows, B.MJD_PART_SPS, upsample)
+                cpu_s, dispatch_s = min(cpu_s, t["cpu_s"]), min(dispatch_s, t["dispatch_s"])
+            if cpu_rows:
+                host.append(("p_cpu", w, cpu_rows, cpu_s))
+            if cpu_rows < h:
+                host.append(("t_dispatch", w, h - cpu_rows, dispatch_s))
+        out["host"] = host
+    return out
 
 
 def fit(samples, max_degree: int = B.MJD_POLY_MAX_DEGREE) -> tuple:
@@ -77,6 +100,12 @@ def fit(samples, max_degree: int = B.MJD_POLY_MAX_DEGREE) -> tuple:
         p2, aic = B.mjd_poly2_fit(w / 1024.0, h / 1024.0, np.array([s[part] for s in samples]), max_degree)
         setattr(model, part, p2)
         info[part] = (p2.degree, aic)
+    for part in HOST_PARTS:  # against (width, rows) of the part's side
+        pts = np.array([x[1:] for s in samples for x in s.get("host", ()) if x[0] == part], np.float64)
+        if len(pts):
+            p2, aic = B.mjd_poly2_fit(pts[:, 0] / 1024.0, pts[:, 1] / 1024.0, pts[:, 2], max_degree)
+            setattr(model, part, p2)
+            info[part] = (p2.degree, aic)
     return model, info
 
 
@@ -88,7 +117,7 @@ def to_dict(model) -> dict:
     """A JSON-able copy of the model's coefficients."""
     out = {"huff_per_pixel": {"degree": model.huff_per_pixel.degree,
                               "c": list(model.huff_per_pixel.c)[:model.huff_per_pixel.degree + 1]}}
-    for part in PARTS:
+    for part in PARTS + HOST_PARTS:
         p = getattr(model, part)
         out[part] = {"degree": p.degree, "c": list(p.c)[:(p.degree + 1) * (p.degree + 2) // 2]}
     return out
@@ -99,7 +128,9 @@ def from_dict(d: dict):
     model.huff_per_pixel.degree = d["huff_per_pixel"]["degree"]
     for i, c in enumerate(d["huff_per_pixel"]["c"]):
         model.huff_per_pixel.c[i] = c
-    for part in PARTS:
+    for part in PARTS + HOST_PARTS:
+        if part not in d:
+            continue
         p = getattr(model, part)
         p.degree = d[part]["degree"]
         for i, c in enumerate(d[part]["c"]):

@@ -189,3 +189,113 @@ def test_fit_errors(M):
     with pytest.raises(M.MjdError) as ei:
         M.mjd_model_predict(M.mjd_model(), 0, 10, 100)
     assert ei.value.code == -1
+
+
+# ---- CPU-GPU partitioning (Sec. 5.2) ------------------------------------------------------
+
+def _model_pair(M, cpu_rate, gpu_rate, dispatch, hpp):
+    """A library model and the oracle's copy: P_cpu and P_gpu linear in the
+    pixels (seconds per 1024^2 pixels), a constant dispatch, a constant
+    Huffman rate."""
+    m = M.mjd_model()
+    m.huff_per_pixel.degree = 0
+    m.huff_per_pixel.c[0] = hpp
+    o = {"huff_per_pixel": (0, [hpp])}
+    for name, val in (("o_w", 0.0), ("t_kernel", gpu_rate), ("o_r", 0.0), ("p_cpu", cpu_rate),
+                      ("t_dispatch", 0.0)):
+        p = getattr(m, name)
+        p.degree = 2
+        c = [0.0] * 6
+        c[4] = val  # the a*b term: t(1, 1) = 1 * (2*2 + 3 - 1) / 2 + 1 = 4
+        if name == "t_dispatch":
+            c[0] = dispatch
+        for i, v in enumerate(c):
+            p.c[i] = v
+        o[name] = (2, c)
+    return m, o
+
+
+@pytest.mark.parametrize("scheme", ["sps", "pps"])
+def test_newton_partition_matches_brute_force(M, scheme):
+    code = M.MJD_PART_SPS if scheme == "sps" else M.MJD_PART_PPS
+    cases = [(2e-3, 2e-3, 1e-5, 5e-10), (4e-3, 1e-3, 2e-5, 1e-9), (1e-3, 3e-3, 1e-5, 2e-9)]
+    for cpu_rate, gpu_rate, dispatch, hpp in cases:
+        m, o = _model_pair(M, cpu_rate, gpu_rate, dispatch, hpp)
+        for w, h, mh in ((4096, 3072, 16), (1000, 777, 16), (640, 480, 8)):
+            nbytes = w * h // 3
+            got = M.mjd_partition_rows(m, code, w, h, mh, nbytes, 4.0)
+            t_best, x_best = O.best_partition(o, scheme, w, h, mh, nbytes, 4.0)
+            assert abs(got["cpu_rows"] - x_best) <= mh, (cpu_rate, gpu_rate, w, h)
+            # the continuous root balances both sides
+            if 0 < got["x"] < h:
+                cpu, gpu = O.sides(o, scheme, w, h, nbytes, 4.0, got["x"])
+                assert math.isclose(cpu, gpu, rel_tol=1e-6)
+            assert got["iterations"] >= 1 or got["x"] in (0.0, float(h))
+            cpu, gpu = O.sides(o, scheme, w, h, nbytes, 4.0, got["cpu_rows"])
+            assert math.isclose(got["t_gpu"], gpu if got["cpu_rows"] < h else 0.0, rel_tol=1e-9)
+
+
+def test_partition_ends(M):
+    # a GPU far faster than the CPU keeps every row; a GPU far slower gives them all away
+    m, _ = _model_pair(M, 1.0, 1e-6, 1e-4, 1e-9)
+    assert M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, 3072, 16, 10 ** 6)["cpu_rows"] == 0
+    m, _ = _model_pair(M, 1e-6, 1.0, 0.0, 1e-9)
+    assert M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, 3072, 16, 10 ** 6)["cpu_rows"] == 3072
+    with pytest.raises(M.MjdError):
+        M.mjd_partition_rows(m, 7, 4096, 3072, 16, 10 ** 6)
+    with pytest.raises(M.MjdError):
+        M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, 3072, 12, 10 ** 6)
+
+
+@pytest.mark.parametrize("scheme", ["sps", "pps"])
+def test_oracle_sides_balance_at_the_linear_closed_form(scheme):
+    # linear costs: CPU = D + c*A*x (+ hpp*w*x/n for PPS), GPU = g*A*(h - x),
+    # A = w / 1024^2, so the sides meet at x = (g*A*h - D) / (c*A + g*A (+ hpp*w/n))
+    cpu_rate, gpu_rate, dispatch, hpp, n = 3e-3, 1e-3, 2e-4, 1e-9, 4.0
+    o = {"huff_per_pixel": (0, [hpp])}
+    for name, val in (("o_w", 0.0), ("t_kernel", gpu_rate), ("o_r", 0.0), ("p_cpu", cpu_rate),
+                      ("t_dispatch", 0.0)):
+        c = [0.0] * 6
+        c[4] = val  # a*b
+        if name == "t_dispatch":
+            c[0] = dispatch
+        o[name] = (2, c)
+    w, h, mh = 4096, 3072, 16
+    A = w / 1024.0 ** 2
+    slope = cpu_rate * A + gpu_rate * A + (hpp * w / n if scheme == "pps" else 0.0)
+    x = (gpu_rate * A * h - dispatch) / slope
+    assert 0 < x < h
+    cpu, gpu = O.sides(o, scheme, w, h, w * h // 3, n, x)
+    assert math.isclose(cpu, gpu, rel_tol=1e-12)
+    assert math.isclose(gpu, gpu_rate * A * (h - x), rel_tol=1e-12)
+    # the brute force's split is the MCU-row boundary on either side of the root
+    t, xb = O.best_partition(o, scheme, w, h, mh, w * h // 3, n)
+    assert abs(xb - x) < mh
+    assert t >= gpu - 1e-15
+
+
+def test_fit_recovers_host_parts_against_rows(M):
+    # samples carrying host-part points at (width, rows): a bilinear truth is
+    # recovered and evaluated where the partition needs it
+    from paper_1311_5304_amd import perfmodel
+    rng = np.random.default_rng(5)
+    samples = []
+    for _ in range(30):
+        w = int(rng.integers(1024, 6000))
+        h = int(rng.integers(768, 4000))
+        s = {"width": w, "height": h, "bytes": w * h // 4, "t_huff": 2e-9 * w * h,
+             "o_w": 1e-4 + 1e-3 * w * h / 2 ** 20, "t_kernel": 2e-5 * w * h / 2 ** 20, "o_r": 1e-3 * w * h / 2 ** 20}
+        host = []
+        for x in (h // 4, h // 2, h):
+            host.append(("p_cpu", w, x, 3e-4 + 4e-3 * w * x / 2 ** 20))
+            host.append(("t_dispatch", w, h - x + 1, 5e-5))
+        s["host"] = host
+        samples.append(s)
+    model, info = perfmodel.fit(samples)
+    assert set(info) == {"huff_per_pixel", "o_w", "t_kernel", "o_r", "p_cpu", "t_dispatch"}
+    assert info["p_cpu"][0] == 2 and info["t_dispatch"][0] == 0
+    for w, x in ((2000, 100), (5000, 3000)):
+        got = M.mjd_poly2_eval(model.p_cpu, w / 1024.0, x / 1024.0)
+        assert math.isclose(got, 3e-4 + 4e-3 * w * x / 2 ** 20, rel_tol=1e-8)
+    back = perfmodel.from_dict(perfmodel.to_dict(model))
+    assert back.p_cpu.degree == 2 and math.isclose(back.t_dispatch.c[0], 5e-5, rel_tol=1e-9)
