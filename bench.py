@@ -336,9 +336,11 @@ def model_workload(args, M, ctx, dev):
 def partition_experiment(M, model, hetero, n_threads, bitstream, workloads):
     """The CPU-GPU partitioning (Sec. 5.2) on a 12.6 MP and a 24 MP 4:2:0
     image (RGB back to pinned host memory, Huffman on the host's threads):
-    GPU alone, host alone, and the SPS and PPS splits the fitted model's
-    Newton solve gives, with the model's predicted sides beside the measured
-    ones; for SPS also half and twice the chosen host share.  Every run's
+    GPU alone, host alone, and the SPS, overlapped and PPS splits the fitted
+    model's Newton solve gives, with the model's predicted sides beside the
+    measured ones; for SPS also half and twice the chosen host share; for PPS
+    chunks of 4 to 32 MCU rows (the paper picks the chunk by profiling), then
+    the best chunk with re-partitioning before the last chunk.  Every run's
     RGB must equal the GPU-only run's bytes.  Times are the best of 5."""
     import torch
 
@@ -349,43 +351,66 @@ def partition_experiment(M, model, hetero, n_threads, bitstream, workloads):
         mcu_h = 16
         ref = torch.empty(h * w * 3, dtype=torch.uint8).pin_memory()
         rgb = torch.empty(h * w * 3, dtype=torch.uint8).pin_memory()
+        same = [True]
 
-        def run(cpu_rows, scheme, dst):
+        def run(cpu_rows, scheme, dst=rgb, **kw):
             best = None
             for _ in range(5):
-                t = hetero.decode(jpg, dst, 3 * w, cpu_rows, scheme, M.MJD_UPSAMPLE_FANCY)
+                t = hetero.decode(jpg, dst, 3 * w, cpu_rows, scheme, M.MJD_UPSAMPLE_FANCY, **kw)
                 if best is None or t["total_s"] < best["total_s"]:
                     best = t
+            if dst is not ref:
+                same[0] &= bool(torch.equal(dst, ref))
             return best
 
         def ms(t):
-            return {k[:-2] + "_ms": round(v * 1e3, 3) for k, v in t.items()}
+            return {(k[:-2] + "_ms" if k.endswith("_s") else k): (round(v * 1e3, 3) if k.endswith("_s") else v)
+                    for k, v in t.items()}
 
         gpu_only = run(0, M.MJD_PART_SPS, ref)
-        row = {"image": f"{w}x{h}", "bytes": len(jpg), "huff_threads": n_threads, "gpu_only": ms(gpu_only)}
-        same = True
-        t = run(h, M.MJD_PART_SPS, rgb)
-        same &= bool(torch.equal(rgb, ref))
-        row["cpu_only"] = ms(t)
-        for name, scheme in (("sps", M.MJD_PART_SPS), ("pps", M.MJD_PART_PPS)):
+
+        def summary(p, t, sides=True):
+            d = {"planned_cpu_rows": p["cpu_rows"], "newton_iterations": p["iterations"],
+                 "predicted_cpu_side_ms": round(p["t_cpu"] * 1e3, 3),
+                 "predicted_gpu_side_ms": round(p["t_gpu"] * 1e3, 3)}
+            if sides:
+                d["measured_cpu_side_ms"] = round((t["dispatch_s"] + t["huff_cpu_s"] + t["cpu_s"]) * 1e3, 3)
+                d["measured_gpu_side_ms"] = round(t["gpu_s"] * 1e3, 3)
+            d.update(ms(t))
+            d["speedup_vs_gpu_only"] = round(gpu_only["total_s"] / t["total_s"], 3)
+            return d
+
+        row = {"image": f"{w}x{h}", "bytes": len(jpg), "huff_threads": n_threads, "gpu_only": ms(gpu_only),
+               "cpu_only": ms(run(h, M.MJD_PART_SPS))}
+        for name, scheme in (("sps", M.MJD_PART_SPS), ("overlap", M.MJD_PART_OVERLAP)):
             p = M.mjd_partition_rows(model, scheme, w, h, mcu_h, len(jpg), n_threads)
-            t = run(p["cpu_rows"], scheme, rgb)
-            same &= bool(torch.equal(rgb, ref))
-            row[name] = {"cpu_rows": p["cpu_rows"], "newton_iterations": p["iterations"],
-                         "predicted_cpu_side_ms": round(p["t_cpu"] * 1e3, 3),
-                         "predicted_gpu_side_ms": round(p["t_gpu"] * 1e3, 3),
-                         "measured_cpu_side_ms": round((t["dispatch_s"] + t["huff_cpu_s"] + t["cpu_s"]) * 1e3, 3),
-                         "measured_gpu_side_ms": round(t["gpu_s"] * 1e3, 3), **ms(t),
-                         "speedup_vs_gpu_only": round(gpu_only["total_s"] / t["total_s"], 3)}
+            row[name] = summary(p, run(p["cpu_rows"], scheme))
             if name == "sps":
                 sweep = []
                 for f in (0.5, 2.0):
                     r = h - min(h, int(round((h - p["cpu_rows"] * f) / mcu_h)) * mcu_h)
                     r = min(max(r, 0), h)
-                    sweep.append({"cpu_rows": r, "total_ms": round(run(r, scheme, rgb)["total_s"] * 1e3, 3)})
-                    same &= bool(torch.equal(rgb, ref))
+                    sweep.append({"cpu_rows": r, "total_ms": round(run(r, scheme)["total_s"] * 1e3, 3)})
                 row["sps_sweep"] = sweep
-        row["all_runs_equal_gpu_only"] = same
+        chunks = []
+        for c in (4, 8, 16, 32):
+            p = M.mjd_partition_rows(model, M.MJD_PART_PPS, w, h, mcu_h, len(jpg), n_threads, c * mcu_h)
+            chunks.append((c, p, run(p["cpu_rows"], M.MJD_PART_PPS, chunk_mcu_rows=c)))
+        row["pps_chunks"] = [{"chunk_mcu_rows": c, "cpu_rows": t["cpu_rows"], "total_ms": round(t["total_s"] * 1e3, 3)}
+                             for c, p, t in chunks]
+        c, p, t = min(chunks, key=lambda e: e[2]["total_s"])
+        row["pps"] = {"chunk_mcu_rows": c, **summary(p, t, sides=False)}
+        t = run(p["cpu_rows"], M.MJD_PART_PPS, chunk_mcu_rows=c, model=model, huff_threads=n_threads)
+        row["pps_repartition"] = {"chunk_mcu_rows": c, **summary(p, t, sides=False)}
+        # Amdahl (Eqs. 18-19): against the host-only decoder, whose Huffman
+        # part cannot be shared, the attainable speed-up is T_total / T_huff
+        cpu_only = row["cpu_only"]
+        bound = cpu_only["total_ms"] / cpu_only["huff_gpu_ms"]
+        best_pps = min(row["pps"]["total_ms"], row["pps_repartition"]["total_ms"])
+        row["amdahl"] = {"attainable_speedup_vs_cpu_only": round(bound, 3),
+                         "pps_speedup_vs_cpu_only": round(cpu_only["total_ms"] / best_pps, 3),
+                         "fraction_of_attainable": round(cpu_only["total_ms"] / best_pps / bound, 3)}
+        row["all_runs_equal_gpu_only"] = same[0]
         out.append(row)
     return out
 

@@ -163,23 +163,37 @@ typedef struct mjd_hetero mjd_hetero;
 /* Seconds spent in each part of one mjd_hetero_decode, on the host clock. */
 typedef struct mjd_hetero_times {
   double huff_gpu_s; /* Huffman decoding of the rows the GPU needs (SPS: all rows) */
-  double dispatch_s; /* enqueueing the GPU part: copies in, kernel, copies out */
-  double huff_cpu_s; /* PPS: Huffman decoding of the CPU's remaining rows */
+  double dispatch_s; /* enqueueing the GPU part: copies in, kernels, copies out */
+  double huff_cpu_s; /* OVERLAP, PPS: Huffman decoding of the rows left for the CPU */
   double cpu_s;      /* mjd_decode_host of the CPU's rows */
   double gpu_s;      /* device time from the GPU part's first copy in to its last copy out */
   double total_s;    /* the whole call */
+  uint32_t chunks;   /* GPU launches (one per chunk) */
+  uint32_t cpu_rows; /* the CPU's rows in the end (PPS re-partitioning may change them) */
 } mjd_hetero_times;
 
 /* max_blocks / max_pixels: the largest image; n_threads (1..256) host
  * threads for Huffman decoding and the CPU rows. */
 int mjd_hetero_create(mjd_ctx* ctx, uint64_t max_blocks, uint64_t max_pixels, int n_threads, mjd_hetero** out);
 
+/* How one image is shared. */
+typedef struct mjd_hetero_plan {
+  int scheme;              /* MJD_PART_SPS, MJD_PART_OVERLAP or MJD_PART_PPS */
+  uint32_t cpu_rows;       /* 0, the height, or the height minus a multiple of the MCU height */
+  uint32_t chunk_mcu_rows; /* PPS: MCU rows per GPU chunk (0: all the GPU's rows in one) */
+  uint32_t pad;
+  const struct mjd_model* model; /* PPS: re-partition before the last of two or more chunks with
+                              mjd_repartition_rows (NULL: keep cpu_rows) */
+  double huff_threads;     /* PPS re-partitioning: as for mjd_partition_rows */
+} mjd_hetero_plan;
+
 /* Decodes h_jpg into h_rgb (height rows of pitch bytes; pinned memory lets
- * the GPU rows arrive by DMA).  scheme: MJD_PART_SPS or MJD_PART_PPS.
- * cpu_rows: 0, the height, or height minus a multiple of the MCU height.
- * Returns when every row is in h_rgb; times may be NULL.  Bit-exact with
- * mjd_decode of the whole image. */
-int mjd_hetero_decode(mjd_hetero* h, const uint8_t* h_jpg, size_t len, int upsample, int scheme, uint32_t cpu_rows,
+ * the GPU rows arrive by DMA) as the plan shares it.  Returns when every
+ * row is in h_rgb; times may be NULL.  Bit-exact with mjd_decode of the
+ * whole image, whatever the plan.  MJD_EINVAL for null pointers, an unknown
+ * scheme, an image above the decoder's capacity, pitch < 3 * width, or
+ * cpu_rows off an MCU-row boundary; a bitstream's errors as mjd_parse. */
+int mjd_hetero_decode(mjd_hetero* h, const uint8_t* h_jpg, size_t len, int upsample, const mjd_hetero_plan* plan,
                       uint8_t* h_rgb, size_t pitch, mjd_hetero_times* times);
 
 /* Synchronise and free. */
@@ -485,26 +499,56 @@ int mjd_model_predict(const mjd_model* model, uint32_t width, uint32_t height, u
 /* CPU-GPU partitioning of one image (paper Sec. 5.2).  The GPU decodes the
  * image's first rows and the CPU the last x rows, x chosen so that both
  * sides finish together (f(x) = 0), by Newton's method on the model's
- * polynomials, then rounded so that the GPU keeps whole MCU rows.
- *   SPS (simple): Huffman decoding of the whole image first, then
+ * polynomials (from h/2, kept inside [0, h], until a step no longer reduces
+ * |f|), then rounded so that the GPU keeps whole MCU rows.  Huffman terms
+ * are T_huff(w, rows, d) = huff_per_pixel(d) * w * rows / huff_threads.
+ *   SPS (simple, Eqs. 8-10): Huffman decoding of the whole image first, then
  *     f(x) = T_dispatch(w, h-x) + P_cpu(w, x) - P_gpu(w, h-x).
- *   PPS (pipelined): Huffman decoding of the GPU's rows, the dispatch, then
- *     the CPU decodes its own rows' Huffman data while the GPU works:
- *     f(x) = T_dispatch(w, h-x) + T_huff(w, x, d) / huff_threads
- *            + P_cpu(w, x) - P_gpu(w, h-x).
+ *   OVERLAP (Fig. 7b, Eqs. 12-13): Huffman decoding of the GPU's rows, the
+ *     dispatch, then the CPU decodes its own rows' Huffman data while the
+ *     GPU works:
+ *     f(x) = T_dispatch(w, h-x) + T_huff(w, x, d) + P_cpu(w, x) - P_gpu(w, h-x).
+ *   PPS (pipelined, Eqs. 14-15): the GPU's rows go in chunks, each launched
+ *     as soon as its Huffman data is decoded; after the first chunk of c
+ *     rows the CPU decodes every remaining row's Huffman data, then its own
+ *     rows:
+ *     f(x) = T_huff(w, h-c, d) + P_cpu(w, x) + T_dispatch(w, h-x) - P_gpu(w, h-x),
+ *     with c = min(chunk_rows, h-x).
  * huff_threads: the speed-up of the host Huffman decoder over the model's
- * one-thread rate (restart intervals decode in parallel); >= 1. */
-enum { MJD_PART_SPS = 0, MJD_PART_PPS = 1 };
+ * one-thread rate (restart intervals decode in parallel); >= 1.
+ * chunk_rows: PPS only, the GPU chunk's height in rows (> 0).
+ * MJD_EINVAL for null pointers, a zero dimension, an MCU height other than
+ * 8 or 16, an unknown scheme, huff_threads < 1 or PPS without chunk_rows. */
+enum { MJD_PART_SPS = 0, MJD_PART_OVERLAP = 1, MJD_PART_PPS = 2 };
 
 typedef struct mjd_partition {
-  uint32_t cpu_rows;   /* the CPU's rows: height - (GPU's whole MCU rows) * mcu_h */
+  uint32_t cpu_rows;   /* the CPU's rows: rows - (GPU's whole MCU rows) * mcu_h */
   uint32_t iterations; /* Newton steps taken */
-  double x;            /* the unrounded balance point in rows (0 or height when f keeps one sign) */
+  double x;            /* the unrounded balance point in rows (0 or all rows when f keeps one sign) */
   double t_cpu, t_gpu; /* predicted seconds of both sides at cpu_rows, after the common Huffman prefix */
 } mjd_partition;
 
 int mjd_partition_rows(const mjd_model* model, int scheme, uint32_t width, uint32_t height, uint32_t mcu_h,
-                       uint64_t file_bytes, double huff_threads, mjd_partition* out);
+                       uint64_t file_bytes, double huff_threads, uint32_t chunk_rows, mjd_partition* out);
+
+/* PPS re-partitioning before the GPU's last chunk (paper Sec. 5.2, Eqs.
+ * 16-17).  rows_left: the image's rows from the first row not yet given to
+ * the GPU to the bottom (the last chunk and the CPU's rows; the split is on
+ * an MCU-row boundary of these rows); huff_rows_left: the rows whose Huffman
+ * data is still undecoded; huff_done_s: the measured seconds of Huffman
+ * decoding so far; gpu_busy_s: the estimated device time still owed to the
+ * earlier chunks.  The density of the undecoded rows is
+ *   d' = (max(0, E - huff_done_s) / E) / (huff_rows_left / h) * d,
+ * E = T_huff(w, h, d) the estimate for the whole image, and the split of
+ * rows_left solves
+ *   f(x') = T_dispatch(w, r-x') + T_huff(w, huff_rows_left, d') + P_cpu(w, x')
+ *           - P_gpu(w, r-x') - gpu_busy_s,   r = rows_left.
+ * out->cpu_rows is x' rounded (the CPU's rows, at the bottom of the image).
+ * MJD_EINVAL for null pointers, bad dimensions, rows_left outside
+ * 1..height, negative times or huff_threads < 1. */
+int mjd_repartition_rows(const mjd_model* model, uint32_t width, uint32_t height, uint32_t rows_left, uint32_t mcu_h,
+                         uint64_t file_bytes, double huff_threads, uint32_t huff_rows_left, double huff_done_s,
+                         double gpu_busy_s, mjd_partition* out);
 
 /* ---------------------------------------------------------------------
  * Serving: a request loop that decodes images of different sizes as they

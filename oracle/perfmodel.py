@@ -115,32 +115,75 @@ def predict(model, width: int, height: int, file_bytes: int) -> dict:
 
 # ---- CPU-GPU partitioning (Sec. 5.2) --------------------------------------------------------
 # The GPU decodes the first rows, the CPU the last x (reading of the paper's
-# equations, which name x the CPU's rows).  After the Huffman decoding both
-# sides wait for:
-#   SPS: CPU = T_dispatch(w, h - x) + P_cpu(w, x),        GPU = P_gpu(w, h - x)
-#   PPS: CPU = T_dispatch(w, h - x) + T_huff(w, x, d) / n_huff + P_cpu(w, x),
-#        GPU = P_gpu(w, h - x)
-# (PPS: the CPU decodes its own rows' Huffman data while the GPU works; the
-# GPU's Huffman data is decoded before both.)
+# equations, which name x the CPU's rows).  Huffman time of r rows is
+# huff_per_pixel(d) * w * r / n for n host threads.  After the Huffman
+# decoding that precedes the split both sides take:
+#   SPS (Eqs. 8-10):      CPU = T_dispatch(w, h - x) + P_cpu(w, x)
+#   overlap (Eqs. 12-13): CPU = T_dispatch(w, h - x) + T_huff(w, x, d) + P_cpu(w, x)
+#   PPS (Eqs. 14-15):     CPU = T_huff(w, h - c, d) + P_cpu(w, x) + T_dispatch(w, h - x),
+#                         c = min(chunk, h - x) the GPU's first chunk
+#   and in each            GPU = P_gpu(w, h - x).
+# Readings: the overlap scheme's CPU Huffman term covers the CPU's x rows
+# (the text: the CPU decodes its own part's entropy data while the GPU
+# runs); the first chunk cannot be taller than the GPU's share.
 
-def sides(model, scheme: str, w: int, h: int, file_bytes: int, huff_threads: float, x: float):
+def _huff(model, w, h, file_bytes, rows, n):
+    return eval1(*model["huff_per_pixel"], file_bytes / (w * h)) * w * rows / n
+
+
+def sides(model, scheme: str, w: int, h: int, file_bytes: int, huff_threads: float, x: float, chunk: float = 0.0):
     a = w / 1024.0
     gpu = sum(eval2(*model[p], a, (h - x) / 1024.0) for p in ("o_w", "t_kernel", "o_r"))
     cpu = eval2(*model["t_dispatch"], a, (h - x) / 1024.0) + eval2(*model["p_cpu"], a, x / 1024.0)
-    if scheme == "pps":
-        cpu += eval1(*model["huff_per_pixel"], file_bytes / (w * h)) * w * x / huff_threads
+    if scheme == "overlap":
+        cpu += _huff(model, w, h, file_bytes, x, huff_threads)
+    elif scheme == "pps":
+        cpu += _huff(model, w, h, file_bytes, h - min(chunk, h - x), huff_threads)
     return cpu, gpu
 
 
-def best_partition(model, scheme: str, w: int, h: int, mcu_h: int, file_bytes: int, huff_threads: float = 1.0):
-    """Brute force over every split on an MCU-row boundary -> (later finish
-    time, CPU rows) of the split that minimises the later finish."""
+def best_split(rows: int, mcu_h: int, side_fn):
+    """Brute force over every split of `rows` on an MCU-row boundary (the GPU
+    takes whole MCU rows from the top) -> (later finish, CPU rows)."""
     best = None
-    for r in range(-(-h // mcu_h) + 1):
-        g = min(h, r * mcu_h)
-        x = h - g
-        cpu, gpu = sides(model, scheme, w, h, file_bytes, huff_threads, x)
+    for r in range(-(-rows // mcu_h) + 1):
+        g = min(rows, r * mcu_h)
+        x = rows - g
+        cpu, gpu = side_fn(x)
         t = max(cpu if x else 0.0, gpu if g else 0.0)
         if best is None or t < best[0]:
             best = (t, x)
     return best
+
+
+def best_partition(model, scheme: str, w: int, h: int, mcu_h: int, file_bytes: int, huff_threads: float = 1.0,
+                   chunk: float = 0.0):
+    return best_split(h, mcu_h, lambda x: sides(model, scheme, w, h, file_bytes, huff_threads, x, chunk))
+
+
+# Re-partitioning before the GPU's last chunk (Eqs. 16-17).  r rows remain to
+# be shared (the last chunk's and the CPU's); the Huffman data of u rows is
+# still undecoded, after t_done seconds of decoding; the earlier chunks still
+# owe the GPU `busy` seconds.  Readings: the undecoded rows' density is
+# d' = (max(0, E - t_done) / E) / (u / h) * d with E the model's estimate for
+# the whole image (the share of Huffman time left over the share of height
+# left); the split of the r rows gives the GPU r - x' (the equation's P_GPU
+# argument h - x read as the remainder's r - x'), and the paper's
+# P_prevGPU/T_prevGPU is `busy`.
+#   CPU = T_dispatch(w, r - x') + T_huff(w, u, d') + P_cpu(w, x')
+#   GPU = P_gpu(w, r - x') + busy
+
+def repartition_sides(model, w, h, r, file_bytes, huff_threads, u, t_done, busy, x):
+    d = file_bytes / (w * h)
+    est = eval1(*model["huff_per_pixel"], d) * w * h / huff_threads
+    d_new = (max(0.0, est - t_done) / est) / (u / h) * d if u and est > 0 else 0.0
+    a = w / 1024.0
+    gpu = sum(eval2(*model[p], a, (r - x) / 1024.0) for p in ("o_w", "t_kernel", "o_r")) + busy
+    cpu = (eval2(*model["t_dispatch"], a, (r - x) / 1024.0) + eval1(*model["huff_per_pixel"], d_new) * w * u
+           / huff_threads + eval2(*model["p_cpu"], a, x / 1024.0))
+    return cpu, gpu
+
+
+def best_repartition(model, w, h, r, mcu_h, file_bytes, huff_threads, u, t_done, busy):
+    return best_split(r, mcu_h, lambda x: repartition_sides(model, w, h, r, file_bytes, huff_threads, u, t_done,
+                                                            busy, x))

@@ -4,9 +4,9 @@ chroma upsampling -> YCbCr->RGB as one fused HIP kernel behind a C ABI
 """
 from __future__ import annotations
 
-from ._binding import (MJD_PART_PPS, MJD_PART_SPS, MJD_SERVE_CONTINUOUS, MJD_SERVE_SYNC,  # noqa: F401
+from ._binding import (MJD_PART_OVERLAP, MJD_PART_PPS, MJD_PART_SPS, MJD_SERVE_CONTINUOUS, MJD_SERVE_SYNC,  # noqa: F401
                        MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE,
-                       Batch, Context, EntropyBatch, Hetero, MjdError, Pipeline, Server, mjd_partition_rows,
+                       Batch, Context, EntropyBatch, Hetero, MjdError, Pipeline, Server, mjd_partition_rows, mjd_repartition_rows,
                        mjd_batch_create, mjd_batch_destroy, mjd_batch_launch,
                        mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
                        mjd_decode, mjd_decode_host, mjd_entropy_batch_create, mjd_entropy_batch_destroy,

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_PKG, "_lib", "libmjd.so")
 MJD_OK = 0
 MJD_POLY_MAX_DEGREE = 7
 MJD_PART_SPS = 0
-MJD_PART_PPS = 1
+MJD_PART_OVERLAP = 1
+MJD_PART_PPS = 2
 MJD_EINVAL = -1
 MJD_EUNSUPPORTED = -2
 MJD_ENOMEM = -3
@@ -101,7 +102,13 @@ class mjd_partition(ctypes.Structure):
 
 class mjd_hetero_times(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in ("huff_gpu_s", "dispatch_s", "huff_cpu_s", "cpu_s", "gpu_s",
-                                               "total_s")]
+                                               "total_s")] + [("chunks", ctypes.c_uint32),
+                                                              ("cpu_rows", ctypes.c_uint32)]
+
+
+class mjd_hetero_plan(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_int32), ("cpu_rows", ctypes.c_uint32), ("chunk_mcu_rows", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("model", ctypes.c_void_p), ("huff_threads", ctypes.c_double)]
 
 
 class mjd_pipeline_config(ctypes.Structure):
@@ -199,11 +206,16 @@ def lib() -> ctypes.CDLL:
                                         ctypes.POINTER(mjd_prediction)]
         L.mjd_model_predict.restype = i32
         L.mjd_partition_rows.argtypes = [ctypes.POINTER(mjd_model), i32, u32, u32, u32, ctypes.c_uint64,
-                                         ctypes.c_double, ctypes.POINTER(mjd_partition)]
+                                         ctypes.c_double, u32, ctypes.POINTER(mjd_partition)]
         L.mjd_partition_rows.restype = i32
+        L.mjd_repartition_rows.argtypes = [ctypes.POINTER(mjd_model), u32, u32, u32, u32, ctypes.c_uint64,
+                                           ctypes.c_double, u32, ctypes.c_double, ctypes.c_double,
+                                           ctypes.POINTER(mjd_partition)]
+        L.mjd_repartition_rows.restype = i32
         L.mjd_hetero_create.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, i32, ctypes.POINTER(vp)]
         L.mjd_hetero_create.restype = i32
-        L.mjd_hetero_decode.argtypes = [vp, vp, sz, i32, i32, u32, vp, sz, ctypes.POINTER(mjd_hetero_times)]
+        L.mjd_hetero_decode.argtypes = [vp, vp, sz, i32, ctypes.POINTER(mjd_hetero_plan), vp, sz,
+                                        ctypes.POINTER(mjd_hetero_times)]
         L.mjd_hetero_decode.restype = i32
         L.mjd_hetero_destroy.argtypes = [vp]
         L.mjd_hetero_destroy.restype = None
@@ -544,10 +556,19 @@ def mjd_model_predict(model: mjd_model, width: int, height: int, file_bytes: int
 
 
 def mjd_partition_rows(model: mjd_model, scheme: int, width: int, height: int, mcu_h: int, file_bytes: int,
-                       huff_threads: float = 1.0) -> dict:
+                       huff_threads: float = 1.0, chunk_rows: int = 0) -> dict:
     out = mjd_partition()
     _check(lib().mjd_partition_rows(ctypes.byref(model), int(scheme), int(width), int(height), int(mcu_h),
-                                    int(file_bytes), float(huff_threads), ctypes.byref(out)))
+                                    int(file_bytes), float(huff_threads), int(chunk_rows), ctypes.byref(out)))
+    return {k: getattr(out, k) for k, _ in mjd_partition._fields_}
+
+
+def mjd_repartition_rows(model: mjd_model, width: int, height: int, rows_left: int, mcu_h: int, file_bytes: int,
+                         huff_threads: float, huff_rows_left: int, huff_done_s: float, gpu_busy_s: float) -> dict:
+    out = mjd_partition()
+    _check(lib().mjd_repartition_rows(ctypes.byref(model), int(width), int(height), int(rows_left), int(mcu_h),
+                                      int(file_bytes), float(huff_threads), int(huff_rows_left), float(huff_done_s),
+                                      float(gpu_busy_s), ctypes.byref(out)))
     return {k: getattr(out, k) for k, _ in mjd_partition._fields_}
 
 
@@ -561,11 +582,15 @@ class Hetero:
         self.handle = p
 
     def decode(self, jpg, rgb, pitch: int, cpu_rows: int, scheme: int = MJD_PART_SPS,
-               upsample: int = MJD_UPSAMPLE_FANCY) -> dict:
+               upsample: int = MJD_UPSAMPLE_FANCY, chunk_mcu_rows: int = 0, model: mjd_model | None = None,
+               huff_threads: float = 1.0) -> dict:
         a, n = _bytes_view(jpg)
+        plan = mjd_hetero_plan(scheme=int(scheme), cpu_rows=int(cpu_rows), chunk_mcu_rows=int(chunk_mcu_rows),
+                               model=ctypes.cast(ctypes.pointer(model), ctypes.c_void_p) if model is not None else None,
+                               huff_threads=float(huff_threads))
         t = mjd_hetero_times()
-        _check(lib().mjd_hetero_decode(self.handle, _ptr(a), n, int(upsample), int(scheme), int(cpu_rows),
-                                       _ptr(rgb), int(pitch), ctypes.byref(t)))
+        _check(lib().mjd_hetero_decode(self.handle, _ptr(a), n, int(upsample), ctypes.byref(plan), _ptr(rgb),
+                                       int(pitch), ctypes.byref(t)))
         return {k: getattr(t, k) for k, _ in mjd_hetero_times._fields_}
 
     def close(self):

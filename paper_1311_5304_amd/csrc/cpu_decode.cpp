@@ -21,9 +21,9 @@
 #include <string.h>
 
 #include <algorithm>
-#include <thread>
 #include <vector>
 
+#include "cpu_decode.h"
 #include "mjd.h"
 #include "mjd_common.h"
 
@@ -200,8 +200,9 @@ static void decode_band(const Plan& p, const int16_t* coef, const uint16_t* qt, 
 }  // namespace cpu
 }  // namespace mjd
 
-extern "C" int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, const uint16_t* h_qt, int upsample,
-                               uint8_t* h_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads) {
+int mjd::cpu::decode_host_with(const mjd_frame* frame, const int16_t* h_coef, const uint16_t* h_qt, int upsample,
+                               uint8_t* h_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads,
+                               const ParallelFor& pf) {
   using namespace mjd::cpu;
   if (!frame || !h_coef || !h_qt || !h_rgb) return mjd::fail(MJD_EINVAL, "null frame or buffer pointer");
   if (upsample != MJD_UPSAMPLE_SIMPLE && upsample != MJD_UPSAMPLE_FANCY)
@@ -228,15 +229,16 @@ extern "C" int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, co
   // split the rows into per-thread bands of whole MCU rows
   const int nrows = static_cast<int>(mcu_row1 - mcu_row0);
   const int nt = std::min(n_threads, nrows);
-  std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t) {
+  pf(nt, [&](int t) {
     const int ra = static_cast<int>(mcu_row0) + nrows * t / nt, rb = static_cast<int>(mcu_row0) + nrows * (t + 1) / nt;
     const int ya = ra * mh, yb = std::min(H, rb * mh);
-    if (ya >= yb) continue;
-    auto work = [&p, h_coef, h_qt, fancy, ya, yb, h_rgb, pitch] { decode_band(p, h_coef, h_qt, fancy, ya, yb, h_rgb, pitch); };
-    if (t + 1 == nt) work();
-    else th.emplace_back(work);
-  }
-  for (auto& x : th) x.join();
+    if (ya < yb) decode_band(p, h_coef, h_qt, fancy, ya, yb, h_rgb, pitch);
+  });
   return MJD_OK;
+}
+
+extern "C" int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, const uint16_t* h_qt, int upsample,
+                               uint8_t* h_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads) {
+  return mjd::cpu::decode_host_with(frame, h_coef, h_qt, upsample, h_rgb, pitch, mcu_row0, mcu_row1, n_threads,
+                                    [n_threads](int n, const mjd::TaskFn& fn) { mjd::spawn_for(n_threads, n, fn); });
 }

@@ -6,6 +6,7 @@
 
 #include <string>
 
+#include "host_pool.h"
 #include "mjd.h"
 
 namespace mjd {
@@ -49,6 +50,21 @@ int decode_interval(const uint8_t* jpg, const mjd_scan* scan, const ScanLayout& 
 
 int decode_rows(const uint8_t* jpg, size_t len, const mjd_scan* scan, const uint64_t* offsets, int16_t* coef,
                 uint32_t row0, uint32_t row1, int n_threads);
+
+// One scan made ready for decoding MCU-row ranges: layout, tables, and the
+// restart index checked against the stream once, for callers that decode an
+// image in many ranges.  Holds pointers to jpg, scan and offsets.
+struct RowDecoder {
+  const uint8_t* jpg = nullptr;
+  const mjd_scan* scan = nullptr;
+  const uint64_t* offsets = nullptr;
+  ScanLayout L;
+  ScanTables T;
+};
+int prepare_rows(const uint8_t* jpg, size_t len, const mjd_scan* scan, const uint64_t* offsets, RowDecoder* out);
+
+// Decodes MCU rows [row0, row1) into coef, one task per restart interval.
+int decode_rows_with(const RowDecoder& D, int16_t* coef, uint32_t row0, uint32_t row1, const ParallelFor& pf);
 
 }  // namespace host
 }  // namespace mjd

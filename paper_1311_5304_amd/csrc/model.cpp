@@ -91,21 +91,83 @@ struct Sides {
   double cpu, gpu, f, df;
 };
 
-static Sides sides(const mjd_model& m, int scheme, double w, double h, double hpp, double huff_threads, double x) {
+// One split problem: the rows h being shared (the GPU takes the first h - x),
+// the Huffman terms of the CPU's side and a constant added to the GPU's.
+struct Split {
+  int scheme;
+  double w, h;
+  double hpp;          // the model's Huffman seconds per pixel at the image's density
+  double n;            // huff_threads
+  double chunk;        // PPS: rows of the GPU's first chunk
+  double huff_fixed;   // re-partitioning: seconds of Huffman decoding of all remaining rows
+  double gpu_fixed;    // re-partitioning: the earlier chunks' remaining device time
+};
+
+static Sides sides(const mjd_model& m, const Split& q, double x) {
+  const double w = q.w, h = q.h;
   const double a = w / 1024.0, bc = x / 1024.0, bg = (h - x) / 1024.0;
   Sides s;
   const double pgpu = mjd_poly2_eval(&m.o_w, a, bg) + mjd_poly2_eval(&m.t_kernel, a, bg) + mjd_poly2_eval(&m.o_r, a, bg);
   const double dpgpu = poly2_db(m.o_w, a, bg) + poly2_db(m.t_kernel, a, bg) + poly2_db(m.o_r, a, bg);
-  s.cpu = mjd_poly2_eval(&m.t_dispatch, a, bg) + mjd_poly2_eval(&m.p_cpu, a, bc);
+  s.cpu = mjd_poly2_eval(&m.t_dispatch, a, bg) + mjd_poly2_eval(&m.p_cpu, a, bc) + q.huff_fixed;
   double dcpu = (-poly2_db(m.t_dispatch, a, bg) + poly2_db(m.p_cpu, a, bc)) / 1024.0;
-  if (scheme == MJD_PART_PPS) {
-    s.cpu += hpp * w * x / huff_threads;
-    dcpu += hpp * w / huff_threads;
+  if (q.scheme == MJD_PART_OVERLAP) {  // the CPU's own rows
+    s.cpu += q.hpp * w * x / q.n;
+    dcpu += q.hpp * w / q.n;
+  } else if (q.scheme == MJD_PART_PPS) {  // every row after the GPU's first chunk
+    const double c = std::min(q.chunk, h - x);
+    s.cpu += q.hpp * w * (h - c) / q.n;
+    if (q.chunk > h - x) dcpu += q.hpp * w / q.n;
   }
-  s.gpu = pgpu;
+  s.gpu = pgpu + q.gpu_fixed;
   s.f = s.cpu - s.gpu;
   s.df = dcpu + dpgpu / 1024.0;  // d/dx P_gpu(w, h - x) = -dP/db / 1024
   return s;
+}
+
+// Newton's method for f(x) = 0 on [0, h]: the ends when f keeps one sign,
+// else from the middle, kept inside [0, h]; it stops when a step no longer
+// reduces |f| or moves less than a quarter row.  Then the GPU keeps whole
+// MCU rows: the nearest split on an MCU-row boundary of the h rows.
+static void solve(const mjd_model& m, const Split& q, uint32_t rows, uint32_t mcu_h, mjd_partition* out) {
+  const double h = q.h;
+  uint32_t it = 0;
+  double x;
+  if (sides(m, q, 0.0).f >= 0.0) {
+    x = 0.0;  // even no rows on the CPU finish no earlier than the GPU's share
+  } else if (sides(m, q, h).f <= 0.0) {
+    x = h;  // the CPU alone finishes first
+  } else {
+    x = h / 2;
+    Sides cur = sides(m, q, x);
+    for (it = 0; it < 100; ++it) {
+      if (!(cur.df > 0.0)) break;
+      double nx = x - cur.f / cur.df;
+      nx = nx < 0.0 ? 0.0 : (nx > h ? h : nx);
+      const Sides nxt = sides(m, q, nx);
+      if (fabs(nxt.f) >= fabs(cur.f)) break;
+      const double step = fabs(nx - x);
+      x = nx;
+      cur = nxt;
+      if (step < 0.25) {
+        ++it;
+        break;
+      }
+    }
+  }
+  // the splits are k * mcu_h for k < the MCU rows, and all the rows (the
+  // last MCU row may be partial): take the nearest to h - x
+  const double target = h - x;
+  const uint32_t mcus = (rows + mcu_h - 1) / mcu_h;
+  const uint32_t k = std::min(mcus, static_cast<uint32_t>(target / mcu_h));
+  const uint32_t lo = std::min(rows, k * mcu_h), hi = std::min(rows, (k + 1) * mcu_h);
+  const uint32_t gpu_rows = target - lo <= hi - target ? lo : hi;
+  out->cpu_rows = rows - gpu_rows;
+  out->iterations = it;
+  out->x = x;
+  const Sides fin = sides(m, q, static_cast<double>(out->cpu_rows));
+  out->t_cpu = out->cpu_rows ? fin.cpu : 0.0;
+  out->t_gpu = gpu_rows ? fin.gpu : 0.0;
 }
 
 }  // namespace model
@@ -232,52 +294,40 @@ int mjd_model_predict(const mjd_model* m, uint32_t width, uint32_t height, uint6
 }
 
 int mjd_partition_rows(const mjd_model* m, int scheme, uint32_t width, uint32_t height, uint32_t mcu_h,
-                       uint64_t file_bytes, double huff_threads, mjd_partition* out) {
+                       uint64_t file_bytes, double huff_threads, uint32_t chunk_rows, mjd_partition* out) {
   if (!m || !out) return mjd::fail(MJD_EINVAL, "null model or output pointer");
   if (!width || !height || (mcu_h != 8 && mcu_h != 16)) return mjd::fail(MJD_EINVAL, "bad image or MCU height");
-  if (scheme != MJD_PART_SPS && scheme != MJD_PART_PPS) return mjd::fail(MJD_EINVAL, "unknown scheme %d", scheme);
+  if (scheme != MJD_PART_SPS && scheme != MJD_PART_OVERLAP && scheme != MJD_PART_PPS)
+    return mjd::fail(MJD_EINVAL, "unknown scheme %d", scheme);
   if (!(huff_threads >= 1.0)) return mjd::fail(MJD_EINVAL, "huff_threads below 1");
+  if (scheme == MJD_PART_PPS && !chunk_rows) return mjd::fail(MJD_EINVAL, "PPS needs a chunk height");
   const double w = width, h = height;
-  const double hpp = mjd_poly1_eval(&m->huff_per_pixel, static_cast<double>(file_bytes) / (w * h));
-  uint32_t it = 0;
-  double x;
-  const Sides s0 = sides(*m, scheme, w, h, hpp, huff_threads, 0.0), sh = sides(*m, scheme, w, h, hpp, huff_threads, h);
-  if (s0.f >= 0.0) {
-    x = 0.0;  // even no rows on the CPU finish no earlier than the GPU's share
-  } else if (sh.f <= 0.0) {
-    x = h;  // the CPU alone finishes first
-  } else {
-    // Newton's method from the middle, kept inside [0, h]; it stops when a
-    // step no longer reduces |f| or moves less than a quarter row
-    x = h / 2;
-    Sides cur = sides(*m, scheme, w, h, hpp, huff_threads, x);
-    for (it = 0; it < 100; ++it) {
-      if (!(cur.df > 0.0)) break;
-      double nx = x - cur.f / cur.df;
-      nx = nx < 0.0 ? 0.0 : (nx > h ? h : nx);
-      const Sides nxt = sides(*m, scheme, w, h, hpp, huff_threads, nx);
-      if (fabs(nxt.f) >= fabs(cur.f)) break;
-      const double step = fabs(nx - x);
-      x = nx;
-      cur = nxt;
-      if (step < 0.25) {
-        ++it;
-        break;
-      }
-    }
-  }
-  // the GPU keeps whole MCU rows: the nearest split on an MCU-row boundary
-  const uint32_t mcus_y = (height + mcu_h - 1) / mcu_h;
-  double gr = (h - x) / mcu_h;
-  uint32_t gpu_mcu_rows = static_cast<uint32_t>(gr + 0.5);
-  if (gpu_mcu_rows > mcus_y) gpu_mcu_rows = mcus_y;
-  const uint32_t gpu_rows = std::min(height, gpu_mcu_rows * mcu_h);
-  out->cpu_rows = height - gpu_rows;
-  out->iterations = it;
-  out->x = x;
-  const Sides fin = sides(*m, scheme, w, h, hpp, huff_threads, static_cast<double>(out->cpu_rows));
-  out->t_cpu = out->cpu_rows ? fin.cpu : 0.0;
-  out->t_gpu = gpu_rows ? fin.gpu : 0.0;
+  Split q{scheme, w, h, mjd_poly1_eval(&m->huff_per_pixel, static_cast<double>(file_bytes) / (w * h)), huff_threads,
+          static_cast<double>(chunk_rows), 0.0, 0.0};
+  solve(*m, q, height, mcu_h, out);
+  return MJD_OK;
+}
+
+int mjd_repartition_rows(const mjd_model* m, uint32_t width, uint32_t height, uint32_t rows_left, uint32_t mcu_h,
+                         uint64_t file_bytes, double huff_threads, uint32_t huff_rows_left, double huff_done_s,
+                         double gpu_busy_s, mjd_partition* out) {
+  if (!m || !out) return mjd::fail(MJD_EINVAL, "null model or output pointer");
+  if (!width || !height || (mcu_h != 8 && mcu_h != 16)) return mjd::fail(MJD_EINVAL, "bad image or MCU height");
+  if (!rows_left || rows_left > height || huff_rows_left > height)
+    return mjd::fail(MJD_EINVAL, "remaining rows outside 1..height");
+  if (!(huff_threads >= 1.0) || !(huff_done_s >= 0.0) || !(gpu_busy_s >= 0.0))
+    return mjd::fail(MJD_EINVAL, "negative time or huff_threads below 1");
+  const double w = width, h = height;
+  const double d = static_cast<double>(file_bytes) / (w * h);
+  const double est = mjd_poly1_eval(&m->huff_per_pixel, d) * w * h / huff_threads;
+  // Eq. 17: the density of the rows still to decode, from the share of the
+  // estimated Huffman time left against the share of the height left
+  double d_new = 0.0;
+  if (huff_rows_left && est > 0.0)
+    d_new = std::max(0.0, est - huff_done_s) / est / (huff_rows_left / h) * d;
+  Split q{MJD_PART_SPS, w, static_cast<double>(rows_left), 0.0, huff_threads, 0.0,
+          mjd_poly1_eval(&m->huff_per_pixel, d_new) * w * huff_rows_left / huff_threads, gpu_busy_s};
+  solve(*m, q, rows_left, mcu_h, out);
   return MJD_OK;
 }
 

@@ -215,24 +215,71 @@ def _model_pair(M, cpu_rate, gpu_rate, dispatch, hpp):
     return m, o
 
 
-@pytest.mark.parametrize("scheme", ["sps", "pps"])
+SCHEMES = ["sps", "overlap", "pps"]
+
+
+def _code(M, scheme):
+    return {"sps": M.MJD_PART_SPS, "overlap": M.MJD_PART_OVERLAP, "pps": M.MJD_PART_PPS}[scheme]
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
 def test_newton_partition_matches_brute_force(M, scheme):
-    code = M.MJD_PART_SPS if scheme == "sps" else M.MJD_PART_PPS
-    cases = [(2e-3, 2e-3, 1e-5, 5e-10), (4e-3, 1e-3, 2e-5, 1e-9), (1e-3, 3e-3, 1e-5, 2e-9)]
+    code = _code(M, scheme)
+    cases = [(2e-3, 2e-3, 1e-5, 5e-10), (4e-3, 1e-3, 2e-5, 1e-9), (1e-3, 3e-3, 1e-5, 2e-9), (1e-3, 4e-3, 1e-5, 1e-10)]
     for cpu_rate, gpu_rate, dispatch, hpp in cases:
         m, o = _model_pair(M, cpu_rate, gpu_rate, dispatch, hpp)
         for w, h, mh in ((4096, 3072, 16), (1000, 777, 16), (640, 480, 8)):
             nbytes = w * h // 3
-            got = M.mjd_partition_rows(m, code, w, h, mh, nbytes, 4.0)
-            t_best, x_best = O.best_partition(o, scheme, w, h, mh, nbytes, 4.0)
+            chunk = 4 * mh if scheme == "pps" else 0
+            got = M.mjd_partition_rows(m, code, w, h, mh, nbytes, 4.0, chunk)
+            t_best, x_best = O.best_partition(o, scheme, w, h, mh, nbytes, 4.0, chunk)
             assert abs(got["cpu_rows"] - x_best) <= mh, (cpu_rate, gpu_rate, w, h)
             # the continuous root balances both sides
             if 0 < got["x"] < h:
-                cpu, gpu = O.sides(o, scheme, w, h, nbytes, 4.0, got["x"])
+                cpu, gpu = O.sides(o, scheme, w, h, nbytes, 4.0, got["x"], chunk)
                 assert math.isclose(cpu, gpu, rel_tol=1e-6)
             assert got["iterations"] >= 1 or got["x"] in (0.0, float(h))
-            cpu, gpu = O.sides(o, scheme, w, h, nbytes, 4.0, got["cpu_rows"])
+            cpu, gpu = O.sides(o, scheme, w, h, nbytes, 4.0, got["cpu_rows"], chunk)
             assert math.isclose(got["t_gpu"], gpu if got["cpu_rows"] < h else 0.0, rel_tol=1e-9)
+            if got["cpu_rows"]:
+                assert math.isclose(got["t_cpu"], cpu, rel_tol=1e-9)
+
+
+def test_repartition_matches_brute_force(M):
+    m, o = _model_pair(M, 1e-3, 3e-3, 1e-5, 2e-9)
+    w, h, mh = 4096, 3072, 16
+    nbytes = w * h // 3
+    est = 2e-9 * w * h / 4.0
+    for r, u, t_done, busy in ((1024, 1008, 0.5 * est, 0.0), (1024, 1008, 0.9 * est, 1e-3), (512, 500, 0.2 * est, 0.0),
+                               (3072, 3072, 0.0, 0.0), (200, 0, est, 5e-4), (1024, 1008, 2.0 * est, 0.0)):
+        got = M.mjd_repartition_rows(m, w, h, r, mh, nbytes, 4.0, u, t_done, busy)
+        _, x_best = O.best_repartition(o, w, h, r, mh, nbytes, 4.0, u, t_done, busy)
+        assert abs(got["cpu_rows"] - x_best) <= mh, (r, u, t_done, busy)
+        assert 0 <= got["cpu_rows"] <= r
+        if 0 < got["x"] < r:
+            cpu, gpu = O.repartition_sides(o, w, h, r, nbytes, 4.0, u, t_done, busy, got["x"])
+            assert math.isclose(cpu, gpu, rel_tol=1e-6)
+    with pytest.raises(M.MjdError):
+        M.mjd_repartition_rows(m, w, h, 0, mh, nbytes, 4.0, 0, 0.0, 0.0)
+    with pytest.raises(M.MjdError):
+        M.mjd_repartition_rows(m, w, h, 100, mh, nbytes, 4.0, 100, -1.0, 0.0)
+
+
+def test_oracle_repartition_density_closed_form():
+    # Huffman on schedule (t_done the decoded rows' share of the estimate)
+    # keeps d' = d; behind schedule the rest is sparser; past the estimate, zero
+    o = {"huff_per_pixel": (1, [0.0, 1e-9]), "p_cpu": (0, [0.0]), "t_dispatch": (0, [0.0]),
+         "o_w": (0, [0.0]), "t_kernel": (0, [0.0]), "o_r": (0, [0.0])}
+    w, h, nbytes, n = 1000, 1000, 400_000, 2.0
+    d = nbytes / (w * h)
+    est = 1e-9 * d * w * h / n
+    u = 250
+    cpu, _ = O.repartition_sides(o, w, h, 300, nbytes, n, u, est * (1 - u / h), 0.0, 0.0)
+    assert math.isclose(cpu, 1e-9 * d * w * u / n, rel_tol=1e-12)
+    cpu, _ = O.repartition_sides(o, w, h, 300, nbytes, n, u, est * (1 - u / h) + 0.5 * est * u / h, 0.0, 0.0)
+    assert math.isclose(cpu, 0.5 * 1e-9 * d * w * u / n, rel_tol=1e-12)
+    cpu, _ = O.repartition_sides(o, w, h, 300, nbytes, n, u, 2 * est, 0.0, 0.0)
+    assert cpu == 0.0
 
 
 def test_partition_ends(M):
@@ -241,16 +288,26 @@ def test_partition_ends(M):
     assert M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, 3072, 16, 10 ** 6)["cpu_rows"] == 0
     m, _ = _model_pair(M, 1e-6, 1.0, 0.0, 1e-9)
     assert M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, 3072, 16, 10 ** 6)["cpu_rows"] == 3072
+    # heights off the MCU grid: the GPU's share may end in the partial MCU row
+    for h, mh in ((121, 8), (777, 16), (3000, 16)):
+        m, _ = _model_pair(M, 1.0, 1e-6, 1e-4, 1e-9)
+        assert M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, h, mh, 10 ** 6)["cpu_rows"] == 0
+        assert M.mjd_repartition_rows(m, 4096, h, h - mh, mh, 10 ** 6, 1.0, 0, 0.0, 0.0)["cpu_rows"] == 0
+        m, _ = _model_pair(M, 1e-6, 1.0, 0.0, 1e-9)
+        assert M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, h, mh, 10 ** 6)["cpu_rows"] == h
     with pytest.raises(M.MjdError):
         M.mjd_partition_rows(m, 7, 4096, 3072, 16, 10 ** 6)
     with pytest.raises(M.MjdError):
         M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, 3072, 12, 10 ** 6)
+    with pytest.raises(M.MjdError):  # PPS needs its chunk height
+        M.mjd_partition_rows(m, M.MJD_PART_PPS, 4096, 3072, 16, 10 ** 6)
 
 
-@pytest.mark.parametrize("scheme", ["sps", "pps"])
+@pytest.mark.parametrize("scheme", SCHEMES)
 def test_oracle_sides_balance_at_the_linear_closed_form(scheme):
-    # linear costs: CPU = D + c*A*x (+ hpp*w*x/n for PPS), GPU = g*A*(h - x),
-    # A = w / 1024^2, so the sides meet at x = (g*A*h - D) / (c*A + g*A (+ hpp*w/n))
+    # linear costs: CPU = D + c*A*x + H(x), GPU = g*A*(h - x), A = w / 1024^2,
+    # H(x) = 0 (SPS), hpp*w*x/n (overlap), hpp*w*(h - chunk)/n (PPS, chunk
+    # below the GPU's rows), so the sides meet at x = (g*A*h - D - H0) / slope
     cpu_rate, gpu_rate, dispatch, hpp, n = 3e-3, 1e-3, 2e-4, 1e-9, 4.0
     o = {"huff_per_pixel": (0, [hpp])}
     for name, val in (("o_w", 0.0), ("t_kernel", gpu_rate), ("o_r", 0.0), ("p_cpu", cpu_rate),
@@ -260,16 +317,17 @@ def test_oracle_sides_balance_at_the_linear_closed_form(scheme):
         if name == "t_dispatch":
             c[0] = dispatch
         o[name] = (2, c)
-    w, h, mh = 4096, 3072, 16
+    w, h, mh, chunk = 4096, 3072, 16, 128
     A = w / 1024.0 ** 2
-    slope = cpu_rate * A + gpu_rate * A + (hpp * w / n if scheme == "pps" else 0.0)
-    x = (gpu_rate * A * h - dispatch) / slope
-    assert 0 < x < h
-    cpu, gpu = O.sides(o, scheme, w, h, w * h // 3, n, x)
+    slope = cpu_rate * A + gpu_rate * A + (hpp * w / n if scheme == "overlap" else 0.0)
+    h0 = hpp * w * (h - chunk) / n if scheme == "pps" else 0.0
+    x = (gpu_rate * A * h - dispatch - h0) / slope
+    assert 0 < x < h - chunk
+    cpu, gpu = O.sides(o, scheme, w, h, w * h // 3, n, x, chunk)
     assert math.isclose(cpu, gpu, rel_tol=1e-12)
     assert math.isclose(gpu, gpu_rate * A * (h - x), rel_tol=1e-12)
     # the brute force's split is the MCU-row boundary on either side of the root
-    t, xb = O.best_partition(o, scheme, w, h, mh, w * h // 3, n)
+    t, xb = O.best_partition(o, scheme, w, h, mh, w * h // 3, n, chunk)
     assert abs(xb - x) < mh
     assert t >= gpu - 1e-15
 
