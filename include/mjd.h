@@ -154,6 +154,52 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef,
 int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, const uint16_t* h_qt, int upsample,
                     uint8_t* h_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads);
 
+/* ---------------------------------------------------------------------
+ * Decoder variants (paper Sec. 2 and Sec. 3 name libjpeg's AAN-based and
+ * integer-or-float IDCTs; Sec. 4.2 decodes samplings other than 4:4:4 and
+ * 4:2:2 the same way).  A generic path of two launches: dequantise + IDCT
+ * into per-component sample planes in a caller workspace, then upsampling
+ * + colour conversion; grayscale writes its rows from the first launch.
+ * IDCT methods:
+ *   MJD_IDCT_ISLOW  LL&M in 13-bit fixed point (mjd_decode's arithmetic);
+ *   MJD_IDCT_IFAST  the AAN flowgraph (transposed forward graph) in fixed
+ *                   point: multipliers q * 2^6 / (s(u) s(v)) with
+ *                   s(0) = 1, s(k) = sqrt(2) cos(k pi / 16), 9-bit
+ *                   constants, truncating products; less accurate;
+ *   MJD_IDCT_FLOAT  the same flowgraph in IEEE single precision.
+ * Samplings: luma (h, v) of (1,1), (2,1), (1,2), (2,2) or (4,1), chroma
+ * (1,1); fancy upsampling filters factors of 2 (Algorithm 1, vertical for
+ * (1,2)) and replicates a factor of 4.  Grayscale: one component, blocks in
+ * raster order, one output byte per pixel.
+ * ------------------------------------------------------------------- */
+enum { MJD_IDCT_ISLOW = 0, MJD_IDCT_IFAST = 1, MJD_IDCT_FLOAT = 2 };
+
+typedef struct mjd_variant {
+  mjd_frame frame;   /* as for mjd_decode; grayscale reads width, height, qsel[0] */
+  uint32_t ncomp;    /* 3: YCbCr -> RGB8 (3 bytes per pixel); 1: grayscale (1 byte per pixel) */
+  int32_t idct;      /* MJD_IDCT_* */
+  int32_t upsample;  /* MJD_UPSAMPLE_* (unused for grayscale) */
+  uint32_t reserved; /* must be 0 */
+} mjd_variant;
+
+/* Host only: validates `variant` and gives its geometry (grayscale:
+ * 8x8 MCUs of one block; comp_w/comp_h of absent components 0) and the
+ * workspace mjd_decode_variant needs (0 for grayscale).  out and work_bytes
+ * may be NULL.  MJD_EINVAL for bad fields, MJD_EUNSUPPORTED for other
+ * samplings. */
+int mjd_variant_geometry(const mjd_variant* variant, mjd_geometry* out, uint64_t* work_bytes);
+
+/* Decodes a whole image.  d_coef: n_blocks * 64 int16 in MCU order,
+ * 16-byte aligned (same numeric domain as mjd_decode); d_qt: uint16[4][64];
+ * d_out: rows of `pitch` bytes (pitch >= ncomp * width, < 2^31), only each
+ * row's first ncomp * width bytes written; d_work: device workspace of at
+ * least the size mjd_variant_geometry gives, 16-byte aligned, owned by the
+ * caller, overwritten (may be NULL for grayscale).  Asynchronous on
+ * `stream`.  MJD_EINVAL for bad arguments, MJD_EDEVICE for launch
+ * failures. */
+int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* d_coef, const uint16_t* d_qt,
+                       uint8_t* d_out, size_t pitch, void* d_work, uint64_t work_bytes, void* stream);
+
 /* Heterogeneous decode of one bitstream (paper Sec. 5.2): the GPU decodes
  * the image's first MCU rows while host threads decode the rest, as a
  * partition (mjd_partition_rows) assigns them.  Owns pinned coefficient

@@ -4,9 +4,10 @@ chroma upsampling -> YCbCr->RGB as one fused HIP kernel behind a C ABI
 """
 from __future__ import annotations
 
-from ._binding import (MJD_PART_OVERLAP, MJD_PART_PPS, MJD_PART_SPS, MJD_SERVE_CONTINUOUS, MJD_SERVE_SYNC,  # noqa: F401
+from ._binding import (MJD_IDCT_FLOAT, MJD_IDCT_IFAST, MJD_IDCT_ISLOW, MJD_PART_OVERLAP, MJD_PART_PPS, MJD_PART_SPS, MJD_SERVE_CONTINUOUS, MJD_SERVE_SYNC,  # noqa: F401
                        MJD_UPSAMPLE_FANCY, MJD_UPSAMPLE_SIMPLE,
-                       Batch, Context, EntropyBatch, Hetero, MjdError, Pipeline, Server, mjd_partition_rows, mjd_repartition_rows,
+                       Batch, Context, EntropyBatch, Hetero, MjdError, Pipeline, Server, make_variant, mjd_decode_variant, mjd_partition_rows,
+                       mjd_repartition_rows, mjd_variant, mjd_variant_geometry,
                        mjd_batch_create, mjd_batch_destroy, mjd_batch_launch,
                        mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
                        mjd_decode, mjd_decode_host, mjd_entropy_batch_create, mjd_entropy_batch_destroy,
@@ -40,6 +41,31 @@ def decode(ctx: Context, frame, coef, qt, mode: str = "fancy", out=None, rows=No
         raise ValueError("out must be a contiguous uint8 tensor [H, W, 3]")
     r0, r1 = rows if rows is not None else (0, g["mcus_y"])
     mjd_decode(ctx, frame, coef, qt, UPSAMPLE[mode], out, 3 * w, r0, r1, stream)
+    return out
+
+
+def decode_variant(ctx: Context, frame, coef, qt, idct: str = "islow", mode: str = "fancy", ncomp: int = 3,
+                   out=None, stream=None):
+    """Decode one image through the variants path (IDCT method `idct`,
+    samplings (1,1), (2,1), (1,2), (2,2), (4,1), or grayscale with ncomp=1).
+    Allocates the plane workspace with torch.  Returns `out`: uint8
+    [H, W, 3], or [H, W] for grayscale."""
+    import torch
+
+    v = make_variant(frame, ncomp, idct, mode)
+    g, wb = mjd_variant_geometry(v)
+    if coef.numel() != g["n_blocks"] * 64 or coef.element_size() != 2 or not coef.is_cuda:
+        raise ValueError("coef must be a CUDA int16 tensor of n_blocks*64 elements")
+    if qt.numel() != 256 or qt.element_size() != 2 or not qt.is_cuda:
+        raise ValueError("qt must be a CUDA 16-bit tensor of 4*64 entries")
+    h, w = int(frame["height"]), int(frame["width"])
+    shape = (h, w, 3) if ncomp == 3 else (h, w)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.uint8, device=coef.device)
+    if tuple(out.shape) != shape or out.dtype != torch.uint8 or not out.is_contiguous():
+        raise ValueError(f"out must be a contiguous uint8 tensor {shape}")
+    work = torch.empty(max(wb, 16), dtype=torch.uint8, device=coef.device)
+    mjd_decode_variant(ctx, v, coef, qt, out, ncomp * w, work, wb, stream)
     return out
 
 

@@ -16,6 +16,10 @@ LIB_PATH = os.path.join(_PKG, "_lib", "libmjd.so")
 
 MJD_OK = 0
 MJD_POLY_MAX_DEGREE = 7
+MJD_IDCT_ISLOW = 0
+MJD_IDCT_IFAST = 1
+MJD_IDCT_FLOAT = 2
+IDCT = {"islow": MJD_IDCT_ISLOW, "ifast": MJD_IDCT_IFAST, "float": MJD_IDCT_FLOAT}
 MJD_PART_SPS = 0
 MJD_PART_OVERLAP = 1
 MJD_PART_PPS = 2
@@ -109,6 +113,11 @@ class mjd_hetero_times(ctypes.Structure):
 class mjd_hetero_plan(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("cpu_rows", ctypes.c_uint32), ("chunk_mcu_rows", ctypes.c_uint32),
                 ("pad", ctypes.c_uint32), ("model", ctypes.c_void_p), ("huff_threads", ctypes.c_double)]
+
+
+class mjd_variant(ctypes.Structure):
+    _fields_ = [("frame", mjd_frame), ("ncomp", ctypes.c_uint32), ("idct", ctypes.c_int32),
+                ("upsample", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
 
 
 class mjd_pipeline_config(ctypes.Structure):
@@ -212,6 +221,11 @@ def lib() -> ctypes.CDLL:
                                            ctypes.c_double, u32, ctypes.c_double, ctypes.c_double,
                                            ctypes.POINTER(mjd_partition)]
         L.mjd_repartition_rows.restype = i32
+        L.mjd_variant_geometry.argtypes = [ctypes.POINTER(mjd_variant), ctypes.POINTER(mjd_geometry),
+                                           ctypes.POINTER(ctypes.c_uint64)]
+        L.mjd_variant_geometry.restype = i32
+        L.mjd_decode_variant.argtypes = [vp, ctypes.POINTER(mjd_variant), vp, vp, vp, sz, vp, ctypes.c_uint64, vp]
+        L.mjd_decode_variant.restype = i32
         L.mjd_hetero_create.argtypes = [vp, ctypes.c_uint64, ctypes.c_uint64, i32, ctypes.POINTER(vp)]
         L.mjd_hetero_create.restype = i32
         L.mjd_hetero_decode.argtypes = [vp, vp, sz, i32, ctypes.POINTER(mjd_hetero_plan), vp, sz,
@@ -570,6 +584,34 @@ def mjd_repartition_rows(model: mjd_model, width: int, height: int, rows_left: i
                                       int(file_bytes), float(huff_threads), int(huff_rows_left), float(huff_done_s),
                                       float(gpu_busy_s), ctypes.byref(out)))
     return {k: getattr(out, k) for k, _ in mjd_partition._fields_}
+
+
+def make_variant(frame, ncomp: int = 3, idct: str = "islow", mode: str = "fancy") -> mjd_variant:
+    """frame dict (as for make_frame; grayscale may give width, height and
+    qsel only) -> mjd_variant."""
+    f = dict(frame)
+    f.setdefault("h", (1, 1, 1))
+    f.setdefault("v", (1, 1, 1))
+    q = tuple(f.get("qsel", (0, 0, 0))) + (0, 0, 0)
+    f["qsel"] = q[:3]
+    return mjd_variant(frame=make_frame(f), ncomp=int(ncomp), idct=IDCT[idct],
+                       upsample=MJD_UPSAMPLE_FANCY if mode == "fancy" else MJD_UPSAMPLE_SIMPLE)
+
+
+def mjd_variant_geometry(variant: mjd_variant) -> tuple:
+    """-> (geometry dict, workspace bytes)."""
+    g = mjd_geometry()
+    wb = ctypes.c_uint64()
+    _check(lib().mjd_variant_geometry(ctypes.byref(variant), ctypes.byref(g), ctypes.byref(wb)))
+    return ({"mcu_w": g.mcu_w, "mcu_h": g.mcu_h, "mcus_x": g.mcus_x, "mcus_y": g.mcus_y,
+             "blocks_per_mcu": g.blocks_per_mcu, "comp_w": list(g.comp_w), "comp_h": list(g.comp_h),
+             "n_blocks": g.n_blocks}, wb.value)
+
+
+def mjd_decode_variant(ctx: Context, variant: mjd_variant, coef, qt, out, pitch: int, work, work_bytes: int,
+                       stream=None):
+    _check(lib().mjd_decode_variant(ctx.handle, ctypes.byref(variant), _ptr(coef), _ptr(qt), _ptr(out),
+                                    int(pitch), _ptr(work), int(work_bytes), _stream(stream)))
 
 
 class Hetero:

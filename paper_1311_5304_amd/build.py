@@ -14,7 +14,7 @@ LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libmjd.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["api.hip", "decode.hip", "batch.hip", "copy.hip", "server.hip", "entropy.hip"]
+SOURCES = ["api.hip", "decode.hip", "batch.hip", "copy.hip", "server.hip", "entropy.hip", "variants.hip"]
 # host-only C++ (no device code): built with the host compiler
 HOST_SOURCES = ["host_jpeg.cpp", "pipeline.cpp", "model.cpp", "cpu_decode.cpp", "hetero.cpp"]
 
@@ -29,6 +29,9 @@ HIPCC_FLAGS = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 
+
+# the float IDCT variant rounds once per operation (no fused multiply-adds)
+HIPCC_FILE_FLAGS = {"variants.hip": ["-ffp-contract=off"]}
 
 CXX_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", "-Wno-unused-parameter",
              "-I" + os.path.join(ROOT, "include"), "-I" + "/opt/rocm/include", "-D__HIP_PLATFORM_AMD__"]
@@ -64,7 +67,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmds.append([cc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([cc, *HIPCC_FLAGS, *HIPCC_FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".host.o")
         objs.append(obj)

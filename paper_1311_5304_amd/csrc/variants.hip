@@ -1,0 +1,445 @@
+// Decoder variants: the IDCT methods libjpeg offers beside islow (the paper
+// notes AAN-based and integer-or-float IDCTs, Sec. 2 and Sec. 3), the
+// samplings beyond 4:4:4 / 4:2:2 / 4:2:0 (the paper decodes the others the
+// same way, Sec. 4.2) and grayscale.  A generic two-kernel path, not the
+// tuned segment pipeline of the fixed configurations:
+//   var_idct    dequantise + 8x8 IDCT, one block per 8 lanes (column pass,
+//               then row pass, through LDS), into per-component sample
+//               planes in a caller workspace (grayscale: straight into the
+//               output rows);
+//   var_colour  chroma upsampling (simple; triangle filter for factors of 2,
+//               Algorithm 1, vertical for h1v2) + YCbCr->RGB (Algorithm 2),
+//               four pixels per lane.
+// IDCT methods:
+//   islow  LL&M in 13-bit fixed point (the fused kernel's arithmetic);
+//   ifast  the transposed AAN flowgraph in fixed point: multipliers
+//          q * 2^6 / (s(u) s(v)) (s(0) = 1, s(k) = sqrt(2) cos(k pi/16)),
+//          9-bit constants with truncating products, ((v + 2^8) >> 9) + 128;
+//   float  the same flowgraph in IEEE single precision, multipliers
+//          fp32(q / (8 s(u) s(v))), one rounding per operation in a fixed
+//          order (no contraction), floor(v + 128.5).
+#include <math.h>
+
+#include <mutex>
+
+#include "mjd_internal.h"
+
+// The float method rounds once per operation, in the order written: no
+// contraction into fused multiply-adds (the file is also built with
+// -ffp-contract=off).
+#pragma clang fp contract(off)
+
+namespace mjd {
+namespace var {
+
+constexpr int kBlocksPerWG = 32;
+constexpr int kThreads = 8 * kBlocksPerWG;
+constexpr int kIfastFrac = 6;
+constexpr int kIfastConstBits = 9;
+constexpr int kIfastShift = kIfastFrac + 3;
+
+// Scale factors and constants, computed once on the host with the C
+// library's cos and passed by value.
+struct Consts {
+  double ss8[64];   // 8 * (s(u) * s(v)), index 8u + v
+  int32_t a14[64];  // round(2^14 / (s(u) * s(v)))
+  int32_t ki[4];    // round(c * 2^9) of cos(pi/4), cos(3pi/8), cos(pi/8) -+ cos(3pi/8)
+  float kf[4];      // the same constants in fp32
+};
+
+const Consts& consts() {
+  static Consts k;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    double s[8];
+    s[0] = 1.0;
+    for (int i = 1; i < 8; ++i) s[i] = sqrt(2.0) * cos(i * M_PI / 16.0);
+    for (int u = 0; u < 8; ++u)
+      for (int v = 0; v < 8; ++v) {
+        const double p = s[u] * s[v];
+        k.ss8[8 * u + v] = 8.0 * p;
+        k.a14[8 * u + v] = static_cast<int32_t>(llround(16384.0 / p));
+      }
+    const double c[4] = {cos(M_PI / 4.0), cos(3.0 * M_PI / 8.0), cos(M_PI / 8.0) - cos(3.0 * M_PI / 8.0),
+                         cos(M_PI / 8.0) + cos(3.0 * M_PI / 8.0)};
+    for (int i = 0; i < 4; ++i) {
+      k.ki[i] = static_cast<int32_t>(llround(c[i] * (1 << kIfastConstBits)));
+      k.kf[i] = static_cast<float>(c[i]);
+    }
+  });
+  return k;
+}
+
+struct View {
+  const int16_t* coef;
+  const uint16_t* qt;
+  uint8_t* out;
+  uint8_t* work;
+  uint64_t n_blocks;
+  uint64_t plane_off[3];
+  uint32_t plane_pitch[3];
+  uint32_t pitch;
+  int width, height, ncomp, hy, vy, mcus_x, bpm, fancy, aligned_out;
+  int qsel[3];
+  int comp_w, comp_h;  // the chroma components' true size
+};
+
+// --- the transposed AAN flowgraph ------------------------------------------
+// Outputs in sample order from inputs in frequency order; sums left to right.
+struct IfastOps {
+  int r, c5, c2, c4;
+  __device__ int mul_r(int v) const { return (v * r) >> kIfastConstBits; }
+  __device__ int mul_c5(int v) const { return (v * c5) >> kIfastConstBits; }
+  __device__ int mul_c2(int v) const { return (v * c2) >> kIfastConstBits; }
+  __device__ int mul_c4(int v) const { return (v * c4) >> kIfastConstBits; }
+};
+struct FloatOps {
+  float r, c5, c2, c4;
+  __device__ float mul_r(float v) const { return v * r; }
+  __device__ float mul_c5(float v) const { return v * c5; }
+  __device__ float mul_c2(float v) const { return v * c2; }
+  __device__ float mul_c4(float v) const { return v * c4; }
+};
+
+__device__ __forceinline__ int add_(int a, int b) { return a + b; }
+__device__ __forceinline__ int sub_(int a, int b) { return a - b; }
+__device__ __forceinline__ float add_(float a, float b) { return a + b; }
+__device__ __forceinline__ float sub_(float a, float b) { return a - b; }
+
+template <class T, class Ops>
+__device__ __forceinline__ void aan8(const T y[8], T x[8], const Ops& k) {
+  // even part
+  const T t10 = add_(y[0], y[4]);
+  const T t11 = sub_(y[0], y[4]);
+  const T u = k.mul_r(sub_(y[2], y[6]));
+  const T t13 = add_(add_(y[2], y[6]), u);
+  const T e0 = add_(t10, t13), e3 = sub_(t10, t13);
+  const T e1 = add_(t11, u), e2 = sub_(t11, u);
+  // odd part
+  const T z13 = add_(y[5], y[3]);
+  const T z2 = sub_(y[5], y[3]);
+  const T z11 = add_(y[1], y[7]);
+  const T z4 = sub_(y[1], y[7]);
+  const T a11 = k.mul_r(sub_(z11, z13));
+  const T t = k.mul_c5(add_(z2, z4));
+  const T a10 = add_(k.mul_c2(z2), t);
+  const T a12 = sub_(k.mul_c4(z4), t);
+  const T o5 = add_(a10, a11);
+  const T o6 = add_(a11, a12);
+  const T o7 = add_(add_(z11, z13), a12);
+  x[0] = add_(e0, o7);
+  x[1] = add_(e1, o6);
+  x[2] = add_(e2, o5);
+  x[3] = add_(e3, a10);
+  x[4] = sub_(e3, a10);
+  x[5] = sub_(e2, o5);
+  x[6] = sub_(e1, o6);
+  x[7] = sub_(e0, o7);
+}
+
+__device__ __forceinline__ uint32_t clamp_u8(int v) { return static_cast<uint32_t>(min(max(v, 0), 255)); }
+
+// --- kernel 1: dequantise + IDCT -------------------------------------------
+template <int M>
+__global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts k) {
+  __shared__ __align__(16) int16_t cf[kBlocksPerWG * 64];
+  __shared__ __align__(16) int32_t ws[kBlocksPerWG * 64];
+  __shared__ int32_t tab[4 * 64];
+  const int t = static_cast<int>(threadIdx.x);
+  // the four multiplier tables
+  {
+    const int e = t & 63;
+    const uint32_t q = v.qt[t];
+    if constexpr (M == MJD_IDCT_ISLOW) {
+      tab[t] = static_cast<int32_t>(q);
+    } else if constexpr (M == MJD_IDCT_IFAST) {
+      tab[t] = static_cast<int32_t>((static_cast<int64_t>(q) * k.a14[e] + (1 << (13 - kIfastFrac))) >> (14 - kIfastFrac));
+    } else {
+      tab[t] = __float_as_int(static_cast<float>(static_cast<double>(q) / k.ss8[e]));
+    }
+  }
+  const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kBlocksPerWG;
+  {
+    const int blk = t >> 3, ch = t & 7;
+    int4 d = {0, 0, 0, 0};
+    if (b0 + blk < v.n_blocks) d = reinterpret_cast<const int4*>(v.coef + (b0 + blk) * 64)[ch];
+    reinterpret_cast<int4*>(cf)[t] = d;
+  }
+  __syncthreads();
+  const int blk = t >> 3, lane = t & 7;
+  const uint64_t b = b0 + blk;
+  const bool live = b < v.n_blocks;
+  // the block's component and position in that component's block grid
+  int comp = 0, bx, by;
+  {
+    const uint64_t m = live ? b / static_cast<uint64_t>(v.bpm) : 0;
+    const int j = live ? static_cast<int>(b - m * static_cast<uint64_t>(v.bpm)) : 0;
+    const int mx = static_cast<int>(m % static_cast<uint64_t>(v.mcus_x));
+    const int my = static_cast<int>(m / static_cast<uint64_t>(v.mcus_x));
+    const int ny = v.hy * v.vy;
+    if (v.ncomp == 1 || j < ny) {
+      const int jy = j / v.hy, jx = j - jy * v.hy;
+      bx = mx * v.hy + jx;
+      by = my * v.vy + jy;
+    } else {
+      comp = j - ny + 1;
+      bx = mx;
+      by = my;
+    }
+  }
+  const int32_t* q = tab + 64 * v.qsel[comp];
+  const int16_t* c = cf + 64 * blk;
+  int32_t* w = ws + 64 * blk;
+  // column pass: this lane's column `lane`
+  if constexpr (M == MJD_IDCT_ISLOW) {
+    int y[8];
+    idct8_raw(c[lane] * q[lane], c[8 + lane] * q[8 + lane], c[16 + lane] * q[16 + lane],
+              c[24 + lane] * q[24 + lane], c[32 + lane] * q[32 + lane], c[40 + lane] * q[40 + lane],
+              c[48 + lane] * q[48 + lane], c[56 + lane] * q[56 + lane], kPass1Bias, y);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[8 * i + lane] = y[i] >> kPass1Shift;
+  } else if constexpr (M == MJD_IDCT_IFAST) {
+    const IfastOps ops{k.ki[0], k.ki[1], k.ki[2], k.ki[3]};
+    int in[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) in[u] = c[8 * u + lane] * q[8 * u + lane];
+    aan8(in, y, ops);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[8 * i + lane] = y[i];
+  } else {
+    const FloatOps ops{k.kf[0], k.kf[1], k.kf[2], k.kf[3]};
+    float in[8], y[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) in[u] = static_cast<float>(c[8 * u + lane]) * __int_as_float(q[8 * u + lane]);
+    aan8(in, y, ops);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) w[8 * i + lane] = __float_as_int(y[i]);
+  }
+  __syncthreads();
+  // row pass: this lane's row `lane`
+  uint32_t px[8];
+  if constexpr (M == MJD_IDCT_ISLOW) {
+    const int* r = w + 8 * lane;
+    int s[8];
+    idct8_raw(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], kPass2Bias, s);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) px[i] = clamp_u8(s[i] >> kPass2Shift);
+  } else if constexpr (M == MJD_IDCT_IFAST) {
+    const IfastOps ops{k.ki[0], k.ki[1], k.ki[2], k.ki[3]};
+    int in[8], s[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) in[i] = w[8 * lane + i];
+    aan8(in, s, ops);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) px[i] = clamp_u8(((s[i] + (1 << (kIfastShift - 1))) >> kIfastShift) + 128);
+  } else {
+    const FloatOps ops{k.kf[0], k.kf[1], k.kf[2], k.kf[3]};
+    float in[8], s[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) in[i] = __int_as_float(w[8 * lane + i]);
+    aan8(in, s, ops);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) px[i] = clamp_u8(static_cast<int>(floorf(s[i] + 128.5f)));
+  }
+  if (!live) return;
+  const uint32_t lo = px[0] | (px[1] << 8) | (px[2] << 16) | (px[3] << 24);
+  const uint32_t hi = px[4] | (px[5] << 8) | (px[6] << 16) | (px[7] << 24);
+  const int y = by * 8 + lane;
+  if (v.ncomp == 1) {  // grayscale: straight into the output, cropped
+    if (y >= v.height) return;
+    uint8_t* dst = v.out + static_cast<size_t>(y) * v.pitch + bx * 8;
+    const int n = min(8, v.width - bx * 8);
+    if (n == 8 && v.aligned_out) {
+      *reinterpret_cast<uint2*>(dst) = make_uint2(lo, hi);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (i < n) dst[i] = static_cast<uint8_t>(px[i]);
+    }
+    return;
+  }
+  uint8_t* dst = v.work + v.plane_off[comp] + static_cast<size_t>(y) * v.plane_pitch[comp] + bx * 8;
+  *reinterpret_cast<uint2*>(dst) = make_uint2(lo, hi);
+}
+
+// --- kernel 2: upsample + colour -------------------------------------------
+__device__ __forceinline__ int chroma_at(const View& v, const uint8_t* p, uint32_t pp, int x, int y) {
+  const int fh = v.hy, fv = v.vy;
+  if (!v.fancy || fh == 4 || (fh == 1 && fv == 1)) return p[static_cast<size_t>(y / fv) * pp + x / fh];
+  if (fv == 1) {  // h2v1: Algorithm 1
+    const int k = x >> 1, odd = x & 1;
+    const int nk = odd ? min(k + 1, v.comp_w - 1) : max(k - 1, 0);
+    const uint8_t* row = p + static_cast<size_t>(y) * pp;
+    return (3 * row[k] + row[nk] + 1 + odd) >> 2;
+  }
+  const int r = y >> 1, oddr = y & 1;
+  const int nr = oddr ? min(r + 1, v.comp_h - 1) : max(r - 1, 0);
+  const uint8_t* a = p + static_cast<size_t>(r) * pp;
+  const uint8_t* b = p + static_cast<size_t>(nr) * pp;
+  if (fh == 1) return (3 * a[x] + b[x] + 1 + oddr) >> 2;  // h1v2: vertical Algorithm 1
+  // h2v2: unrounded vertical sums, then the horizontal filter on the 16x scale
+  const int k = x >> 1, odd = x & 1;
+  const int nk = odd ? min(k + 1, v.comp_w - 1) : max(k - 1, 0);
+  const int s0 = 3 * a[k] + b[k], s1 = 3 * a[nk] + b[nk];
+  return (3 * s0 + s1 + 8 - odd) >> 4;
+}
+
+__global__ __launch_bounds__(256) void var_colour(const View v) {
+  const int gpr = (v.width + 3) >> 2;
+  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (g >= static_cast<uint64_t>(gpr) * static_cast<uint64_t>(v.height)) return;
+  const int y = static_cast<int>(g / static_cast<uint64_t>(gpr));
+  const int x0 = static_cast<int>(g - static_cast<uint64_t>(y) * gpr) * 4;
+  const uint8_t* py = v.work + v.plane_off[0] + static_cast<size_t>(y) * v.plane_pitch[0];
+  const uint8_t* pb = v.work + v.plane_off[1];
+  const uint8_t* pr = v.work + v.plane_off[2];
+  uint32_t b[12];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int x = min(x0 + i, v.width - 1);
+    const int y16 = (static_cast<int>(py[x]) << 16) + 32768;
+    const int xb = chroma_at(v, pb, v.plane_pitch[1], x, y) - 128;
+    const int xr = chroma_at(v, pr, v.plane_pitch[2], x, y) - 128;
+    b[3 * i] = clamp_u8((y16 + kCrR * xr) >> 16);
+    b[3 * i + 1] = clamp_u8((y16 - kCbG * xb - kCrG * xr) >> 16);
+    b[3 * i + 2] = clamp_u8((y16 + kCbB * xb) >> 16);
+  }
+  uint8_t* dst = v.out + static_cast<size_t>(y) * v.pitch + 3 * x0;
+  const int n = min(4, v.width - x0);
+  if (n == 4 && v.aligned_out) {
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    d[0] = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+    d[1] = b[4] | (b[5] << 8) | (b[6] << 16) | (b[7] << 24);
+    d[2] = b[8] | (b[9] << 8) | (b[10] << 16) | (b[11] << 24);
+  } else {
+    for (int i = 0; i < 3 * n; ++i) dst[i] = static_cast<uint8_t>(b[i]);
+  }
+}
+
+}  // namespace var
+
+// Geometry of a variant frame and the workspace its planes need.
+static int variant_geometry(const mjd_variant* vr, mjd_geometry* g, uint64_t* work, uint32_t plane_pitch[3],
+                            uint64_t plane_off[3]) {
+  if (!vr || !g) return fail(MJD_EINVAL, "null variant or geometry pointer");
+  const mjd_frame& f = vr->frame;
+  if (vr->reserved != 0 || f.reserved != 0) return fail(MJD_EINVAL, "reserved fields must be 0");
+  if (f.width < 1 || f.width > 65535 || f.height < 1 || f.height > 65535)
+    return fail(MJD_EINVAL, "image size %ux%u outside 1..65535", f.width, f.height);
+  if (vr->ncomp != 1 && vr->ncomp != 3) return fail(MJD_EINVAL, "ncomp %u is neither 1 nor 3", vr->ncomp);
+  if (vr->idct != MJD_IDCT_ISLOW && vr->idct != MJD_IDCT_IFAST && vr->idct != MJD_IDCT_FLOAT)
+    return fail(MJD_EINVAL, "IDCT method %d unknown", vr->idct);
+  if (vr->upsample != MJD_UPSAMPLE_SIMPLE && vr->upsample != MJD_UPSAMPLE_FANCY)
+    return fail(MJD_EINVAL, "upsample mode %d unknown", vr->upsample);
+  const int nc = static_cast<int>(vr->ncomp);
+  for (int c = 0; c < nc; ++c)
+    if (f.qsel[c] > 3) return fail(MJD_EINVAL, "component %d quant table selector %u > 3", c, f.qsel[c]);
+  uint32_t hy = 1, vy = 1;
+  if (nc == 3) {
+    hy = f.h[0];
+    vy = f.v[0];
+    const bool luma_ok = (hy == 1 && vy == 1) || (hy == 2 && vy == 1) || (hy == 1 && vy == 2) ||
+                         (hy == 2 && vy == 2) || (hy == 4 && vy == 1);
+    if (!luma_ok || f.h[1] != 1 || f.v[1] != 1 || f.h[2] != 1 || f.v[2] != 1)
+      return fail(MJD_EUNSUPPORTED, "sampling Y(%u,%u) Cb(%u,%u) Cr(%u,%u) not supported", f.h[0], f.v[0], f.h[1],
+                  f.v[1], f.h[2], f.v[2]);
+  }
+  g->mcu_w = 8 * hy;
+  g->mcu_h = 8 * vy;
+  g->mcus_x = (f.width + g->mcu_w - 1) / g->mcu_w;
+  g->mcus_y = (f.height + g->mcu_h - 1) / g->mcu_h;
+  g->blocks_per_mcu = nc == 1 ? 1 : hy * vy + 2;
+  g->n_blocks = static_cast<uint64_t>(g->mcus_x) * g->mcus_y * g->blocks_per_mcu;
+  uint64_t total = 0;
+  for (int c = 0; c < 3; ++c) {
+    const uint32_t hc = c == 0 ? hy : 1, vc = c == 0 ? vy : 1;
+    g->comp_w[c] = c < nc ? (f.width * hc + hy - 1) / hy : 0;
+    g->comp_h[c] = c < nc ? (f.height * vc + vy - 1) / vy : 0;
+    plane_pitch[c] = g->mcus_x * hc * 8;
+    plane_off[c] = total;
+    if (nc == 3) total += (static_cast<uint64_t>(plane_pitch[c]) * g->mcus_y * vc * 8 + 255) & ~255ull;
+  }
+  *work = total;
+  return MJD_OK;
+}
+
+}  // namespace mjd
+
+extern "C" {
+
+int mjd_variant_geometry(const mjd_variant* variant, mjd_geometry* out, uint64_t* work_bytes) {
+  uint32_t pp[3];
+  uint64_t po[3], wb = 0;
+  mjd_geometry g;
+  const int rc = mjd::variant_geometry(variant, &g, &wb, pp, po);
+  if (rc != MJD_OK) return rc;
+  if (out) *out = g;
+  if (work_bytes) *work_bytes = wb;
+  return MJD_OK;
+}
+
+int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* d_coef, const uint16_t* d_qt,
+                       uint8_t* d_out, size_t pitch, void* d_work, uint64_t work_bytes, void* stream) {
+  using namespace mjd;
+  if (!ctx) return fail(MJD_EINVAL, "null context");
+  mjd_geometry g;
+  var::View v{};
+  uint64_t need = 0;
+  int rc = variant_geometry(variant, &g, &need, v.plane_pitch, v.plane_off);
+  if (rc != MJD_OK) return rc;
+  if (!d_coef || !d_qt || !d_out) return fail(MJD_EINVAL, "null device buffer");
+  if (reinterpret_cast<uintptr_t>(d_coef) % 16) return fail(MJD_EINVAL, "coefficient buffer not 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(d_qt) % 2) return fail(MJD_EINVAL, "quant table buffer not 2-byte aligned");
+  const int nc = static_cast<int>(variant->ncomp);
+  const uint64_t row_bytes = static_cast<uint64_t>(nc) * variant->frame.width;
+  if (pitch < row_bytes) return fail(MJD_EINVAL, "pitch %zu < %u*width", pitch, nc);
+  if (pitch >= (1ull << 31)) return fail(MJD_EINVAL, "pitch %zu not below 2^31 bytes", pitch);
+  if (nc == 3) {
+    if (!d_work) return fail(MJD_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(d_work) % 16) return fail(MJD_EINVAL, "workspace not 16-byte aligned");
+    if (work_bytes < need) return fail(MJD_EINVAL, "workspace of %llu bytes below the %llu needed",
+                                       static_cast<unsigned long long>(work_bytes), static_cast<unsigned long long>(need));
+  }
+  v.coef = d_coef;
+  v.qt = d_qt;
+  v.out = d_out;
+  v.work = static_cast<uint8_t*>(d_work);
+  v.n_blocks = g.n_blocks;
+  v.pitch = static_cast<uint32_t>(pitch);
+  v.width = static_cast<int>(variant->frame.width);
+  v.height = static_cast<int>(variant->frame.height);
+  v.ncomp = nc;
+  v.hy = nc == 3 ? variant->frame.h[0] : 1;
+  v.vy = nc == 3 ? variant->frame.v[0] : 1;
+  v.mcus_x = static_cast<int>(g.mcus_x);
+  v.bpm = static_cast<int>(g.blocks_per_mcu);
+  v.fancy = variant->upsample == MJD_UPSAMPLE_FANCY ? 1 : 0;
+  const size_t align = nc == 1 ? 8 : 4;
+  v.aligned_out = (reinterpret_cast<uintptr_t>(d_out) % align == 0 && pitch % align == 0) ? 1 : 0;
+  for (int c = 0; c < 3; ++c) v.qsel[c] = c < nc ? variant->frame.qsel[c] : 0;
+  v.comp_w = static_cast<int>(g.comp_w[1]);
+  v.comp_h = static_cast<int>(g.comp_h[1]);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+  }
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const var::Consts& k = var::consts();
+  const unsigned grid1 = static_cast<unsigned>((g.n_blocks + var::kBlocksPerWG - 1) / var::kBlocksPerWG);
+  switch (variant->idct) {
+    case MJD_IDCT_ISLOW: hipLaunchKernelGGL(var::var_idct<MJD_IDCT_ISLOW>, dim3(grid1), dim3(var::kThreads), 0, s, v, k); break;
+    case MJD_IDCT_IFAST: hipLaunchKernelGGL(var::var_idct<MJD_IDCT_IFAST>, dim3(grid1), dim3(var::kThreads), 0, s, v, k); break;
+    default: hipLaunchKernelGGL(var::var_idct<MJD_IDCT_FLOAT>, dim3(grid1), dim3(var::kThreads), 0, s, v, k); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && nc == 3) {
+    const uint64_t groups = static_cast<uint64_t>((v.width + 3) / 4) * v.height;
+    hipLaunchKernelGGL(var::var_colour, dim3(static_cast<unsigned>((groups + 255) / 256)), dim3(256), 0, s, v);
+    e = hipGetLastError();
+  }
+  if (cur != ctx->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return fail(MJD_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return MJD_OK;
+}
+
+}  // extern "C"

@@ -74,7 +74,7 @@ def test_tuning_rejects_null_context():
 STRUCTS = [B.mjd_frame, B.mjd_geometry, B.mjd_tuning, B.mjd_job, B.mjd_huffman, B.mjd_scan,
            B.mjd_pipeline_config, B.mjd_pipeline_stats, B.mjd_server_config, B.mjd_request,
            B.mjd_request_times, B.mjd_entropy_job, B.mjd_poly1, B.mjd_poly2, B.mjd_model, B.mjd_prediction, B.mjd_partition, B.mjd_hetero_times,
-           B.mjd_hetero_plan]
+           B.mjd_hetero_plan, B.mjd_variant]
 
 
 def test_frame_struct_layout():

@@ -1,0 +1,148 @@
+"""GPU parity of the decoder variants (mjd_decode_variant) against the
+variant oracle, byte for byte: every IDCT method (islow, ifast, float) on
+every sampling ((1,1), (2,1), (1,2), (2,2), (4,1)) in both upsampling modes,
+and grayscale; ragged sizes spanning several workgroups, a 1x1 image,
+extreme coefficients of the whole input domain, padded and misaligned
+output rows, and a 4096x3072 image per method.  islow through the variants
+path also equals mjd_decode on the samplings both serve."""
+import numpy as np
+import pytest
+
+import oracle.variants as V
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+SAMPLINGS = [(1, 1), (2, 1), (1, 2), (2, 2), (4, 1)]
+SIZES = [(257, 190), (33, 47), (1, 1)]
+
+
+def say(msg):
+    print(f"[gpu-variants] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1311_5304_amd as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def _case(seed, frame):
+    """Quant tables 1..16 and coefficients on the domain |c * q| <= 1155:
+    mostly decaying blocks, a tenth of them at the domain's extremes."""
+    rng = np.random.default_rng(seed)
+    qt = rng.integers(1, 17, (4, 64)).astype(np.uint16)
+    n = V.variant_geometry(frame)["n_blocks"]
+    lim = (1155 // qt.max(axis=0)).astype(np.int64)  # per position, safe for every table
+    c = (rng.standard_normal((n, 64)) * lim / (1 + np.arange(64) / 6)).astype(np.int64)
+    c[:, 0] = rng.integers(-lim[0], lim[0] + 1, n)
+    ext = rng.random(n) < 0.1
+    c[ext] = rng.choice([-1, 1], (int(ext.sum()), 64)) * lim
+    return np.clip(c, -lim, lim).astype(np.int16), qt
+
+
+def _run(M, ctx, frame, coef, qt, method, mode, ncomp=3):
+    cd = torch.from_numpy(coef.reshape(-1)).cuda()
+    qd = torch.from_numpy(qt.view(np.int16).reshape(-1)).cuda()
+    out = M.decode_variant(ctx, frame, cd, qd, method, mode, ncomp)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("method", V.IDCT_METHODS)
+def test_every_sampling_and_mode_matches_oracle(M, ctx, method):
+    for i, (hy, vy) in enumerate(SAMPLINGS):
+        for w, h in SIZES:
+            fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 2)}
+            coef, qt = _case(1000 * i + w, fr)
+            for mode in ("simple", "fancy"):
+                say(f"{method} {hy}x{vy} {w}x{h} {mode}")
+                got = _run(M, ctx, fr, coef, qt, method, mode)
+                exp = V.decode_variant(fr, coef, qt, method, mode)
+                assert np.array_equal(got, exp), (method, hy, vy, w, h, mode, int((got != exp).sum()))
+
+
+@pytest.mark.parametrize("method", V.IDCT_METHODS)
+def test_grayscale_matches_oracle(M, ctx, method):
+    for w, h in SIZES + [(640, 480)]:
+        fr = {"width": w, "height": h, "ncomp": 1, "h": (1, 1, 1), "v": (1, 1, 1), "qsel": (3, 0, 0)}
+        coef, qt = _case(77 + w, fr)
+        say(f"{method} grayscale {w}x{h}")
+        got = _run(M, ctx, fr, coef, qt, method, "fancy", ncomp=1)
+        assert got.shape == (h, w)
+        assert np.array_equal(got, V.decode_variant(fr, coef, qt, method)), (method, w, h)
+
+
+def test_islow_variant_equals_the_fused_kernel(M, ctx):
+    for hy, vy in ((1, 1), (2, 1), (2, 2)):
+        fr = {"width": 333, "height": 97, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 1)}
+        coef, qt = _case(5 + hy + vy, fr)
+        for mode in ("simple", "fancy"):
+            say(f"islow vs fused {hy}x{vy} {mode}")
+            cd = torch.from_numpy(coef.reshape(-1)).cuda()
+            qd = torch.from_numpy(qt.view(np.int16).reshape(-1)).cuda()
+            a = M.decode_variant(ctx, fr, cd, qd, "islow", mode)
+            b = M.decode(ctx, fr, cd, qd, mode)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b)
+
+
+def test_padded_and_misaligned_rows(M, ctx):
+    # rows of pitch 3w + 5 starting one byte past an aligned address: the
+    # bytes between rows and around the image stay untouched
+    for ncomp, (hy, vy) in ((3, (2, 2)), (3, (4, 1)), (1, (1, 1))):
+        w, h = 61, 35
+        fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 1), "ncomp": ncomp}
+        coef, qt = _case(31 + hy, fr)
+        v = M.make_variant(fr, ncomp, "float", "fancy")
+        g, wb = M.mjd_variant_geometry(v)
+        pitch = ncomp * w + 5
+        buf = torch.full((h * pitch + 64,), 0xA5, dtype=torch.uint8, device="cuda")
+        work = torch.empty(max(wb, 16), dtype=torch.uint8, device="cuda")
+        cd = torch.from_numpy(coef.reshape(-1)).cuda()
+        qd = torch.from_numpy(qt.view(np.int16).reshape(-1)).cuda()
+        say(f"misaligned ncomp={ncomp} {hy}x{vy}")
+        M.mjd_decode_variant(ctx, v, cd, qd, buf.data_ptr() + 1, pitch, work, wb)
+        torch.cuda.synchronize()
+        b = buf.cpu().numpy()
+        rows = b[1:1 + h * pitch].reshape(h, pitch)
+        exp = V.decode_variant(fr, coef, qt, "float", "fancy")
+        assert np.array_equal(rows[:, :ncomp * w].reshape(exp.shape), exp)
+        assert np.all(rows[:, ncomp * w:] == 0xA5) and b[0] == 0xA5 and np.all(b[1 + h * pitch:] == 0xA5)
+
+
+def test_bad_calls_are_refused(M, ctx):
+    fr = {"width": 64, "height": 64, "h": (2, 1, 1), "v": (2, 1, 1), "qsel": (0, 1, 1)}
+    v = M.make_variant(fr, 3, "ifast")
+    g, wb = M.mjd_variant_geometry(v)
+    cd = torch.zeros(g["n_blocks"] * 64, dtype=torch.int16, device="cuda")
+    qd = torch.ones(256, dtype=torch.int16, device="cuda")
+    out = torch.empty((64, 64, 3), dtype=torch.uint8, device="cuda")
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    for args in ((cd, qd, out, 192, work, wb - 1),      # workspace too small
+                 (cd, qd, out, 191, work, wb),          # pitch below 3 * width
+                 (cd, qd, out, 192, 0, wb),             # no workspace
+                 (cd.data_ptr() + 2, qd, out, 192, work, wb)):  # misaligned coefficients
+        with pytest.raises(M.MjdError):
+            M.mjd_decode_variant(ctx, v, *args)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("method", V.IDCT_METHODS)
+def test_full_size_image(M, ctx, method):
+    from synth import workloads
+    frame, coef, qt = workloads.large_420_fancy()
+    say(f"{method} 4096x3072 4:2:0 fancy")
+    got = _run(M, ctx, frame, coef, qt, method, "fancy")
+    exp = V.decode_variant(frame, coef, qt, method, "fancy")
+    assert np.array_equal(got, exp), int((got != exp).sum())
