@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--gpu-entropy-reps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--no-model", action="store_true", help="skip fitting and checking the performance model")
+    ap.add_argument("--no-variants", action="store_true", help="skip the decoder-variant measurements")
     ap.add_argument("--serve-requests", type=int, default=2200, help="requests per trace (the first 200 warm up)")
     return ap.parse_args()
 
@@ -415,6 +416,69 @@ def partition_experiment(M, model, hetero, n_threads, bitstream, workloads):
     return out
 
 
+def variants_workload(args, M, ctx, dev):
+    """The decoder variants at 4096x3072 (generic two-launch path): the three
+    IDCT methods on the headline 4:2:0 fancy coefficients, and islow on h1v2,
+    4:1:1 and grayscale coefficient sets (seeded decaying random blocks on the
+    documented domain).  Four buffer sets rotate so the working set exceeds
+    the 256 MB Infinity Cache.  Algorithmic bytes are the coefficients read
+    and the output written; the planes between the launches are extra."""
+    import torch
+
+    from synth import workloads
+
+    log("decoder variants")
+    stream = torch.cuda.current_stream()
+    frame, coef, qt = workloads.large_420_fancy()
+    W, H = frame["width"], frame["height"]
+    rng = np.random.default_rng(workloads.seed_of(10, 0))
+
+    def synthetic(fr):
+        n = M.mjd_variant_geometry(M.make_variant(fr, fr.get("ncomp", 3)))[0]["n_blocks"]
+        lim = (1155 // qt.max(axis=0)).astype(np.int64)
+        c = (rng.standard_normal((n, 64)) * lim / (4 + np.arange(64))).astype(np.int64)
+        c[:, 0] = rng.integers(-lim[0] // 2, lim[0] // 2 + 1, n)
+        return np.clip(c, -lim, lim).astype(np.int16)
+
+    cases = [("420_fancy_" + m, frame, coef, m, "fancy", 3) for m in ("islow", "ifast", "float")]
+    for name, hv in (("h1v2_fancy_islow", ((1, 1, 1), (2, 1, 1))), ("411_fancy_islow", ((4, 1, 1), (1, 1, 1)))):
+        fr = {"width": W, "height": H, "h": hv[0], "v": hv[1], "qsel": (0, 1, 1)}
+        cases.append((name, fr, synthetic(fr), "islow", "fancy", 3))
+    gray = {"width": W, "height": H, "h": (1, 1, 1), "v": (1, 1, 1), "qsel": (0, 0, 0), "ncomp": 1}
+    cases.append(("gray_islow", gray, synthetic(gray), "islow", "fancy", 1))
+    q_dev = torch.from_numpy(qt.view(np.int16)).to(dev)
+    out = {}
+    for name, fr, c, method, mode, nc in cases:
+        v = M.make_variant(fr, nc, method, mode)
+        g, wb = M.mjd_variant_geometry(v)
+        sets = [(torch.from_numpy(c.reshape(-1)).to(dev),
+                 torch.empty((H, W, 3) if nc == 3 else (H, W), dtype=torch.uint8, device=dev),
+                 torch.empty(max(wb, 16), dtype=torch.uint8, device=dev)) for _ in range(4)]
+
+        def call(k):
+            cd, o, wk = sets[k % 4]
+            M.mjd_decode_variant(ctx, v, cd, q_dev, o, nc * W, wk, wb, stream)
+        for k in range(8):
+            call(k)
+        torch.cuda.synchronize()
+        reps = 40
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for k in range(reps):
+            call(k)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        algo = c.nbytes + nc * W * H
+        out[name] = {"us": round(ms * 1e3, 2), "MPix_s": round(W * H / (ms * 1e-3) / 1e6, 1),
+                     "algorithmic_GB_s": round(algo / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "plane_bytes": wb}
+        del sets
+        torch.cuda.empty_cache()
+    return out
+
+
 def gpu_entropy_workload(args, M, ctx, dev, jpgs, frames, sample_idx, sample):
     """The same corpus decoded on the device end to end: the bitstreams
     resident in HBM, Huffman decoding by the entropy kernel (one lane per
@@ -728,6 +792,8 @@ def main():
         torch.cuda.empty_cache()
         extras["batch"] = batch_workload(args, M, ctx, dev, stream)
         torch.cuda.empty_cache()
+    if not args.no_variants:
+        extras["variants"] = variants_workload(args, M, ctx, dev)
     if not args.no_pipeline:
         extras["pipeline"] = pipeline_workload(args, M, ctx, dev)
     model = None

@@ -9,7 +9,7 @@
 //               output rows);
 //   var_colour  chroma upsampling (simple; triangle filter for factors of 2,
 //               Algorithm 1, vertical for h1v2) + YCbCr->RGB (Algorithm 2),
-//               four pixels per lane.
+//               eight pixels per lane.
 // IDCT methods:
 //   islow  LL&M in 13-bit fixed point (the fused kernel's arithmetic);
 //   ifast  the transposed AAN flowgraph in fixed point: multipliers
@@ -263,54 +263,118 @@ __global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts 
 }
 
 // --- kernel 2: upsample + colour -------------------------------------------
-__device__ __forceinline__ int chroma_at(const View& v, const uint8_t* p, uint32_t pp, int x, int y) {
+// Eight output pixels per lane: luma as one 8-byte load; chroma as the
+// samples the eight pixels read, from aligned loads plus the two clamped
+// neighbours of a triangle filter's window.
+__device__ __forceinline__ int byte_of(uint32_t w, int i) { return static_cast<int>((w >> (8 * i)) & 0xFFu); }
+
+// Chroma row window for a factor-2 filter: s[0..3] the samples k0..k0+3,
+// l / r the clamped neighbours k0-1 and k0+4.
+struct Win {
+  int s[4], l, r;
+};
+__device__ __forceinline__ Win load_win(const uint8_t* row, int k0, int cw) {
+  Win w;
+  const uint32_t d = *reinterpret_cast<const uint32_t*>(row + k0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w.s[i] = byte_of(d, i);
+  w.l = row[max(k0 - 1, 0)];
+  w.r = row[min(k0 + 4, cw - 1)];
+  return w;
+}
+
+// The eight chroma values of pixels x0..x0+7 of row y.
+__device__ __forceinline__ void chroma8(const View& v, const uint8_t* p, uint32_t pp, int x0, int y, int c[8]) {
   const int fh = v.hy, fv = v.vy;
-  if (!v.fancy || fh == 4 || (fh == 1 && fv == 1)) return p[static_cast<size_t>(y / fv) * pp + x / fh];
-  if (fv == 1) {  // h2v1: Algorithm 1
-    const int k = x >> 1, odd = x & 1;
-    const int nk = odd ? min(k + 1, v.comp_w - 1) : max(k - 1, 0);
-    const uint8_t* row = p + static_cast<size_t>(y) * pp;
-    return (3 * row[k] + row[nk] + 1 + odd) >> 2;
+  if (!v.fancy || fh == 4 || (fh == 1 && fv == 1)) {
+    const uint8_t* row = p + static_cast<size_t>(y / fv) * pp;
+    if (fh == 1) {
+      const uint2 d = *reinterpret_cast<const uint2*>(row + x0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        c[i] = byte_of(d.x, i);
+        c[4 + i] = byte_of(d.y, i);
+      }
+    } else if (fh == 2) {
+      const uint32_t d = *reinterpret_cast<const uint32_t*>(row + (x0 >> 1));
+#pragma unroll
+      for (int i = 0; i < 8; ++i) c[i] = byte_of(d, i >> 1);
+    } else {
+      const int a = row[x0 >> 2], b = row[(x0 >> 2) + 1];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) c[i] = i < 4 ? a : b;
+    }
+    return;
   }
-  const int r = y >> 1, oddr = y & 1;
-  const int nr = oddr ? min(r + 1, v.comp_h - 1) : max(r - 1, 0);
-  const uint8_t* a = p + static_cast<size_t>(r) * pp;
-  const uint8_t* b = p + static_cast<size_t>(nr) * pp;
-  if (fh == 1) return (3 * a[x] + b[x] + 1 + oddr) >> 2;  // h1v2: vertical Algorithm 1
-  // h2v2: unrounded vertical sums, then the horizontal filter on the 16x scale
-  const int k = x >> 1, odd = x & 1;
-  const int nk = odd ? min(k + 1, v.comp_w - 1) : max(k - 1, 0);
-  const int s0 = 3 * a[k] + b[k], s1 = 3 * a[nk] + b[nk];
-  return (3 * s0 + s1 + 8 - odd) >> 4;
+  if (fh == 1) {  // h1v2: Algorithm 1 turned vertical
+    const int r = y >> 1, odd = y & 1;
+    const int nr = odd ? min(r + 1, v.comp_h - 1) : max(r - 1, 0);
+    const uint2 a = *reinterpret_cast<const uint2*>(p + static_cast<size_t>(r) * pp + x0);
+    const uint2 b = *reinterpret_cast<const uint2*>(p + static_cast<size_t>(nr) * pp + x0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      c[i] = (3 * byte_of(a.x, i) + byte_of(b.x, i) + 1 + odd) >> 2;
+      c[4 + i] = (3 * byte_of(a.y, i) + byte_of(b.y, i) + 1 + odd) >> 2;
+    }
+    return;
+  }
+  const int k0 = x0 >> 1, cw = v.comp_w;
+  int s[4], l, rr;
+  int sh = 2, bias_even = 1, bias_odd = 2;
+  if (fv == 1) {  // h2v1: Algorithm 1
+    const Win w = load_win(p + static_cast<size_t>(y) * pp, k0, cw);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = w.s[i];
+    l = w.l;
+    rr = w.r;
+  } else {  // h2v2: unrounded vertical sums, then the horizontal filter on the 16x scale
+    const int r = y >> 1, odd = y & 1;
+    const int nr = odd ? min(r + 1, v.comp_h - 1) : max(r - 1, 0);
+    const Win a = load_win(p + static_cast<size_t>(r) * pp, k0, cw);
+    const Win b = load_win(p + static_cast<size_t>(nr) * pp, k0, cw);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[i] = 3 * a.s[i] + b.s[i];
+    l = 3 * a.l + b.l;
+    rr = 3 * a.r + b.r;
+    sh = 4;
+    bias_even = 8;
+    bias_odd = 7;
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = k0 + j;
+    const int left = k - 1 < 0 ? s[j] : (j == 0 ? l : s[j - 1]);
+    const int right = k + 1 > cw - 1 ? s[j] : (j == 3 ? rr : s[j + 1]);
+    c[2 * j] = (3 * s[j] + left + bias_even) >> sh;
+    c[2 * j + 1] = (3 * s[j] + right + bias_odd) >> sh;
+  }
 }
 
 __global__ __launch_bounds__(256) void var_colour(const View v) {
-  const int gpr = (v.width + 3) >> 2;
+  const int gpr = (v.width + 7) >> 3;
   const uint64_t g = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (g >= static_cast<uint64_t>(gpr) * static_cast<uint64_t>(v.height)) return;
   const int y = static_cast<int>(g / static_cast<uint64_t>(gpr));
-  const int x0 = static_cast<int>(g - static_cast<uint64_t>(y) * gpr) * 4;
-  const uint8_t* py = v.work + v.plane_off[0] + static_cast<size_t>(y) * v.plane_pitch[0];
-  const uint8_t* pb = v.work + v.plane_off[1];
-  const uint8_t* pr = v.work + v.plane_off[2];
-  uint32_t b[12];
+  const int x0 = static_cast<int>(g - static_cast<uint64_t>(y) * gpr) * 8;
+  const uint2 yd = *reinterpret_cast<const uint2*>(v.work + v.plane_off[0] + static_cast<size_t>(y) * v.plane_pitch[0] + x0);
+  int cb[8], cr[8];
+  chroma8(v, v.work + v.plane_off[1], v.plane_pitch[1], x0, y, cb);
+  chroma8(v, v.work + v.plane_off[2], v.plane_pitch[2], x0, y, cr);
+  uint32_t b[24];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int x = min(x0 + i, v.width - 1);
-    const int y16 = (static_cast<int>(py[x]) << 16) + 32768;
-    const int xb = chroma_at(v, pb, v.plane_pitch[1], x, y) - 128;
-    const int xr = chroma_at(v, pr, v.plane_pitch[2], x, y) - 128;
+  for (int i = 0; i < 8; ++i) {
+    const int y16 = (byte_of(i < 4 ? yd.x : yd.y, i & 3) << 16) + 32768;
+    const int xb = cb[i] - 128, xr = cr[i] - 128;
     b[3 * i] = clamp_u8((y16 + kCrR * xr) >> 16);
     b[3 * i + 1] = clamp_u8((y16 - kCbG * xb - kCrG * xr) >> 16);
     b[3 * i + 2] = clamp_u8((y16 + kCbB * xb) >> 16);
   }
   uint8_t* dst = v.out + static_cast<size_t>(y) * v.pitch + 3 * x0;
-  const int n = min(4, v.width - x0);
-  if (n == 4 && v.aligned_out) {
+  const int n = min(8, v.width - x0);
+  if (n == 8 && v.aligned_out) {
     uint32_t* d = reinterpret_cast<uint32_t*>(dst);
-    d[0] = b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
-    d[1] = b[4] | (b[5] << 8) | (b[6] << 16) | (b[7] << 24);
-    d[2] = b[8] | (b[9] << 8) | (b[10] << 16) | (b[11] << 24);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) d[i] = b[4 * i] | (b[4 * i + 1] << 8) | (b[4 * i + 2] << 16) | (b[4 * i + 3] << 24);
   } else {
     for (int i = 0; i < 3 * n; ++i) dst[i] = static_cast<uint8_t>(b[i]);
   }
@@ -433,7 +497,7 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && nc == 3) {
-    const uint64_t groups = static_cast<uint64_t>((v.width + 3) / 4) * v.height;
+    const uint64_t groups = static_cast<uint64_t>((v.width + 7) / 8) * v.height;
     hipLaunchKernelGGL(var::var_colour, dim3(static_cast<unsigned>((groups + 255) / 256)), dim3(256), 0, s, v);
     e = hipGetLastError();
   }
