@@ -140,112 +140,13 @@ __device__ __forceinline__ void aan8(const T y[8], T x[8], const Ops& k) {
 __device__ __forceinline__ uint32_t clamp_u8(int v) { return static_cast<uint32_t>(min(max(v, 0), 255)); }
 
 // --- kernel 1: dequantise + IDCT -------------------------------------------
-template <int M>
-__global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts k) {
-  __shared__ __align__(16) int16_t cf[kBlocksPerWG * 64];
-  __shared__ __align__(16) int32_t ws[kBlocksPerWG * 64];
-  __shared__ int32_t tab[4 * 64];
-  const int t = static_cast<int>(threadIdx.x);
-  // the four multiplier tables
-  {
-    const int e = t & 63;
-    const uint32_t q = v.qt[t];
-    if constexpr (M == MJD_IDCT_ISLOW) {
-      tab[t] = static_cast<int32_t>(q);
-    } else if constexpr (M == MJD_IDCT_IFAST) {
-      tab[t] = static_cast<int32_t>((static_cast<int64_t>(q) * k.a14[e] + (1 << (13 - kIfastFrac))) >> (14 - kIfastFrac));
-    } else {
-      tab[t] = __float_as_int(static_cast<float>(static_cast<double>(q) / k.ss8[e]));
-    }
-  }
-  const uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * kBlocksPerWG;
-  {
-    const int blk = t >> 3, ch = t & 7;
-    int4 d = {0, 0, 0, 0};
-    if (b0 + blk < v.n_blocks) d = reinterpret_cast<const int4*>(v.coef + (b0 + blk) * 64)[ch];
-    reinterpret_cast<int4*>(cf)[t] = d;
-  }
-  __syncthreads();
-  const int blk = t >> 3, lane = t & 7;
-  const uint64_t b = b0 + blk;
-  const bool live = b < v.n_blocks;
-  // the block's component and position in that component's block grid
-  int comp = 0, bx, by;
-  {
-    const uint64_t m = live ? b / static_cast<uint64_t>(v.bpm) : 0;
-    const int j = live ? static_cast<int>(b - m * static_cast<uint64_t>(v.bpm)) : 0;
-    const int mx = static_cast<int>(m % static_cast<uint64_t>(v.mcus_x));
-    const int my = static_cast<int>(m / static_cast<uint64_t>(v.mcus_x));
-    const int ny = v.hy * v.vy;
-    if (v.ncomp == 1 || j < ny) {
-      const int jy = j / v.hy, jx = j - jy * v.hy;
-      bx = mx * v.hy + jx;
-      by = my * v.vy + jy;
-    } else {
-      comp = j - ny + 1;
-      bx = mx;
-      by = my;
-    }
-  }
-  const int32_t* q = tab + 64 * v.qsel[comp];
-  const int16_t* c = cf + 64 * blk;
-  int32_t* w = ws + 64 * blk;
-  // column pass: this lane's column `lane`
-  if constexpr (M == MJD_IDCT_ISLOW) {
-    int y[8];
-    idct8_raw(c[lane] * q[lane], c[8 + lane] * q[8 + lane], c[16 + lane] * q[16 + lane],
-              c[24 + lane] * q[24 + lane], c[32 + lane] * q[32 + lane], c[40 + lane] * q[40 + lane],
-              c[48 + lane] * q[48 + lane], c[56 + lane] * q[56 + lane], kPass1Bias, y);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) w[8 * i + lane] = y[i] >> kPass1Shift;
-  } else if constexpr (M == MJD_IDCT_IFAST) {
-    const IfastOps ops{k.ki[0], k.ki[1], k.ki[2], k.ki[3]};
-    int in[8], y[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) in[u] = c[8 * u + lane] * q[8 * u + lane];
-    aan8(in, y, ops);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) w[8 * i + lane] = y[i];
-  } else {
-    const FloatOps ops{k.kf[0], k.kf[1], k.kf[2], k.kf[3]};
-    float in[8], y[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) in[u] = static_cast<float>(c[8 * u + lane]) * __int_as_float(q[8 * u + lane]);
-    aan8(in, y, ops);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) w[8 * i + lane] = __float_as_int(y[i]);
-  }
-  __syncthreads();
-  // row pass: this lane's row `lane`
-  uint32_t px[8];
-  if constexpr (M == MJD_IDCT_ISLOW) {
-    const int* r = w + 8 * lane;
-    int s[8];
-    idct8_raw(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], kPass2Bias, s);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) px[i] = clamp_u8(s[i] >> kPass2Shift);
-  } else if constexpr (M == MJD_IDCT_IFAST) {
-    const IfastOps ops{k.ki[0], k.ki[1], k.ki[2], k.ki[3]};
-    int in[8], s[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) in[i] = w[8 * lane + i];
-    aan8(in, s, ops);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) px[i] = clamp_u8(((s[i] + (1 << (kIfastShift - 1))) >> kIfastShift) + 128);
-  } else {
-    const FloatOps ops{k.kf[0], k.kf[1], k.kf[2], k.kf[3]};
-    float in[8], s[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) in[i] = __int_as_float(w[8 * lane + i]);
-    aan8(in, s, ops);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) px[i] = clamp_u8(static_cast<int>(floorf(s[i] + 128.5f)));
-  }
-  if (!live) return;
+// One decoded row of eight samples: into the component's plane, or, for
+// grayscale, straight into the output row (cropped to the image).
+__device__ __forceinline__ void store_row(const View& v, int comp, int bx, int by, int lane, const uint32_t px[8]) {
   const uint32_t lo = px[0] | (px[1] << 8) | (px[2] << 16) | (px[3] << 24);
   const uint32_t hi = px[4] | (px[5] << 8) | (px[6] << 16) | (px[7] << 24);
   const int y = by * 8 + lane;
-  if (v.ncomp == 1) {  // grayscale: straight into the output, cropped
+  if (v.ncomp == 1) {
     if (y >= v.height) return;
     uint8_t* dst = v.out + static_cast<size_t>(y) * v.pitch + bx * 8;
     const int n = min(8, v.width - bx * 8);
@@ -260,6 +161,131 @@ __global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts 
   }
   uint8_t* dst = v.work + v.plane_off[comp] + static_cast<size_t>(y) * v.plane_pitch[comp] + bx * 8;
   *reinterpret_cast<uint2*>(dst) = make_uint2(lo, hi);
+}
+
+// LDS layouts without bank conflicts for the eight blocks of a wave:
+// coefficients 72 int16 (144 bytes) per block, so the eight blocks' column
+// reads fall on distinct banks; transform values in rows of 9 words, 72
+// words per block, so both the column writes and the row reads of a wave
+// cover 64 distinct banks.
+constexpr int kCfStride = 72;
+constexpr int kWsRow = 9;
+constexpr int kWsStride = 72;
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts k) {
+  __shared__ __align__(16) int16_t cf[kBlocksPerWG * kCfStride];
+  __shared__ __align__(16) int32_t ws[kBlocksPerWG * kWsStride];
+  __shared__ int32_t tab[4 * 64];
+  const int t = static_cast<int>(threadIdx.x);
+  // the four multiplier tables
+  {
+    const int e = t & 63;
+    const uint32_t q = v.qt[t];
+    if constexpr (M == MJD_IDCT_ISLOW) {
+      tab[t] = static_cast<int32_t>(q);
+    } else if constexpr (M == MJD_IDCT_IFAST) {
+      tab[t] = static_cast<int32_t>((static_cast<int64_t>(q) * k.a14[e] + (1 << (13 - kIfastFrac))) >> (14 - kIfastFrac));
+    } else {
+      tab[t] = __float_as_int(static_cast<float>(static_cast<double>(q) / k.ss8[e]));
+    }
+  }
+  // block indices fit 32 bits: at most 65535^2 / 64 * 3 blocks
+  const uint32_t n_blocks = static_cast<uint32_t>(v.n_blocks);
+  const uint32_t n_tiles = (n_blocks + kBlocksPerWG - 1) / kBlocksPerWG;
+  const int blk = t >> 3, lane = t & 7;
+  // persistent over tiles of 32 blocks; the next tile's coefficients load
+  // into registers while this one is transformed
+  auto load = [&](uint32_t tile) {
+    int4 d = {0, 0, 0, 0};
+    const uint32_t bb = tile * kBlocksPerWG + blk;
+    if (tile < n_tiles && bb < n_blocks) d = reinterpret_cast<const int4*>(v.coef + static_cast<size_t>(bb) * 64)[lane];
+    return d;
+  };
+  uint32_t tile = blockIdx.x;
+  int4 next = load(tile);
+  for (; tile < n_tiles; tile += gridDim.x) {
+    *reinterpret_cast<int4*>(cf + blk * kCfStride + lane * 8) = next;
+    next = load(tile + gridDim.x);
+    __syncthreads();
+    const uint32_t b = tile * kBlocksPerWG + blk;
+    const bool live = b < n_blocks;
+    // the block's component and position in that component's block grid
+    int comp = 0, bx, by;
+    {
+      const uint32_t bpm = static_cast<uint32_t>(v.bpm), mcx = static_cast<uint32_t>(v.mcus_x);
+      const uint32_t m = live ? b / bpm : 0;
+      const int j = live ? static_cast<int>(b - m * bpm) : 0;
+      const uint32_t myu = m / mcx;
+      const int mx = static_cast<int>(m - myu * mcx);
+      const int my = static_cast<int>(myu);
+      const int ny = v.hy * v.vy;
+      if (v.ncomp == 1 || j < ny) {
+        const int jy = j / v.hy, jx = j - jy * v.hy;
+        bx = mx * v.hy + jx;
+        by = my * v.vy + jy;
+      } else {
+        comp = j - ny + 1;
+        bx = mx;
+        by = my;
+      }
+    }
+    const int32_t* q = tab + 64 * v.qsel[comp];
+    const int16_t* c = cf + kCfStride * blk;
+    int32_t* w = ws + kWsStride * blk;
+    // column pass: this lane's column `lane`
+    if constexpr (M == MJD_IDCT_ISLOW) {
+      int y[8];
+      idct8_raw(c[lane] * q[lane], c[8 + lane] * q[8 + lane], c[16 + lane] * q[16 + lane],
+                c[24 + lane] * q[24 + lane], c[32 + lane] * q[32 + lane], c[40 + lane] * q[40 + lane],
+                c[48 + lane] * q[48 + lane], c[56 + lane] * q[56 + lane], kPass1Bias, y);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) w[kWsRow * i + lane] = y[i] >> kPass1Shift;
+    } else if constexpr (M == MJD_IDCT_IFAST) {
+      const IfastOps ops{k.ki[0], k.ki[1], k.ki[2], k.ki[3]};
+      int in[8], y[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) in[u] = c[8 * u + lane] * q[8 * u + lane];
+      aan8(in, y, ops);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) w[kWsRow * i + lane] = y[i];
+    } else {
+      const FloatOps ops{k.kf[0], k.kf[1], k.kf[2], k.kf[3]};
+      float in[8], y[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) in[u] = static_cast<float>(c[8 * u + lane]) * __int_as_float(q[8 * u + lane]);
+      aan8(in, y, ops);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) w[kWsRow * i + lane] = __float_as_int(y[i]);
+    }
+    __syncthreads();
+    // row pass: this lane's row `lane`
+    uint32_t px[8];
+    const int* r = w + kWsRow * lane;
+    if constexpr (M == MJD_IDCT_ISLOW) {
+      int s[8];
+      idct8_raw(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], kPass2Bias, s);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) px[i] = clamp_u8(s[i] >> kPass2Shift);
+    } else if constexpr (M == MJD_IDCT_IFAST) {
+      const IfastOps ops{k.ki[0], k.ki[1], k.ki[2], k.ki[3]};
+      int in[8], s[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) in[i] = r[i];
+      aan8(in, s, ops);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) px[i] = clamp_u8(((s[i] + (1 << (kIfastShift - 1))) >> kIfastShift) + 128);
+    } else {
+      const FloatOps ops{k.kf[0], k.kf[1], k.kf[2], k.kf[3]};
+      float in[8], s[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) in[i] = __int_as_float(r[i]);
+      aan8(in, s, ops);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) px[i] = clamp_u8(static_cast<int>(floorf(s[i] + 128.5f)));
+    }
+    if (live) store_row(v, comp, bx, by, lane, px);
+  }
 }
 
 // --- kernel 2: upsample + colour -------------------------------------------
@@ -380,6 +406,23 @@ __global__ __launch_bounds__(256) void var_colour(const View v) {
   }
 }
 
+// The IDCT kernel runs as many workgroups as stay resident (each loops over
+// tiles), or one per tile when there are fewer.
+template <int M>
+hipError_t launch_idct(const View& v, const Consts& k, uint64_t n_tiles, int cu_count, hipStream_t s) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, var_idct<M>, kThreads, 0);
+    if (e != hipSuccess) return e;
+    per_cu = n > 0 ? n : 1;
+  }
+  const uint64_t slots = static_cast<uint64_t>(per_cu) * (cu_count > 0 ? cu_count : 256);
+  const unsigned grid = static_cast<unsigned>(n_tiles < slots ? n_tiles : slots);
+  hipLaunchKernelGGL(var_idct<M>, dim3(grid), dim3(kThreads), 0, s, v, k);
+  return hipGetLastError();
+}
+
 }  // namespace var
 
 // Geometry of a variant frame and the workspace its planes need.
@@ -489,13 +532,13 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   }
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const var::Consts& k = var::consts();
-  const unsigned grid1 = static_cast<unsigned>((g.n_blocks + var::kBlocksPerWG - 1) / var::kBlocksPerWG);
+  const uint64_t n_tiles = (g.n_blocks + var::kBlocksPerWG - 1) / var::kBlocksPerWG;
+  hipError_t e;
   switch (variant->idct) {
-    case MJD_IDCT_ISLOW: hipLaunchKernelGGL(var::var_idct<MJD_IDCT_ISLOW>, dim3(grid1), dim3(var::kThreads), 0, s, v, k); break;
-    case MJD_IDCT_IFAST: hipLaunchKernelGGL(var::var_idct<MJD_IDCT_IFAST>, dim3(grid1), dim3(var::kThreads), 0, s, v, k); break;
-    default: hipLaunchKernelGGL(var::var_idct<MJD_IDCT_FLOAT>, dim3(grid1), dim3(var::kThreads), 0, s, v, k); break;
+    case MJD_IDCT_ISLOW: e = var::launch_idct<MJD_IDCT_ISLOW>(v, k, n_tiles, ctx->cu_count, s); break;
+    case MJD_IDCT_IFAST: e = var::launch_idct<MJD_IDCT_IFAST>(v, k, n_tiles, ctx->cu_count, s); break;
+    default: e = var::launch_idct<MJD_IDCT_FLOAT>(v, k, n_tiles, ctx->cu_count, s); break;
   }
-  hipError_t e = hipGetLastError();
   if (e == hipSuccess && nc == 3) {
     const uint64_t groups = static_cast<uint64_t>((v.width + 7) / 8) * v.height;
     hipLaunchKernelGGL(var::var_colour, dim3(static_cast<unsigned>((groups + 255) / 256)), dim3(256), 0, s, v);
