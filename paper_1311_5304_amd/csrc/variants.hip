@@ -202,11 +202,18 @@ __global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts 
     if (tile < n_tiles && bb < n_blocks) d = reinterpret_cast<const int4*>(v.coef + static_cast<size_t>(bb) * 64)[lane];
     return d;
   };
-  uint32_t tile = blockIdx.x;
-  int4 next = load(tile);
-  for (; tile < n_tiles; tile += gridDim.x) {
+  // Workgroups are dealt to the 8 XCDs round-robin (the grid is a multiple
+  // of 8): each XCD walks its own contiguous run of tiles, so the partial
+  // plane lines that neighbouring tiles write meet in one L2.
+  const uint32_t per_xcd = (n_tiles + 7) / 8;
+  const uint32_t xcd = blockIdx.x & 7u;
+  const uint32_t end = min(n_tiles, (xcd + 1) * per_xcd);
+  const uint32_t stride = gridDim.x >> 3;
+  uint32_t tile = xcd * per_xcd + (blockIdx.x >> 3);
+  int4 next = tile < end ? load(tile) : int4{0, 0, 0, 0};
+  for (; tile < end; tile += stride) {
     *reinterpret_cast<int4*>(cf + blk * kCfStride + lane * 8) = next;
-    next = load(tile + gridDim.x);
+    next = tile + stride < end ? load(tile + stride) : int4{0, 0, 0, 0};
     __syncthreads();
     const uint32_t b = tile * kBlocksPerWG + blk;
     const bool live = b < n_blocks;
@@ -378,7 +385,11 @@ __device__ __forceinline__ void chroma8(const View& v, const uint8_t* p, uint32_
 
 __global__ __launch_bounds__(256) void var_colour(const View v) {
   const int gpr = (v.width + 7) >> 3;
-  const uint64_t g = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+  // the grid is a multiple of 8 dealt to the XCDs round-robin: each XCD
+  // takes a contiguous band of rows, so the chroma rows that neighbouring
+  // output rows share are fetched once into its L2
+  const uint32_t wg = (blockIdx.x & 7u) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const uint64_t g = static_cast<uint64_t>(wg) * 256 + threadIdx.x;
   if (g >= static_cast<uint64_t>(gpr) * static_cast<uint64_t>(v.height)) return;
   const int y = static_cast<int>(g / static_cast<uint64_t>(gpr));
   const int x0 = static_cast<int>(g - static_cast<uint64_t>(y) * gpr) * 8;
@@ -407,7 +418,7 @@ __global__ __launch_bounds__(256) void var_colour(const View v) {
 }
 
 // The IDCT kernel runs as many workgroups as stay resident (each loops over
-// tiles), or one per tile when there are fewer.
+// tiles), or about one per tile when there are fewer.
 template <int M>
 hipError_t launch_idct(const View& v, const Consts& k, uint64_t n_tiles, int cu_count, hipStream_t s) {
   static int per_cu = 0;
@@ -417,8 +428,10 @@ hipError_t launch_idct(const View& v, const Consts& k, uint64_t n_tiles, int cu_
     if (e != hipSuccess) return e;
     per_cu = n > 0 ? n : 1;
   }
-  const uint64_t slots = static_cast<uint64_t>(per_cu) * (cu_count > 0 ? cu_count : 256);
-  const unsigned grid = static_cast<unsigned>(n_tiles < slots ? n_tiles : slots);
+  // a multiple of 8, at most the resident slots and about one tile each
+  const uint64_t slots = (static_cast<uint64_t>(per_cu) * (cu_count > 0 ? cu_count : 256)) & ~7ull;
+  const uint64_t want = (n_tiles + 7) & ~7ull;
+  const unsigned grid = static_cast<unsigned>(want < slots ? want : (slots >= 8 ? slots : 8));
   hipLaunchKernelGGL(var_idct<M>, dim3(grid), dim3(kThreads), 0, s, v, k);
   return hipGetLastError();
 }
@@ -541,7 +554,8 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   }
   if (e == hipSuccess && nc == 3) {
     const uint64_t groups = static_cast<uint64_t>((v.width + 7) / 8) * v.height;
-    hipLaunchKernelGGL(var::var_colour, dim3(static_cast<unsigned>((groups + 255) / 256)), dim3(256), 0, s, v);
+    const unsigned grid2 = static_cast<unsigned>(((groups + 255) / 256 + 7) & ~7ull);
+    hipLaunchKernelGGL(var::var_colour, dim3(grid2), dim3(256), 0, s, v);
     e = hipGetLastError();
   }
   if (cur != ctx->device) (void)hipSetDevice(cur);
