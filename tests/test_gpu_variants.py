@@ -3,7 +3,8 @@ variant oracle, byte for byte: every IDCT method (islow, ifast, float) on
 every sampling ((1,1), (2,1), (1,2), (2,2), (4,1)) in both upsampling modes,
 and grayscale; ragged sizes spanning several workgroups, a 1x1 image,
 extreme coefficients of the whole input domain, padded and misaligned
-output rows, and a 4096x3072 image per method.  islow through the variants
+output rows, the largest widths and heights, and a 4096x3072 image per
+method.  islow through the variants
 path also equals mjd_decode on the samplings both serve."""
 import numpy as np
 import pytest
@@ -136,6 +137,17 @@ def test_bad_calls_are_refused(M, ctx):
         with pytest.raises(M.MjdError):
             M.mjd_decode_variant(ctx, v, *args)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("w,h,hy,vy,ncomp", [(65535, 16, 4, 1, 3), (65535, 9, 1, 2, 3), (17, 65535, 2, 2, 3),
+                                             (65535, 11, 1, 1, 1)])
+def test_maximum_sizes(M, ctx, w, h, hy, vy, ncomp):
+    fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 1), "ncomp": ncomp}
+    coef, qt = _case(w + h + hy, fr)
+    for method in V.IDCT_METHODS:
+        say(f"{method} {w}x{h} {hy}x{vy} ncomp={ncomp}")
+        got = _run(M, ctx, fr, coef, qt, method, "fancy", ncomp)
+        assert np.array_equal(got, V.decode_variant(fr, coef, qt, method, "fancy")), (method, w, h)
 
 
 @pytest.mark.parametrize("method", V.IDCT_METHODS)
