@@ -38,6 +38,19 @@ Readings (the paper names the methods only):
   floor(v + 128.5) clamped to 0..255.  s(k) and the constants come from the
   C library's cos (Python's math module).
 
+Scaled decoding (output 1/s of the image in each direction, s in 2, 4, 8;
+N = 8 / s) takes each block's top-left N x N coefficients through the
+N-point IDCT with the 8-point normalisation, so a constant block keeps its
+value:
+  x(m, n) = 1/4 sum_{u, v < N} c(u) c(v) F(u, v) cos((2m+1) u pi / 2N) cos((2n+1) v pi / 2N).
+Readings: the fixed-point form follows islow (the 1-D transform
+x0 * 2^13 + sum_{u >= 1} round(2^13 sqrt(2) cos((2m+1) u pi / 2N)) x_u,
+columns then rows, pass 1 descaled by 11 and pass 2 by 18 with rounding,
++128, clamp), whatever the IDCT method of the full-size decode; the output
+is ceil(W / s) x ceil(H / s) and component c's plane ceil(W h_c / (hmax s))
+wide (likewise in height); upsampling and colour conversion then run at that
+size.
+
 Samplings
   luma (h, v) in {(1,1), (2,1), (1,2), (2,2), (4,1)}, chroma 1x1, and
   grayscale (one component, blocks in raster order).
@@ -172,6 +185,36 @@ def idct_float(coef: np.ndarray, q: np.ndarray) -> np.ndarray:
     return np.clip(out, 0, 255).astype(np.uint8).reshape(shape + (8, 8))
 
 
+# ---- reduced (scaled) IDCT -------------------------------------------------------------------
+SCALES = (1, 2, 4, 8)
+
+
+def reduced_constants(n: int):
+    """K[m][u] = round(2^13 sqrt(2) cos((2m+1) u pi / 2n)) for u >= 1."""
+    return [[round((1 << 13) * math.sqrt(2.0) * math.cos((2 * m + 1) * u * math.pi / (2 * n))) for u in range(n)]
+            for m in range(n)]
+
+
+def _reduced_1d(x, K):
+    n = len(x)
+    return [_chk(sum((K[m][u] * x[u] for u in range(1, n)), _chk(x[0] << 13))) for m in range(n)]
+
+
+def idct_reduced(coef: np.ndarray, q: np.ndarray, n: int) -> np.ndarray:
+    """int16[..., 64], uint16[64] -> uint8[..., n, n] from the top-left n x n
+    coefficients."""
+    c = np.asarray(coef, dtype=np.int64)
+    shape = c.shape[:-1]
+    d = (c.reshape(-1, 8, 8) * np.asarray(q, dtype=np.int64).reshape(8, 8))[:, :n, :n]   # [k, u, v]
+    K = reduced_constants(n)
+    cols = _reduced_1d([d[:, u, :] for u in range(n)], K)                # m -> [k, v]
+    ws = np.stack([_chk(_chk(y + (1 << 10)) >> 11) for y in cols], axis=1)  # [k, m, v]
+    rows = _reduced_1d([ws[:, :, v] for v in range(n)], K)               # x -> [k, m]
+    out = np.stack(rows, axis=2)                                         # [k, m, x]
+    out = _chk(out + (1 << 17) + (128 << 18)) >> 18
+    return np.clip(out, 0, 255).astype(np.uint8).reshape(shape + (n, n))
+
+
 def idct(coef: np.ndarray, q: np.ndarray, method: str) -> np.ndarray:
     if method == "islow":
         return idct_blocks(dequantise(coef, q))
@@ -198,8 +241,13 @@ def variant_geometry(frame: dict) -> dict:
     return geometry(frame)
 
 
-def planes(frame: dict, coef: np.ndarray, qt: np.ndarray, method: str):
-    """MCU-order blocks -> cropped uint8 component planes."""
+def planes(frame: dict, coef: np.ndarray, qt: np.ndarray, method: str, scale: int = 1):
+    """MCU-order blocks -> cropped uint8 component planes (1/scale size)."""
+    if scale not in SCALES:
+        raise ValueError(f"scale 1/{scale} not supported")
+    if scale > 1 and method != "islow":
+        raise ValueError("scaled decoding has the islow-style reduced transform only")
+    n = 8 // scale
     g = variant_geometry(frame)
     nc = frame.get("ncomp", 3)
     mx, my, bpm = g["mcus_x"], g["mcus_y"], g["blocks_per_mcu"]
@@ -211,10 +259,11 @@ def planes(frame: dict, coef: np.ndarray, qt: np.ndarray, method: str):
         part = c[:, :, first:first + hc * vc, :].reshape(my, mx, vc, hc, 64)
         grid = part.transpose(0, 2, 1, 3, 4).reshape(my * vc, mx * hc, 64)
         first += hc * vc
-        s = idct(grid, np.asarray(qt)[frame["qsel"][k]], method)       # [gh, gw, 8, 8]
+        q = np.asarray(qt)[frame["qsel"][k]]
+        s = idct(grid, q, method) if n == 8 else idct_reduced(grid, q, n)   # [gh, gw, n, n]
         gh, gw = s.shape[:2]
-        plane = s.transpose(0, 2, 1, 3).reshape(gh * 8, gw * 8)
-        out.append(plane[:g["comp_h"][k], :g["comp_w"][k]])
+        plane = s.transpose(0, 2, 1, 3).reshape(gh * n, gw * n)
+        out.append(plane[:ceil_div(g["comp_h"][k], scale), :ceil_div(g["comp_w"][k], scale)])
     return out
 
 
@@ -246,11 +295,12 @@ def upsample_variant(c: np.ndarray, fh: int, fv: int, mode: str) -> np.ndarray:
 
 
 def decode_variant(frame: dict, coef: np.ndarray, qt: np.ndarray, method: str = "islow",
-                   mode: str = "fancy") -> np.ndarray:
-    """-> uint8[H, W, 3] (YCbCr frames) or uint8[H, W] (grayscale)."""
+                   mode: str = "fancy", scale: int = 1) -> np.ndarray:
+    """-> uint8[H', W', 3] (YCbCr frames) or uint8[H', W'] (grayscale),
+    W' = ceil(W / scale), H' = ceil(H / scale)."""
     g = variant_geometry(frame)
-    w, h = frame["width"], frame["height"]
-    p = planes(frame, coef, qt, method)
+    w, h = ceil_div(frame["width"], scale), ceil_div(frame["height"], scale)
+    p = planes(frame, coef, qt, method, scale)
     if frame.get("ncomp", 3) == 1:
         return p[0][:h, :w].astype(np.uint8)
     full = []

@@ -183,3 +183,87 @@ def test_rejects_unknown_variants():
         V.variant_geometry(_frame(8, 8, 4, 2))
     with pytest.raises(ValueError):
         V.idct(np.zeros((1, 64), np.int16), np.ones(64, np.uint16), "aan")
+
+
+# ---- scaled decoding ----------------------------------------------------------------------
+
+
+def _exact_reduced(coef, q, n):
+    Cn = np.array([[(math.sqrt(0.5) if u == 0 else 1.0) * math.cos((2 * m + 1) * u * math.pi / (2 * n))
+                    for u in range(n)] for m in range(n)])
+    F = (np.asarray(coef, np.float64).reshape(-1, 8, 8) * np.asarray(q, np.float64).reshape(8, 8))[:, :n, :n]
+    return 0.25 * np.einsum("mu,kuv,nv->kmn", Cn, F, Cn)
+
+
+@pytest.mark.parametrize("n", [4, 2, 1])
+def test_reduced_idct_within_one_level_of_fp64(n):
+    rng = np.random.default_rng(40 + n)
+    for qv in (1, 3, 12):
+        q = np.full(64, qv, np.uint16)
+        coef = _blocks(rng, 500, qv)
+        ref = np.clip(np.floor(_exact_reduced(coef, q, n) + 128.5), 0, 255)
+        d = np.abs(V.idct_reduced(coef, q, n).astype(np.float64) - ref)
+        assert d.max() <= 1 and (d == 0).mean() > 0.95
+
+
+@pytest.mark.parametrize("n", [4, 2, 1])
+def test_reduced_dc_only_is_exact(n):
+    for qv in (1, 5, 16):
+        q = np.full(64, 7, np.uint16)
+        q[0] = qv
+        dc = np.arange(-1155 // qv, 1155 // qv + 1)
+        coef = np.zeros((len(dc), 64), np.int16)
+        coef[:, 0] = dc
+        want = np.clip(np.floor(dc * qv / 8 + 0.5) + 128, 0, 255)
+        got = V.idct_reduced(coef, q, n)
+        assert np.array_equal(got, np.broadcast_to(want[:, None, None], got.shape))
+
+
+def test_reduced_2x2_is_the_exact_haar_average():
+    # N = 2: sqrt(2) cos(pi/4) = 1, so the transform is exact integer
+    # arithmetic: x(m, n) = round((F00 + sm F10 + sn F01 + sm sn F11) / 8) + 128
+    rng = np.random.default_rng(8)
+    q = rng.integers(1, 9, 64).astype(np.uint16)
+    coef = rng.integers(-100, 101, (300, 64)).astype(np.int16)
+    F = coef.reshape(-1, 8, 8).astype(np.int64) * q.reshape(8, 8).astype(np.int64)
+    got = V.idct_reduced(coef, q, 2)
+    for m, sm in ((0, 1), (1, -1)):
+        for n, sn in ((0, 1), (1, -1)):
+            s = F[:, 0, 0] + sm * F[:, 1, 0] + sn * F[:, 0, 1] + sm * sn * F[:, 1, 1]
+            want = np.clip(np.floor(s / 8 + 0.5) + 128, 0, 255)
+            assert np.array_equal(got[:, m, n], want)
+
+
+@pytest.mark.parametrize("samp,scale", [("444", 2), ("444", 4), ("420", 2), ("420", 8), ("422", 4)])
+def test_scaled_decode_is_close_to_a_box_downscale(samp, scale):
+    # a smooth image: the scaled decode against the full-size decode averaged
+    # over scale x scale boxes
+    from synth import encode, images
+    w, h = 128, 96
+    frame, coef, qt = encode.encode_rgb(images.texture_rgb(w, h, 5, sigma=2), samp, 95)
+    full = V.decode_variant(frame, coef, qt, "islow", "fancy").astype(np.float64)
+    box = full.reshape(h // scale, scale, w // scale, scale, 3).mean(axis=(1, 3))
+    got = V.decode_variant(frame, coef, qt, "islow", "fancy", scale).astype(np.float64)
+    assert got.shape == (h // scale, w // scale, 3)
+    # chroma upsampled at the reduced size differs from averaged full-size
+    # chroma by a few levels; a one-pixel shift costs several times more
+    err = np.abs(got - box).mean()
+    assert err < (2.5 if samp == "444" else 5.0)
+    assert np.abs(got[:, 1:] - box[:, :-1]).mean() > 2 * err
+    assert np.abs(got[1:] - box[:-1]).mean() > 2 * err
+
+
+def test_scaled_output_sizes():
+    rng = np.random.default_rng(2)
+    qt = np.ones((4, 64), np.uint16)
+    for w, h, hy, vy in ((37, 21, 2, 2), (1, 1, 4, 1), (17, 9, 1, 2), (65, 33, 2, 1)):
+        fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 1)}
+        c = _coef(rng, fr)
+        for s in (2, 4, 8):
+            assert V.decode_variant(fr, c, qt, "islow", "fancy", s).shape == (-(-h // s), -(-w // s), 3)
+            p = V.planes(fr, c, qt, "islow", s)
+            assert p[1].shape == (-(-h // (vy * s)), -(-w // (hy * s)))
+    with pytest.raises(ValueError):
+        V.planes(fr, c, qt, "ifast", 2)
+    with pytest.raises(ValueError):
+        V.planes(fr, c, qt, "islow", 3)
