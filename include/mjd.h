@@ -171,6 +171,11 @@ int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, const uint16_
  * (1,1); fancy upsampling filters factors of 2 (Algorithm 1, vertical for
  * (1,2)) and replicates a factor of 4.  Grayscale: one component, blocks in
  * raster order, one output byte per pixel.
+ * Scaled decoding (scale 2, 4, 8; islow only): each block's top-left N x N
+ * coefficients (N = 8 / scale) through the N-point IDCT with the 8-point
+ * normalisation, x(m,n) = 1/4 sum c(u) c(v) F(u,v) cos((2m+1)u pi/2N)
+ * cos((2n+1)v pi/2N), in islow-style fixed point; the output is
+ * ceil(W / scale) x ceil(H / scale), upsampled and converted at that size.
  * ------------------------------------------------------------------- */
 enum { MJD_IDCT_ISLOW = 0, MJD_IDCT_IFAST = 1, MJD_IDCT_FLOAT = 2 };
 
@@ -179,20 +184,22 @@ typedef struct mjd_variant {
   uint32_t ncomp;    /* 3: YCbCr -> RGB8 (3 bytes per pixel); 1: grayscale (1 byte per pixel) */
   int32_t idct;      /* MJD_IDCT_* */
   int32_t upsample;  /* MJD_UPSAMPLE_* (unused for grayscale) */
-  uint32_t reserved; /* must be 0 */
+  uint32_t scale;    /* output 1/scale of the image in each direction: 0 or 1 (full size), 2, 4 or 8 */
 } mjd_variant;
 
-/* Host only: validates `variant` and gives its geometry (grayscale:
- * 8x8 MCUs of one block; comp_w/comp_h of absent components 0) and the
- * workspace mjd_decode_variant needs (0 for grayscale).  out and work_bytes
+/* Host only: validates `variant` and gives its geometry: the coefficient
+ * layout (grayscale: 8x8 MCUs of one block), comp_w/comp_h at the output
+ * scale (0 for absent components), and the workspace mjd_decode_variant
+ * needs (0 for grayscale).  out and work_bytes
  * may be NULL.  MJD_EINVAL for bad fields, MJD_EUNSUPPORTED for other
  * samplings. */
 int mjd_variant_geometry(const mjd_variant* variant, mjd_geometry* out, uint64_t* work_bytes);
 
 /* Decodes a whole image.  d_coef: n_blocks * 64 int16 in MCU order,
  * 16-byte aligned (same numeric domain as mjd_decode); d_qt: uint16[4][64];
- * d_out: rows of `pitch` bytes (pitch >= ncomp * width, < 2^31), only each
- * row's first ncomp * width bytes written; d_work: device workspace of at
+ * d_out: ceil(H / scale) rows of `pitch` bytes (pitch >= ncomp * ceil(W /
+ * scale), < 2^31), only each row's first ncomp * ceil(W / scale) bytes
+ * written; d_work: device workspace of at
  * least the size mjd_variant_geometry gives, 16-byte aligned, owned by the
  * caller, overwritten (may be NULL for grayscale).  Asynchronous on
  * `stream`.  MJD_EINVAL for bad arguments, MJD_EDEVICE for launch

@@ -45,20 +45,21 @@ def decode(ctx: Context, frame, coef, qt, mode: str = "fancy", out=None, rows=No
 
 
 def decode_variant(ctx: Context, frame, coef, qt, idct: str = "islow", mode: str = "fancy", ncomp: int = 3,
-                   out=None, stream=None):
+                   out=None, stream=None, scale: int = 1):
     """Decode one image through the variants path (IDCT method `idct`,
-    samplings (1,1), (2,1), (1,2), (2,2), (4,1), or grayscale with ncomp=1).
-    Allocates the plane workspace with torch.  Returns `out`: uint8
-    [H, W, 3], or [H, W] for grayscale."""
+    samplings (1,1), (2,1), (1,2), (2,2), (4,1), or grayscale with ncomp=1;
+    output 1/scale of the image for scale 2, 4, 8).  Allocates the plane
+    workspace with torch.  Returns `out`: uint8 [H', W', 3], or [H', W'] for
+    grayscale, H' = ceil(H / scale), W' = ceil(W / scale)."""
     import torch
 
-    v = make_variant(frame, ncomp, idct, mode)
+    v = make_variant(frame, ncomp, idct, mode, scale)
     g, wb = mjd_variant_geometry(v)
     if coef.numel() != g["n_blocks"] * 64 or coef.element_size() != 2 or not coef.is_cuda:
         raise ValueError("coef must be a CUDA int16 tensor of n_blocks*64 elements")
     if qt.numel() != 256 or qt.element_size() != 2 or not qt.is_cuda:
         raise ValueError("qt must be a CUDA 16-bit tensor of 4*64 entries")
-    h, w = int(frame["height"]), int(frame["width"])
+    h, w = -(-int(frame["height"]) // scale), -(-int(frame["width"]) // scale)
     shape = (h, w, 3) if ncomp == 3 else (h, w)
     if out is None:
         out = torch.empty(shape, dtype=torch.uint8, device=coef.device)

@@ -117,7 +117,7 @@ class mjd_hetero_plan(ctypes.Structure):
 
 class mjd_variant(ctypes.Structure):
     _fields_ = [("frame", mjd_frame), ("ncomp", ctypes.c_uint32), ("idct", ctypes.c_int32),
-                ("upsample", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+                ("upsample", ctypes.c_int32), ("scale", ctypes.c_uint32)]
 
 
 class mjd_pipeline_config(ctypes.Structure):
@@ -586,7 +586,7 @@ def mjd_repartition_rows(model: mjd_model, width: int, height: int, rows_left: i
     return {k: getattr(out, k) for k, _ in mjd_partition._fields_}
 
 
-def make_variant(frame, ncomp: int = 3, idct: str = "islow", mode: str = "fancy") -> mjd_variant:
+def make_variant(frame, ncomp: int = 3, idct: str = "islow", mode: str = "fancy", scale: int = 1) -> mjd_variant:
     """frame dict (as for make_frame; grayscale may give width, height and
     qsel only) -> mjd_variant."""
     f = dict(frame)
@@ -595,7 +595,7 @@ def make_variant(frame, ncomp: int = 3, idct: str = "islow", mode: str = "fancy"
     q = tuple(f.get("qsel", (0, 0, 0))) + (0, 0, 0)
     f["qsel"] = q[:3]
     return mjd_variant(frame=make_frame(f), ncomp=int(ncomp), idct=IDCT[idct],
-                       upsample=MJD_UPSAMPLE_FANCY if mode == "fancy" else MJD_UPSAMPLE_SIMPLE)
+                       upsample=MJD_UPSAMPLE_FANCY if mode == "fancy" else MJD_UPSAMPLE_SIMPLE, scale=int(scale))
 
 
 def mjd_variant_geometry(variant: mjd_variant) -> tuple:

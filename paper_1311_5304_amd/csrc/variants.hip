@@ -18,6 +18,12 @@
 //   float  the same flowgraph in IEEE single precision, multipliers
 //          fp32(q / (8 s(u) s(v))), one rounding per operation in a fixed
 //          order (no contraction), floor(v + 128.5).
+// Scaled decoding (1/2, 1/4, 1/8 output): var_idct_red<N>, one block per
+// lane, takes the block's top-left N x N coefficients through the N-point
+// IDCT with the 8-point normalisation, in islow-style fixed point
+// (x0 * 2^13 + sum round(2^13 sqrt(2) cos((2m+1) u pi / 2N)) x_u, pass 1
+// descaled by 11, pass 2 by 18, +128); the colour kernel then runs at the
+// reduced size.
 #include <math.h>
 
 #include <mutex>
@@ -70,6 +76,27 @@ const Consts& consts() {
   return k;
 }
 
+// Constants of the reduced transforms: K[m][u] = round(2^13 sqrt(2)
+// cos((2m+1) u pi / 2N)), index N*m + u.
+struct RedConsts {
+  int32_t k4[16];
+  int32_t k2[4];
+};
+
+const RedConsts& red_consts() {
+  static RedConsts k;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (int m = 0; m < 4; ++m)
+      for (int u = 0; u < 4; ++u)
+        k.k4[4 * m + u] = static_cast<int32_t>(llround(8192.0 * sqrt(2.0) * cos((2 * m + 1) * u * M_PI / 8.0)));
+    for (int m = 0; m < 2; ++m)
+      for (int u = 0; u < 2; ++u)
+        k.k2[2 * m + u] = static_cast<int32_t>(llround(8192.0 * sqrt(2.0) * cos((2 * m + 1) * u * M_PI / 4.0)));
+  });
+  return k;
+}
+
 struct View {
   const int16_t* coef;
   const uint16_t* qt;
@@ -80,6 +107,7 @@ struct View {
   uint32_t plane_pitch[3];
   uint32_t pitch;
   int width, height, ncomp, hy, vy, mcus_x, bpm, fancy, aligned_out;
+  int n;  // samples per block side in the planes (8, or 8 / scale)
   int qsel[3];
   int comp_w, comp_h;  // the chroma components' true size
 };
@@ -295,6 +323,87 @@ __global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts 
   }
 }
 
+// --- kernel 1b: reduced IDCT for scaled decoding -----------------------------
+template <int N>
+__device__ __forceinline__ void red_1d(const int x[N], int y[N], const int32_t* K, int bias) {
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    int acc = (x[0] << 13) + bias;
+#pragma unroll
+    for (int u = 1; u < N; ++u) acc += K[N * m + u] * x[u];
+    y[m] = acc;
+  }
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void var_idct_red(const View v, const RedConsts k) {
+  const uint32_t b = blockIdx.x * 256u + threadIdx.x;
+  if (b >= static_cast<uint32_t>(v.n_blocks)) return;
+  const int32_t* K = N == 4 ? k.k4 : k.k2;
+  int comp = 0, bx, by;
+  {
+    const uint32_t bpm = static_cast<uint32_t>(v.bpm), mcx = static_cast<uint32_t>(v.mcus_x);
+    const uint32_t m = b / bpm;
+    const int j = static_cast<int>(b - m * bpm);
+    const uint32_t myu = m / mcx;
+    const int mx = static_cast<int>(m - myu * mcx), my = static_cast<int>(myu);
+    const int ny = v.hy * v.vy;
+    if (v.ncomp == 1 || j < ny) {
+      const int jy = j / v.hy, jx = j - jy * v.hy;
+      bx = mx * v.hy + jx;
+      by = my * v.vy + jy;
+    } else {
+      comp = j - ny + 1;
+      bx = mx;
+      by = my;
+    }
+  }
+  const int16_t* c = v.coef + static_cast<size_t>(b) * 64;
+  const uint16_t* q = v.qt + 64 * v.qsel[comp];
+  uint32_t px[N][N];
+  if constexpr (N == 1) {
+    px[0][0] = clamp_u8(((c[0] * static_cast<int>(q[0])) * 32768 + (1 << 17) + (128 << 18)) >> 18);
+  } else {
+    int ws[N][N];
+#pragma unroll
+    for (int vv = 0; vv < N; ++vv) {  // pass 1: column vv
+      int x[N], y[N];
+#pragma unroll
+      for (int u = 0; u < N; ++u) x[u] = c[8 * u + vv] * static_cast<int>(q[8 * u + vv]);
+      red_1d<N>(x, y, K, 1 << 10);
+#pragma unroll
+      for (int m = 0; m < N; ++m) ws[m][vv] = y[m] >> 11;
+    }
+#pragma unroll
+    for (int m = 0; m < N; ++m) {  // pass 2: row m
+      int z[N];
+      red_1d<N>(ws[m], z, K, (1 << 17) + (128 << 18));
+#pragma unroll
+      for (int n = 0; n < N; ++n) px[m][n] = clamp_u8(z[n] >> 18);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const int y = by * N + m;
+    if (v.ncomp == 1) {  // grayscale: into the output rows, cropped
+      if (y >= v.height) break;
+      uint8_t* dst = v.out + static_cast<size_t>(y) * v.pitch + bx * N;
+#pragma unroll
+      for (int n = 0; n < N; ++n)
+        if (bx * N + n < v.width) dst[n] = static_cast<uint8_t>(px[m][n]);
+      continue;
+    }
+    uint8_t* dst = v.work + v.plane_off[comp] + static_cast<size_t>(y) * v.plane_pitch[comp] + bx * N;
+    if constexpr (N == 4) {
+      *reinterpret_cast<uint32_t*>(dst) = px[m][0] | (px[m][1] << 8) | (px[m][2] << 16) | (px[m][3] << 24);
+    } else if constexpr (N == 2) {
+      *reinterpret_cast<uint16_t*>(dst) = static_cast<uint16_t>(px[m][0] | (px[m][1] << 8));
+    } else {
+      dst[0] = static_cast<uint8_t>(px[m][0]);
+    }
+  }
+}
+
 // --- kernel 2: upsample + colour -------------------------------------------
 // Eight output pixels per lane: luma as one 8-byte load; chroma as the
 // samples the eight pixels read, from aligned loads plus the two clamped
@@ -443,7 +552,10 @@ static int variant_geometry(const mjd_variant* vr, mjd_geometry* g, uint64_t* wo
                             uint64_t plane_off[3]) {
   if (!vr || !g) return fail(MJD_EINVAL, "null variant or geometry pointer");
   const mjd_frame& f = vr->frame;
-  if (vr->reserved != 0 || f.reserved != 0) return fail(MJD_EINVAL, "reserved fields must be 0");
+  if (f.reserved != 0) return fail(MJD_EINVAL, "reserved frame field must be 0");
+  const uint32_t scale = vr->scale ? vr->scale : 1;
+  if (scale != 1 && scale != 2 && scale != 4 && scale != 8)
+    return fail(MJD_EINVAL, "scale 1/%u is not 1, 1/2, 1/4 or 1/8", vr->scale);
   if (f.width < 1 || f.width > 65535 || f.height < 1 || f.height > 65535)
     return fail(MJD_EINVAL, "image size %ux%u outside 1..65535", f.width, f.height);
   if (vr->ncomp != 1 && vr->ncomp != 3) return fail(MJD_EINVAL, "ncomp %u is neither 1 nor 3", vr->ncomp);
@@ -451,6 +563,8 @@ static int variant_geometry(const mjd_variant* vr, mjd_geometry* g, uint64_t* wo
     return fail(MJD_EINVAL, "IDCT method %d unknown", vr->idct);
   if (vr->upsample != MJD_UPSAMPLE_SIMPLE && vr->upsample != MJD_UPSAMPLE_FANCY)
     return fail(MJD_EINVAL, "upsample mode %d unknown", vr->upsample);
+  if (scale > 1 && vr->idct != MJD_IDCT_ISLOW)
+    return fail(MJD_EUNSUPPORTED, "scaled decoding has the islow-style reduced transform only");
   const int nc = static_cast<int>(vr->ncomp);
   for (int c = 0; c < nc; ++c)
     if (f.qsel[c] > 3) return fail(MJD_EINVAL, "component %d quant table selector %u > 3", c, f.qsel[c]);
@@ -470,14 +584,18 @@ static int variant_geometry(const mjd_variant* vr, mjd_geometry* g, uint64_t* wo
   g->mcus_y = (f.height + g->mcu_h - 1) / g->mcu_h;
   g->blocks_per_mcu = nc == 1 ? 1 : hy * vy + 2;
   g->n_blocks = static_cast<uint64_t>(g->mcus_x) * g->mcus_y * g->blocks_per_mcu;
+  // component sizes at the output scale; planes of whole blocks of n
+  // samples, rows padded to 16 bytes
+  const uint32_t n = 8 / scale;
   uint64_t total = 0;
   for (int c = 0; c < 3; ++c) {
     const uint32_t hc = c == 0 ? hy : 1, vc = c == 0 ? vy : 1;
-    g->comp_w[c] = c < nc ? (f.width * hc + hy - 1) / hy : 0;
-    g->comp_h[c] = c < nc ? (f.height * vc + vy - 1) / vy : 0;
-    plane_pitch[c] = g->mcus_x * hc * 8;
+    const uint32_t cw = (f.width * hc + hy - 1) / hy, ch = (f.height * vc + vy - 1) / vy;
+    g->comp_w[c] = c < nc ? (cw + scale - 1) / scale : 0;
+    g->comp_h[c] = c < nc ? (ch + scale - 1) / scale : 0;
+    plane_pitch[c] = (g->mcus_x * hc * n + 15) & ~15u;
     plane_off[c] = total;
-    if (nc == 3) total += (static_cast<uint64_t>(plane_pitch[c]) * g->mcus_y * vc * 8 + 255) & ~255ull;
+    if (nc == 3) total += (static_cast<uint64_t>(plane_pitch[c]) * g->mcus_y * vc * n + 255) & ~255ull;
   }
   *work = total;
   return MJD_OK;
@@ -511,7 +629,9 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   if (reinterpret_cast<uintptr_t>(d_coef) % 16) return fail(MJD_EINVAL, "coefficient buffer not 16-byte aligned");
   if (reinterpret_cast<uintptr_t>(d_qt) % 2) return fail(MJD_EINVAL, "quant table buffer not 2-byte aligned");
   const int nc = static_cast<int>(variant->ncomp);
-  const uint64_t row_bytes = static_cast<uint64_t>(nc) * variant->frame.width;
+  const uint32_t scale = variant->scale ? variant->scale : 1;
+  const uint32_t out_w = (variant->frame.width + scale - 1) / scale, out_h = (variant->frame.height + scale - 1) / scale;
+  const uint64_t row_bytes = static_cast<uint64_t>(nc) * out_w;
   if (pitch < row_bytes) return fail(MJD_EINVAL, "pitch %zu < %u*width", pitch, nc);
   if (pitch >= (1ull << 31)) return fail(MJD_EINVAL, "pitch %zu not below 2^31 bytes", pitch);
   if (nc == 3) {
@@ -526,8 +646,9 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   v.work = static_cast<uint8_t*>(d_work);
   v.n_blocks = g.n_blocks;
   v.pitch = static_cast<uint32_t>(pitch);
-  v.width = static_cast<int>(variant->frame.width);
-  v.height = static_cast<int>(variant->frame.height);
+  v.width = static_cast<int>(out_w);
+  v.height = static_cast<int>(out_h);
+  v.n = static_cast<int>(8 / scale);
   v.ncomp = nc;
   v.hy = nc == 3 ? variant->frame.h[0] : 1;
   v.vy = nc == 3 ? variant->frame.v[0] : 1;
@@ -547,7 +668,14 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   const var::Consts& k = var::consts();
   const uint64_t n_tiles = (g.n_blocks + var::kBlocksPerWG - 1) / var::kBlocksPerWG;
   hipError_t e;
-  switch (variant->idct) {
+  const unsigned grid_red = static_cast<unsigned>((g.n_blocks + 255) / 256);
+  if (scale > 1) {
+    const var::RedConsts& rk = var::red_consts();
+    if (scale == 2) hipLaunchKernelGGL(var::var_idct_red<4>, dim3(grid_red), dim3(256), 0, s, v, rk);
+    else if (scale == 4) hipLaunchKernelGGL(var::var_idct_red<2>, dim3(grid_red), dim3(256), 0, s, v, rk);
+    else hipLaunchKernelGGL(var::var_idct_red<1>, dim3(grid_red), dim3(256), 0, s, v, rk);
+    e = hipGetLastError();
+  } else switch (variant->idct) {
     case MJD_IDCT_ISLOW: e = var::launch_idct<MJD_IDCT_ISLOW>(v, k, n_tiles, ctx->cu_count, s); break;
     case MJD_IDCT_IFAST: e = var::launch_idct<MJD_IDCT_IFAST>(v, k, n_tiles, ctx->cu_count, s); break;
     default: e = var::launch_idct<MJD_IDCT_FLOAT>(v, k, n_tiles, ctx->cu_count, s); break;

@@ -150,6 +150,37 @@ def test_maximum_sizes(M, ctx, w, h, hy, vy, ncomp):
         assert np.array_equal(got, V.decode_variant(fr, coef, qt, method, "fancy")), (method, w, h)
 
 
+@pytest.mark.parametrize("scale", [2, 4, 8])
+def test_scaled_decoding_matches_oracle(M, ctx, scale):
+    # every sampling in both modes, grayscale, ragged sizes and the full image
+    for i, (hy, vy) in enumerate(SAMPLINGS):
+        for w, h in SIZES + [(65, 9)]:
+            fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 2)}
+            coef, qt = _case(500 * i + w + scale, fr)
+            for mode in ("simple", "fancy"):
+                say(f"1/{scale} {hy}x{vy} {w}x{h} {mode}")
+                cd = torch.from_numpy(coef.reshape(-1)).cuda()
+                qd = torch.from_numpy(qt.view(np.int16).reshape(-1)).cuda()
+                got = M.decode_variant(ctx, fr, cd, qd, "islow", mode, scale=scale).cpu().numpy()
+                exp = V.decode_variant(fr, coef, qt, "islow", mode, scale)
+                assert np.array_equal(got, exp), (scale, hy, vy, w, h, mode)
+    for w, h in ((257, 190), (1, 1), (65535, 9)):
+        fr = {"width": w, "height": h, "ncomp": 1, "h": (1, 1, 1), "v": (1, 1, 1), "qsel": (1, 0, 0)}
+        coef, qt = _case(w * scale, fr)
+        say(f"1/{scale} grayscale {w}x{h}")
+        cd = torch.from_numpy(coef.reshape(-1)).cuda()
+        qd = torch.from_numpy(qt.view(np.int16).reshape(-1)).cuda()
+        got = M.decode_variant(ctx, fr, cd, qd, "islow", ncomp=1, scale=scale).cpu().numpy()
+        assert np.array_equal(got, V.decode_variant(fr, coef, qt, "islow", scale=scale))
+    from synth import workloads
+    frame, coef, qt = workloads.large_420_fancy()
+    say(f"1/{scale} 4096x3072 4:2:0 fancy")
+    cd = torch.from_numpy(coef.reshape(-1)).cuda()
+    qd = torch.from_numpy(qt.view(np.int16).reshape(-1)).cuda()
+    got = M.decode_variant(ctx, frame, cd, qd, "islow", "fancy", scale=scale).cpu().numpy()
+    assert np.array_equal(got, V.decode_variant(frame, coef, qt, "islow", "fancy", scale))
+
+
 @pytest.mark.parametrize("method", V.IDCT_METHODS)
 def test_full_size_image(M, ctx, method):
     from synth import workloads

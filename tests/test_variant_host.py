@@ -24,9 +24,17 @@ def test_geometry_matches_oracle(M, w, h, hy, vy):
     for k in ("mcu_w", "mcu_h", "mcus_x", "mcus_y", "blocks_per_mcu", "n_blocks"):
         assert g[k] == o[k], k
     assert g["comp_w"] == o["comp_w"] and g["comp_h"] == o["comp_h"]
-    # the three sample planes, each a whole block grid, 256-byte aligned
-    need = sum(-(-(o["grid_w"][c] * 8 * o["grid_h"][c] * 8) // 256) * 256 for c in range(3))
-    assert wb == need
+    # the three sample planes, each a whole block grid with rows padded to 16
+    # bytes, 256-byte aligned; at 1/s scale blocks of 8/s samples
+    for s in (1, 2, 4, 8):
+        g, wb = M.mjd_variant_geometry(M.make_variant(fr, 3, "islow", "fancy", s))
+        n = 8 // s
+        need = sum(-(-((o["grid_w"][c] * n + 15) // 16 * 16 * o["grid_h"][c] * n) // 256) * 256 for c in range(3))
+        assert wb == need
+        assert g["comp_w"] == [-(-x // s) for x in o["comp_w"]] and g["comp_h"] == [-(-x // s) for x in o["comp_h"]]
+    with pytest.raises(M.MjdError) as e:  # the reduced transforms are islow-style only
+        M.mjd_variant_geometry(M.make_variant(fr, 3, "float", "fancy", 2))
+    assert e.value.code == -2
 
 
 @pytest.mark.parametrize("w,h", [(29, 19), (8, 8), (1, 1), (65535, 3)])
@@ -43,7 +51,7 @@ def test_bad_variants_are_refused(M):
     fr = {"width": 64, "height": 64, "h": (2, 1, 1), "v": (2, 1, 1), "qsel": (0, 1, 1)}
     ok = M.make_variant(fr)
     M.mjd_variant_geometry(ok)
-    for field, value in (("ncomp", 2), ("idct", 3), ("upsample", 9), ("reserved", 1)):
+    for field, value in (("ncomp", 2), ("idct", 3), ("upsample", 9), ("scale", 3)):
         bad = M.make_variant(fr)
         setattr(bad, field, value)
         with pytest.raises(M.MjdError):
