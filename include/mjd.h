@@ -331,7 +331,8 @@ typedef struct mjd_scan {
  * Returns MJD_ECORRUPT for malformed or truncated streams and
  * MJD_EUNSUPPORTED for valid JPEG this library does not decode
  * (progressive, arithmetic, 12-bit, not three components, sampling other
- * than 4:4:4 / 4:2:2 / 4:2:0, more than one scan).  Reads only
+ * than 4:4:4 / 4:2:2 / 4:2:0 and the variant samplings h1v2 / 4:1:1,
+ * which only mjd_decode_variant decodes; more than one scan).  Reads only
  * [h_jpg, h_jpg + len). */
 int mjd_parse(const uint8_t* h_jpg, size_t len, mjd_scan* scan, uint16_t h_qt[4][64]);
 

@@ -79,7 +79,7 @@ def entropy_decode(jpg, n_threads: int = 1, out=None):
 
     scan, qt = mjd_parse(jpg)
     frame = scan_frame(scan)
-    g = mjd_geometry_of(frame)
+    g, _ = mjd_variant_geometry(make_variant(frame))  # also the variant samplings h1v2 and 4:1:1
     off = mjd_restart_index(jpg, scan)
     coef = np.empty((g["n_blocks"], 64), dtype=np.int16) if out is None else out
     mjd_entropy_decode(jpg, scan, off, coef, 0, g["mcus_y"], n_threads)

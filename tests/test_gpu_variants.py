@@ -181,6 +181,34 @@ def test_scaled_decoding_matches_oracle(M, ctx, scale):
     assert np.array_equal(got, V.decode_variant(frame, coef, qt, "islow", "fancy", scale))
 
 
+def test_variant_bitstreams_decode_on_the_device(M, ctx):
+    # h1v2 and 4:1:1 bitstreams: the GPU entropy kernel returns the encoded
+    # coefficients, and the variants path turns them into the oracle's RGB
+    from synth import bitstream
+    rng = np.random.default_rng(61)
+    for hy, vy in ((1, 2), (4, 1)):
+        for w, h, ri in ((97, 61, 4), (640, 480, 32)):
+            fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 1)}
+            coef, qt = _case(w + hy, fr)
+            coef[rng.random(coef.shape) < 0.5] = 0
+            coef = np.clip(coef, -1023, 1023)  # baseline ranges: AC and DC-difference categories
+            data = bitstream.write_jpeg(fr, coef, qt, restart_interval=ri)
+            scan, q = M.mjd_parse(data)
+            off = M.mjd_restart_index(data, scan)
+            d_jpg = torch.zeros(-(-len(data) // 16) * 16, dtype=torch.uint8, device="cuda")
+            d_jpg[:len(data)] = torch.from_numpy(np.frombuffer(data, dtype=np.uint8).copy()).cuda()
+            d_coef = torch.full((coef.size,), 0x5A5A, dtype=torch.int16, device="cuda")
+            say(f"bitstream {hy}x{vy} {w}x{h} ri={ri}")
+            b = M.EntropyBatch(ctx, [(scan, off, d_jpg, len(data), d_coef)])
+            b.launch()
+            assert b.status() == -1
+            b.close()
+            assert np.array_equal(d_coef.cpu().numpy().reshape(-1, 64), coef)
+            qd = torch.from_numpy(q.view(np.int16).reshape(-1)).cuda()
+            got = M.decode_variant(ctx, M.scan_frame(scan), d_coef, qd, "islow", "fancy").cpu().numpy()
+            assert np.array_equal(got, V.decode_variant(fr, coef, qt, "islow", "fancy"))
+
+
 @pytest.mark.parametrize("method", V.IDCT_METHODS)
 def test_full_size_image(M, ctx, method):
     from synth import workloads

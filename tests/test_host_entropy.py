@@ -119,6 +119,29 @@ def test_corrupt_and_truncated_streams_fail_cleanly(M):
             assert e.code in (-5, -1)
 
 
+@pytest.mark.parametrize("hy,vy", [(1, 2), (4, 1)])
+@pytest.mark.parametrize("ri", [0, 2, 5])
+def test_variant_samplings_decode_to_the_encoded_coefficients(M, hy, vy, ri):
+    # h1v2 and 4:1:1 streams: the parser and the threaded decoder return the
+    # coefficients the writer encoded; the fused decoder refuses the frame
+    import oracle.variants as V
+    rng = np.random.default_rng(hy * 10 + vy + ri)
+    for w, h in ((45, 35), (8, 8), (97, 61)):
+        fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 1)}
+        n = V.variant_geometry(fr)["n_blocks"]
+        coef = rng.integers(-30, 31, (n, 64)).astype(np.int16)
+        coef[:, 0] = rng.integers(-500, 501, n)
+        coef[rng.random((n, 64)) < 0.6] = 0
+        qt = rng.integers(1, 50, (4, 64)).astype(np.uint16)
+        data = bitstream.write_jpeg(fr, coef, qt, restart_interval=ri)
+        f, c, q = M.entropy_decode(data, n_threads=3)
+        assert (f["h"], f["v"]) == ((hy, 1, 1), (vy, 1, 1))
+        assert np.array_equal(c, coef.reshape(c.shape))
+        with pytest.raises(M.MjdError) as ei:
+            M.mjd_geometry_of(f)
+        assert ei.value.code == -2
+
+
 def test_unsupported_streams(M):
     frame, coef, qt, data = _stream(16, 16, "444", 75, 0)
     bad = bytearray(data)
