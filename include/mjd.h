@@ -318,7 +318,9 @@ typedef struct mjd_scan {
   uint64_t data_end;         /* byte offset of the EOI marker */
   uint8_t dc_sel[3];         /* DC Huffman table per component (0..3) */
   uint8_t ac_sel[3];         /* AC Huffman table per component (0..3) */
-  uint8_t reserved[2];
+  uint8_t ncomp;             /* 3, or 1 for a grayscale frame (component 0 only, one block per MCU,
+                                frame h/v 1x1; decode it with mjd_decode_variant, ncomp 1) */
+  uint8_t reserved;
   mjd_huffman dc[4];
   mjd_huffman ac[4];
 } mjd_scan;
@@ -330,9 +332,10 @@ typedef struct mjd_scan {
  *         not define are all ones).
  * Returns MJD_ECORRUPT for malformed or truncated streams and
  * MJD_EUNSUPPORTED for valid JPEG this library does not decode
- * (progressive, arithmetic, 12-bit, not three components, sampling other
- * than 4:4:4 / 4:2:2 / 4:2:0 and the variant samplings h1v2 / 4:1:1,
- * which only mjd_decode_variant decodes; more than one scan).  Reads only
+ * (progressive, arithmetic, 12-bit, neither three components nor one,
+ * sampling other than 4:4:4 / 4:2:2 / 4:2:0 and the variant samplings
+ * h1v2 / 4:1:1, which only mjd_decode_variant decodes like grayscale; more
+ * than one scan).  Reads only
  * [h_jpg, h_jpg + len). */
 int mjd_parse(const uint8_t* h_jpg, size_t len, mjd_scan* scan, uint16_t h_qt[4][64]);
 

@@ -27,6 +27,8 @@ def decode(ctx: Context, frame, coef, qt, mode: str = "fancy", out=None, rows=No
     torch.uint8 CUDA tensor [H, W, 3] (contiguous).  Returns `out`."""
     import torch
 
+    if frame.get("ncomp", 3) != 3:
+        raise ValueError("grayscale frames decode with decode_variant(..., ncomp=1)")
     g = mjd_geometry_of(frame)
     if coef.numel() != g["n_blocks"] * 64 or coef.element_size() != 2 or not coef.is_cuda:
         raise ValueError("coef must be a CUDA int16 tensor of n_blocks*64 elements")
@@ -79,7 +81,7 @@ def entropy_decode(jpg, n_threads: int = 1, out=None):
 
     scan, qt = mjd_parse(jpg)
     frame = scan_frame(scan)
-    g, _ = mjd_variant_geometry(make_variant(frame))  # also the variant samplings h1v2 and 4:1:1
+    g, _ = mjd_variant_geometry(make_variant(frame, frame.get("ncomp", 3)))  # also h1v2, 4:1:1, grayscale
     off = mjd_restart_index(jpg, scan)
     coef = np.empty((g["n_blocks"], 64), dtype=np.int16) if out is None else out
     mjd_entropy_decode(jpg, scan, off, coef, 0, g["mcus_y"], n_threads)

@@ -72,7 +72,8 @@ class mjd_huffman(ctypes.Structure):
 class mjd_scan(ctypes.Structure):
     _fields_ = [("frame", mjd_frame), ("restart_interval", ctypes.c_uint32), ("n_intervals", ctypes.c_uint32),
                 ("data_offset", ctypes.c_uint64), ("data_end", ctypes.c_uint64),
-                ("dc_sel", ctypes.c_uint8 * 3), ("ac_sel", ctypes.c_uint8 * 3), ("reserved", ctypes.c_uint8 * 2),
+                ("dc_sel", ctypes.c_uint8 * 3), ("ac_sel", ctypes.c_uint8 * 3), ("ncomp", ctypes.c_uint8),
+                ("reserved", ctypes.c_uint8),
                 ("dc", mjd_huffman * 4), ("ac", mjd_huffman * 4)]
 
 
@@ -648,8 +649,12 @@ class Hetero:
 
 
 def scan_frame(scan: mjd_scan) -> dict:
+    """The frame of a parsed scan; grayscale frames carry "ncomp": 1."""
     f = scan.frame
-    return {"width": f.width, "height": f.height, "h": tuple(f.h), "v": tuple(f.v), "qsel": tuple(f.qsel)}
+    d = {"width": f.width, "height": f.height, "h": tuple(f.h), "v": tuple(f.v), "qsel": tuple(f.qsel)}
+    if scan.ncomp == 1:
+        d["ncomp"] = 1
+    return d
 
 
 class Pipeline:

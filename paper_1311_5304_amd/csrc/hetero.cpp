@@ -118,6 +118,7 @@ int mjd_hetero_decode(mjd_hetero* h, const uint8_t* h_jpg, size_t len, int upsam
   uint16_t qt[4][64];
   int rc = mjd::host::parse(h_jpg, len, &scan, qt);
   if (rc != MJD_OK) return rc;
+  if (scan.ncomp != 3) return mjd::fail(MJD_EUNSUPPORTED, "grayscale stream (mjd_decode_variant decodes it)");
   mjd_geometry g;
   rc = mjd::frame_geometry(&scan.frame, &g);
   if (rc != MJD_OK) return rc;

@@ -255,6 +255,7 @@ struct Run {
     if (!jpg || !rgb) return bad(fail(MJD_EINVAL, "null bitstream or output pointer"));
     int rc = host::parse(jpg, len, &im.scan, im.qt);
     if (rc != MJD_OK) return bad(rc);
+    if (im.scan.ncomp != 3) return bad(fail(MJD_EUNSUPPORTED, "grayscale stream (mjd_decode_variant decodes it)"));
     if ((rc = frame_geometry(&im.scan.frame, &im.g)) != MJD_OK) return bad(rc);
     const uint32_t W = im.scan.frame.width, H = im.scan.frame.height;
     if (im.g.n_blocks > p->cfg.max_blocks || static_cast<uint64_t>(W) * H > p->cfg.max_pixels)

@@ -155,8 +155,11 @@ def build_tables(dc_counts, ac_counts):
 
 
 def headers(frame: dict, qt: np.ndarray, tables, restart_interval: int) -> bytearray:
-    """SOI, DQT, SOF0, DHT, optional DRI and SOS: everything before the entropy-coded data."""
-    hs, vs, qsel = frame["h"], frame["v"], frame["qsel"]
+    """SOI, DQT, SOF0, DHT, optional DRI and SOS: everything before the
+    entropy-coded data.  frame["ncomp"] == 1 writes a grayscale frame (one
+    component, sampling 1x1, one non-interleaved scan)."""
+    nc = frame.get("ncomp", 3)
+    hs, vs, qsel = (frame["h"], frame["v"], frame["qsel"]) if nc == 3 else ((1,), (1,), tuple(frame["qsel"][:1]))
     tbl = LUMA_CHROMA_TABLES
     out = bytearray(b"\xFF\xD8")
     for slot in sorted(set(qsel)):
@@ -164,16 +167,16 @@ def headers(frame: dict, qt: np.ndarray, tables, restart_interval: int) -> bytea
         if zz.max() > 255 or zz.min() < 1:
             raise ValueError("baseline quant tables need entries in 1..255")
         out += _segment(0xDB, bytes([slot]) + bytes(int(v) for v in zz))
-    sof = struct.pack(">BHHB", 8, frame["height"], frame["width"], 3)
-    for c in range(3):
+    sof = struct.pack(">BHHB", 8, frame["height"], frame["width"], nc)
+    for c in range(nc):
         sof += bytes([c + 1, (hs[c] << 4) | vs[c], qsel[c]])
     out += _segment(0xC0, sof)
     for cls, t, bits, vals in tables:
         out += _segment(0xC4, bytes([(cls << 4) | t]) + bytes(bits) + bytes(vals))
     if restart_interval:
         out += _segment(0xDD, struct.pack(">H", restart_interval))
-    sos = bytes([3])
-    for c in range(3):
+    sos = bytes([nc])
+    for c in range(nc):
         sos += bytes([c + 1, (tbl[c] << 4) | tbl[c]])
     sos += bytes([0, 63, 0])
     out += _segment(0xDA, sos)
@@ -181,14 +184,15 @@ def headers(frame: dict, qt: np.ndarray, tables, restart_interval: int) -> bytea
 
 
 def write_jpeg(frame: dict, coef: np.ndarray, qt: np.ndarray, restart_interval: int = 0) -> bytes:
-    hs, vs, qsel = frame["h"], frame["v"], frame["qsel"]
+    nc = frame.get("ncomp", 3)
+    hs, vs = (frame["h"], frame["v"]) if nc == 3 else ((1,), (1,))
     hmax, vmax = max(hs), max(vs)
     mx = -(-frame["width"] // (8 * hmax))
     my = -(-frame["height"] // (8 * vmax))
     bpm = sum(h * v for h, v in zip(hs, vs))
     n_mcu = mx * my
     coef = np.asarray(coef, dtype=np.int16).reshape(n_mcu, bpm, 64)
-    comp_of = [c for c in range(3) for _ in range(hs[c] * vs[c])]
+    comp_of = [c for c in range(nc) for _ in range(hs[c] * vs[c])]
     tbl = LUMA_CHROMA_TABLES
 
     # pass 1: tokens and symbol statistics

@@ -207,6 +207,28 @@ def test_variant_bitstreams_decode_on_the_device(M, ctx):
             qd = torch.from_numpy(q.view(np.int16).reshape(-1)).cuda()
             got = M.decode_variant(ctx, M.scan_frame(scan), d_coef, qd, "islow", "fancy").cpu().numpy()
             assert np.array_equal(got, V.decode_variant(fr, coef, qt, "islow", "fancy"))
+    # grayscale: one component, one block per MCU
+    for w, h, ri in ((97, 61, 3), (640, 480, 40)):
+        fr = {"width": w, "height": h, "ncomp": 1, "h": (1, 1, 1), "v": (1, 1, 1), "qsel": (1, 1, 1)}
+        coef, qt = _case(w + 7, fr)
+        coef[rng.random(coef.shape) < 0.5] = 0
+        coef = np.clip(coef, -1023, 1023)
+        data = bitstream.write_jpeg(fr, coef, qt, restart_interval=ri)
+        scan, q = M.mjd_parse(data)
+        off = M.mjd_restart_index(data, scan)
+        d_jpg = torch.zeros(-(-len(data) // 16) * 16, dtype=torch.uint8, device="cuda")
+        d_jpg[:len(data)] = torch.from_numpy(np.frombuffer(data, dtype=np.uint8).copy()).cuda()
+        d_coef = torch.full((coef.size,), 0x5A5A, dtype=torch.int16, device="cuda")
+        say(f"grayscale bitstream {w}x{h} ri={ri}")
+        b = M.EntropyBatch(ctx, [(scan, off, d_jpg, len(data), d_coef)])
+        b.launch()
+        assert b.status() == -1
+        b.close()
+        assert np.array_equal(d_coef.cpu().numpy().reshape(-1, 64), coef)
+        qd = torch.from_numpy(q.view(np.int16).reshape(-1)).cuda()
+        for method in V.IDCT_METHODS:
+            got = M.decode_variant(ctx, M.scan_frame(scan), d_coef, qd, method, ncomp=1).cpu().numpy()
+            assert np.array_equal(got, V.decode_variant(fr, coef, qt, method))
 
 
 @pytest.mark.parametrize("method", V.IDCT_METHODS)

@@ -142,6 +142,25 @@ def test_variant_samplings_decode_to_the_encoded_coefficients(M, hy, vy, ri):
         assert ei.value.code == -2
 
 
+@pytest.mark.parametrize("ri", [0, 1, 7])
+def test_grayscale_streams_decode_to_the_encoded_coefficients(M, ri):
+    import oracle.variants as V
+    rng = np.random.default_rng(70 + ri)
+    for w, h in ((45, 35), (8, 8), (1, 1), (130, 9)):
+        fr = {"width": w, "height": h, "ncomp": 1, "h": (1, 1, 1), "v": (1, 1, 1), "qsel": (2, 2, 2)}
+        n = V.variant_geometry(fr)["n_blocks"]
+        coef = rng.integers(-40, 41, (n, 64)).astype(np.int16)
+        coef[:, 0] = rng.integers(-900, 901, n)
+        coef[rng.random((n, 64)) < 0.5] = 0
+        qt = rng.integers(1, 50, (4, 64)).astype(np.uint16)
+        data = bitstream.write_jpeg(fr, coef, qt, restart_interval=ri)
+        scan, q = M.mjd_parse(data)
+        assert scan.ncomp == 1 and scan.n_intervals == (-(-n // ri) if ri else 1)
+        f, c, q = M.entropy_decode(data, n_threads=3)
+        assert f["ncomp"] == 1 and f["qsel"][0] == 2
+        assert np.array_equal(c, coef.reshape(c.shape)) and np.array_equal(q[2], qt[2])
+
+
 def test_unsupported_streams(M):
     frame, coef, qt, data = _stream(16, 16, "444", 75, 0)
     bad = bytearray(data)
@@ -171,8 +190,15 @@ def test_reads_libjpeg_written_files(M):
     with pytest.raises(M.MjdError) as ei:
         M.mjd_parse(b.getvalue())
     assert ei.value.code == -2
+    # a libjpeg-written grayscale file: one component, one block per MCU;
+    # its coefficients through the variant oracle land within a level of
+    # libjpeg's own decode (the IDCT factorisations differ)
+    import oracle.variants as V
     b = io.BytesIO()
     Image.fromarray(rgb[..., 0]).save(b, "JPEG", quality=80)
-    with pytest.raises(M.MjdError) as ei:
-        M.mjd_parse(b.getvalue())
-    assert ei.value.code == -2
+    f, c, q = M.entropy_decode(b.getvalue(), n_threads=2)
+    assert f.get("ncomp") == 1 and c.shape == (-(-97 // 8) * -(-61 // 8), 64)
+    ours = V.decode_variant(f, c, q, "islow").astype(np.int64)
+    theirs = np.asarray(Image.open(io.BytesIO(b.getvalue()))).astype(np.int64)
+    assert ours.shape == theirs.shape == (61, 97)
+    assert np.abs(ours - theirs).max() <= 1
