@@ -210,7 +210,9 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
 /* Heterogeneous decode of one bitstream (paper Sec. 5.2): the GPU decodes
  * the image's first MCU rows while host threads decode the rest, as a
  * partition (mjd_partition_rows) assigns them.  Owns pinned coefficient
- * staging, device buffers for the largest image and a stream. */
+ * staging, device buffers for the largest image, a stream and a pool of
+ * host threads; calls on one decoder must not overlap (use one decoder per
+ * calling thread). */
 typedef struct mjd_hetero mjd_hetero;
 
 /* Seconds spent in each part of one mjd_hetero_decode, on the host clock. */

@@ -26,6 +26,7 @@
 // reduced size.
 #include <math.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "mjd_internal.h"
@@ -530,12 +531,14 @@ __global__ __launch_bounds__(256) void var_colour(const View v) {
 // tiles), or about one per tile when there are fewer.
 template <int M>
 hipError_t launch_idct(const View& v, const Consts& k, uint64_t n_tiles, int cu_count, hipStream_t s) {
-  static int per_cu = 0;
+  static std::atomic<int> cached{0};  // resident workgroups per CU (the same on every gfx950 device)
+  int per_cu = cached.load(std::memory_order_relaxed);
   if (per_cu == 0) {
     int n = 0;
     const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, var_idct<M>, kThreads, 0);
     if (e != hipSuccess) return e;
     per_cu = n > 0 ? n : 1;
+    cached.store(per_cu, std::memory_order_relaxed);
   }
   // a multiple of 8, at most the resident slots and about one tile each
   const uint64_t slots = (static_cast<uint64_t>(per_cu) * (cu_count > 0 ? cu_count : 256)) & ~7ull;
