@@ -108,7 +108,6 @@ struct View {
   uint32_t plane_pitch[3];
   uint32_t pitch;
   int width, height, ncomp, hy, vy, mcus_x, bpm, fancy, aligned_out;
-  int n;  // samples per block side in the planes (8, or 8 / scale)
   int qsel[3];
   int comp_w, comp_h;  // the chroma components' true size
 };
@@ -651,7 +650,6 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   v.pitch = static_cast<uint32_t>(pitch);
   v.width = static_cast<int>(out_w);
   v.height = static_cast<int>(out_h);
-  v.n = static_cast<int>(8 / scale);
   v.ncomp = nc;
   v.hy = nc == 3 ? variant->frame.h[0] : 1;
   v.vy = nc == 3 ? variant->frame.v[0] : 1;
