@@ -31,7 +31,8 @@ def ctx(M):
     c.close()
 
 
-SPECS = [(257, 190, "420", 85, 4), (333, 47, "422", 90, 0), (100, 121, "444", 60, 3), (640, 480, "420", 75, 32)]
+SPECS = [(257, 190, "420", 85, 4), (333, 47, "422", 90, 0), (100, 121, "444", 60, 3), (640, 480, "420", 75, 32),
+         (1, 1, "420", 80, 0), (17, 300, "422", 70, 1)]
 
 
 def _streams():

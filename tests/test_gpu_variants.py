@@ -231,6 +231,34 @@ def test_variant_bitstreams_decode_on_the_device(M, ctx):
             assert np.array_equal(got, V.decode_variant(fr, coef, qt, method))
 
 
+def test_mixed_sampling_entropy_batch(M, ctx):
+    # one GPU entropy launch over 4:2:0, h1v2, 4:1:1 and grayscale streams:
+    # every job's coefficients come back as encoded
+    from synth import bitstream
+    rng = np.random.default_rng(83)
+    jobs, want = [], []
+    for i, (hy, vy, nc) in enumerate(((2, 2, 3), (1, 2, 3), (4, 1, 3), (1, 1, 1), (2, 2, 3))):
+        w, h = (131 + 40 * i, 77 + 13 * i)
+        fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 1), "ncomp": nc}
+        coef, qt = _case(900 + i, fr)
+        coef[rng.random(coef.shape) < 0.5] = 0
+        coef = np.clip(coef, -1023, 1023)
+        data = bitstream.write_jpeg(fr, coef, qt, restart_interval=(0, 3, 8, 1, 64)[i])
+        scan, _ = M.mjd_parse(data)
+        off = M.mjd_restart_index(data, scan)
+        d_jpg = torch.zeros(-(-len(data) // 16) * 16, dtype=torch.uint8, device="cuda")
+        d_jpg[:len(data)] = torch.from_numpy(np.frombuffer(data, dtype=np.uint8).copy()).cuda()
+        jobs.append((scan, off, d_jpg, len(data), torch.full((coef.size,), 0x5A5A, dtype=torch.int16, device="cuda")))
+        want.append(coef)
+    say("mixed-sampling entropy batch")
+    b = M.EntropyBatch(ctx, jobs)
+    b.launch()
+    assert b.status() == -1
+    b.close()
+    for j, coef in zip(jobs, want):
+        assert np.array_equal(j[4].cpu().numpy().reshape(-1, 64), coef)
+
+
 @pytest.mark.parametrize("method", V.IDCT_METHODS)
 def test_full_size_image(M, ctx, method):
     from synth import workloads
