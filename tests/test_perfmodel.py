@@ -357,3 +357,17 @@ def test_fit_recovers_host_parts_against_rows(M):
         assert math.isclose(got, 3e-4 + 4e-3 * w * x / 2 ** 20, rel_tol=1e-8)
     back = perfmodel.from_dict(perfmodel.to_dict(model))
     assert back.p_cpu.degree == 2 and math.isclose(back.t_dispatch.c[0], 5e-5, rel_tol=1e-9)
+
+
+def test_pps_with_a_whole_image_chunk_is_the_overlapped_scheme(M):
+    # c = min(chunk, h - x) = h - x when chunk >= h, so the CPU's Huffman term
+    # T_huff(w, h - c) becomes T_huff(w, x): exactly the overlapped scheme
+    for rates in ((2e-3, 2e-3, 1e-5, 5e-10), (1e-3, 3e-3, 1e-5, 2e-9), (4e-3, 1e-3, 2e-5, 1e-9)):
+        m, o = _model_pair(M, *rates)
+        for w, h, mh in ((4096, 3072, 16), (1000, 777, 16)):
+            a = M.mjd_partition_rows(m, M.MJD_PART_PPS, w, h, mh, w * h // 3, 4.0, h)
+            b = M.mjd_partition_rows(m, M.MJD_PART_OVERLAP, w, h, mh, w * h // 3, 4.0)
+            assert a["cpu_rows"] == b["cpu_rows"] and math.isclose(a["x"], b["x"], rel_tol=1e-9, abs_tol=1e-9)
+            for x in (0.0, h / 3, h - 1.0):
+                assert all(math.isclose(p, q, rel_tol=1e-12, abs_tol=1e-15) for p, q in
+                           zip(O.sides(o, "pps", w, h, w * h // 3, 4.0, x, h), O.sides(o, "overlap", w, h, w * h // 3, 4.0, x)))
