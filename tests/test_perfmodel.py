@@ -371,3 +371,15 @@ def test_pps_with_a_whole_image_chunk_is_the_overlapped_scheme(M):
             for x in (0.0, h / 3, h - 1.0):
                 assert all(math.isclose(p, q, rel_tol=1e-12, abs_tol=1e-15) for p, q in
                            zip(O.sides(o, "pps", w, h, w * h // 3, 4.0, x, h), O.sides(o, "overlap", w, h, w * h // 3, 4.0, x)))
+
+
+def test_repartition_with_nothing_left_to_decode_is_sps_on_the_remainder(M):
+    # no Huffman data left (u = 0) and an idle GPU: Eq. 16 is Eq. 10 on the
+    # remaining rows
+    for rates in ((2e-3, 2e-3, 1e-5, 5e-10), (1e-3, 3e-3, 1e-5, 2e-9)):
+        m, _ = _model_pair(M, *rates)
+        for r in (3072, 1000, 480):
+            a = M.mjd_repartition_rows(m, 4096, 3072, r, 16, 4096 * 3072 // 3, 4.0, 0, 0.0, 0.0)
+            b = M.mjd_partition_rows(m, M.MJD_PART_SPS, 4096, r, 16, 4096 * r // 3, 4.0)
+            assert a["cpu_rows"] == b["cpu_rows"] and math.isclose(a["x"], b["x"], rel_tol=1e-9, abs_tol=1e-9)
+            assert math.isclose(a["t_cpu"], b["t_cpu"], rel_tol=1e-12) and math.isclose(a["t_gpu"], b["t_gpu"], rel_tol=1e-12)
