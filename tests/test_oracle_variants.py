@@ -267,3 +267,82 @@ def test_scaled_output_sizes():
         V.planes(fr, c, qt, "ifast", 2)
     with pytest.raises(ValueError):
         V.planes(fr, c, qt, "islow", 3)
+
+
+# ---- ifast: constants, multipliers and bias ----------------------------------------------
+
+
+def _graph_response(mul, amplitude):
+    """8x8 matrix E[n][k]: the 1-D graph's output n for an impulse of the
+    given amplitude at input k, divided by the amplitude."""
+    E = np.zeros((8, 8))
+    for k in range(8):
+        Y = [np.array([0], dtype=np.int64) for _ in range(8)]
+        Y[k] = np.array([amplitude], dtype=np.int64)
+        out = V.aan_1d(Y, mul, V._ifast_add, V._ifast_sub)
+        E[:, k] = [int(o[0]) / amplitude for o in out]
+    return E
+
+
+def test_ifast_graph_constants_are_the_nearest_9_bit_roundings():
+    # Every path of the transposed AAN graph crosses at most one constant
+    # multiply, so its impulse response is M0 + sum_j (K_j / 2^9) M_j with
+    # integer structure matrices.  Recover the four K_j from the fixed-point
+    # graph's behaviour at a large amplitude (truncation below 2^-10) and
+    # check each against the real constant: only the correctly rounded
+    # integer lies within 1/2, so a constant one LSB off fails.
+    names = ("r", "c5", "c2", "c4")
+    real = {"r": V.C_R, "c5": V.C_5, "c2": V.C_2, "c4": V.C_4}
+    structure = {}
+    for j in names + (None,):
+        structure[j] = np.array([[float(v) for v in col] for col in
+                                 [V.aan_1d([1.0 if i == k else 0.0 for i in range(8)],
+                                           lambda v, name, j=j: v if name == j else 0.0) for k in range(8)]]).T
+    M0 = structure[None]
+    for j in names:
+        structure[j] = structure[j] - M0   # the terms through constant j alone
+    E = _graph_response(V._ifast_mul, 1 << 20)
+    A = np.stack([structure[j].ravel() for j in names], axis=1)
+    k, *_ = np.linalg.lstsq(A, (E - M0).ravel(), rcond=None)
+    K = k * (1 << V.IFAST_CONST_BITS)
+    resid = np.abs(A @ k - (E - M0).ravel()).max()
+    assert resid < 1e-5
+    for j, kj in zip(names, K):
+        assert abs(kj - round(kj)) < 1e-3, (j, kj)
+        assert abs(round(kj) - real[j] * (1 << V.IFAST_CONST_BITS)) < 0.5, (j, kj)
+
+
+def test_ifast_multipliers_round_the_scaled_table():
+    # M(u, v) approximates q * 2^6 / (s(u) s(v)) through two roundings (the
+    # 14-bit table entry, then the product to 6 fraction bits); at q = 256
+    # the second is exact, so M is the table entry itself
+    exact = np.array([[(1 << 14) / (V.S[u] * V.S[v]) for v in range(8)] for u in range(8)])
+    a = V.ifast_multipliers(np.full(64, 256, np.uint16)).reshape(8, 8)
+    assert np.all(np.abs(a - exact) <= 0.5)
+    for qv in (1, 7, 99, 255):
+        m = V.ifast_multipliers(np.full(64, qv, np.uint16)).reshape(8, 8)
+        assert np.all(np.abs(m - qv * exact / 256) <= 0.5 + qv * 0.5 / 256 + 1e-9)
+    # the DC multiplier is exact: q * 2^6
+    for qv in range(1, 256):
+        assert V.ifast_multipliers(np.full(64, qv, np.uint16)).reshape(64)[0] == qv << 6
+
+
+def test_ifast_per_position_error_is_unbiased_on_photographic_blocks():
+    # IEEE-1180-style statistics against the FP64 IDCT on encoded texture
+    # blocks (quality 50, 75, 90), over samples away from the clamp: per
+    # position, the mean signed error and the mean squared error stay small
+    # (a wrong rounding bias shifts every mean by about 1/2)
+    from synth import encode, images
+    errs = []
+    for seed, qual in ((21, 75), (22, 50), (23, 90)):
+        frame, coef, qt = encode.encode_rgb(images.texture_rgb(256, 192, seed, sigma=12), "444", qual)
+        c = np.asarray(coef).reshape(-1, 3, 64)
+        for comp in range(3):
+            q = qt[frame["qsel"][comp]]
+            ex = exact_idct(c[:, comp], q) + 128
+            e = V.idct_ifast(c[:, comp], q).astype(np.float64) - np.clip(np.floor(ex + 0.5), 0, 255)
+            e[(ex < 0.5) | (ex > 254.5)] = np.nan
+            errs.append(e)
+    e = np.concatenate(errs)
+    assert np.nanmax(np.abs(np.nanmean(e, axis=0))) < 0.05
+    assert np.nanmax(np.nanmean(e * e, axis=0)) < 0.06
