@@ -332,7 +332,8 @@ typedef struct mjd_scan {
  * frame order (Ss=0, Se=63, Ah=Al=0), EOI; APPn and COM are skipped.
  *   h_qt: receives uint16[4][64] in natural order (tables the stream does
  *         not define are all ones).
- * Returns MJD_ECORRUPT for malformed or truncated streams and
+ * Returns MJD_ECORRUPT for malformed or truncated streams (a 16-bit DQT
+ * table, which T.81 B.2.4.1 allows only in 12-bit frames, included) and
  * MJD_EUNSUPPORTED for valid JPEG this library does not decode
  * (progressive, arithmetic, 12-bit, neither three components nor one,
  * sampling other than 4:4:4 / 4:2:2 / 4:2:0 and the variant samplings

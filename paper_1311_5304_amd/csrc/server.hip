@@ -336,16 +336,21 @@ static void run_continuous(mjd_server* s) {
 static void run_sync(mjd_server* s) {
   for (;;) {
     uint64_t id;
+    Request* qp;
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_work.wait(lk, [&] { return s->stop || s->next_admit < s->reqs.size(); });
       if (s->next_admit >= s->reqs.size()) return;  // stopped, nothing left
       id = s->next_admit;
-      const uint64_t arr = s->reqs[id].r.arrival_ns;
+      // The element is looked up under the lock: a concurrent submit may
+      // grow the deque's map.  References to its elements stay valid across
+      // push_back, so q may be used after the lock is released.
+      qp = &s->reqs[id];
+      const uint64_t arr = qp->r.arrival_ns;
       while (s->now_ns() < arr) s->cv_work.wait_until(lk, s->t0 + std::chrono::nanoseconds(arr));
       ++s->next_admit;
     }
-    Request& q = s->reqs[id];  // stable: deque
+    Request& q = *qp;
     q.off = 0;                 // alone in the arena
     q.t.admit_ns = s->now_ns();
     hipError_t e = copy_in(s, q);

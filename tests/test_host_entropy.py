@@ -202,3 +202,27 @@ def test_reads_libjpeg_written_files(M):
     theirs = np.asarray(Image.open(io.BytesIO(b.getvalue()))).astype(np.int64)
     assert ours.shape == theirs.shape == (61, 97)
     assert np.abs(ours - theirs).max() <= 1
+
+
+def _with_16bit_dqt(data: bytes, value_of=lambda v: v) -> bytes:
+    """The stream with its first DQT table rewritten with Pq = 1 (16-bit
+    entries, big-endian), each entry mapped by value_of."""
+    i = data.index(b"\xFF\xDB")
+    seglen = (data[i + 2] << 8) | data[i + 3]
+    seg = data[i + 4:i + 2 + seglen]
+    tq, vals, rest = seg[0] & 15, seg[1:65], seg[65:]
+    wide = bytes([0x10 | tq]) + b"".join(int(value_of(v)).to_bytes(2, "big") for v in vals)
+    body = wide + rest
+    return data[:i] + b"\xFF\xDB" + (len(body) + 2).to_bytes(2, "big") + body + data[i + 2 + seglen:]
+
+
+def test_16bit_quant_tables_are_refused(M):
+    # T.81 B.2.4.1: Pq = 1 only with 12-bit samples; an 8-bit stream carrying
+    # one is corrupt, whatever its values (small ones included)
+    frame, coef, qt, data = _stream(24, 16, "420", 75, 0)
+    for value_of in (lambda v: v, lambda v: 300 + v):
+        bad = _with_16bit_dqt(data, value_of)
+        assert oracle.parse_and_decode(bad)[0] == frame   # the oracle's reader still parses the layout
+        with pytest.raises(M.MjdError) as ei:
+            M.mjd_parse(bad)
+        assert ei.value.code == -5 and "16-bit" in str(ei.value)
