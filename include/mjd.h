@@ -361,8 +361,13 @@ int mjd_restart_index(const uint8_t* h_jpg, size_t len, const mjd_scan* scan, ui
  * markers the whole scan is one interval.  h_offsets is the output of
  * mjd_restart_index, or NULL to have it computed here.  MJD_ECORRUPT for
  * invalid codes, coefficient runs past the end of a block, or an interval
- * that needs more bits than its data holds; the rows' contents are then
- * unspecified.  Memory-safe for any input bytes. */
+ * that needs more bits than its data holds.  Huffman data cannot be
+ * resynchronised inside an interval (paper Sec. 1: no code word marks a
+ * block boundary), but the next restart marker is a resync point: every
+ * other interval is still decoded, the blocks of a corrupt interval's MCUs
+ * inside the rows are set to zero (mid-grey after the back half), and the
+ * message names the lowest-numbered corrupt interval.  Memory-safe for any
+ * input bytes. */
 int mjd_entropy_decode(const uint8_t* h_jpg, size_t len, const mjd_scan* scan, const uint64_t* h_offsets,
                        int16_t* h_coef, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads);
 

@@ -226,3 +226,57 @@ def test_16bit_quant_tables_are_refused(M):
         with pytest.raises(M.MjdError) as ei:
             M.mjd_parse(bad)
         assert ei.value.code == -5 and "16-bit" in str(ei.value)
+
+
+def _intervals(M, data):
+    scan, _ = M.mjd_parse(data)
+    off = M.mjd_restart_index(data, scan)
+    return scan, [int(o) for o in off]
+
+
+@pytest.mark.parametrize("samp,ri", [("420", 2), ("444", 5), ("422", 1)])
+def test_corrupt_interval_is_cleared_and_the_rest_decodes(M, samp, ri):
+    # Interval k's entropy-coded bytes replaced by all-ones (0xFF stuffed
+    # as 0xFF 0x00): no valid code is sixteen 1-bits, so it is corrupt from
+    # its first code.  The restart marker after it resynchronises the
+    # decoder: every other interval decodes to the encoded coefficients,
+    # interval k's MCUs come back as zero blocks, and MJD_ECORRUPT names k.
+    frame, coef, qt, data = _stream(70, 45, samp, 80, ri, seed=11)
+    scan, off = _intervals(M, data)
+    g = geometry(frame)
+    per_mcu = g["blocks_per_mcu"]
+    n_int = scan.n_intervals
+    for k in sorted({0, n_int // 2, n_int - 1}):
+        bad = bytearray(data)
+        a, b = off[k], off[k + 1] - 2
+        fill = (b"\xFF\x00" * ((b - a) // 2 + 1))[:b - a]
+        if fill.endswith(b"\xFF"):
+            fill = fill[:-1] + b"\x00"
+        bad[a:b] = fill
+        for threads in (1, 3):
+            with pytest.raises(M.MjdError) as ei:
+                M.entropy_decode(bytes(bad), n_threads=threads)
+            assert ei.value.code == -5 and f"interval {k}" in str(ei.value)
+            c = np.full_like(coef.reshape(-1, 64), 0x5A5A)
+            rc_err = None
+            try:
+                M.mjd_entropy_decode(bytes(bad), scan, None, c, 0, g["mcus_y"], threads)
+            except M.MjdError as e:
+                rc_err = e.code
+            assert rc_err == -5
+            want = coef.reshape(-1, 64).copy()
+            m0, m1 = k * ri, min((k + 1) * ri, g["mcus_x"] * g["mcus_y"])
+            want[m0 * per_mcu:m1 * per_mcu] = 0
+            assert np.array_equal(c, want)
+
+
+def test_two_corrupt_intervals_report_the_first(M):
+    frame, coef, qt, data = _stream(64, 48, "420", 80, 1, seed=12)
+    scan, off = _intervals(M, data)
+    bad = bytearray(data)
+    for k in (5, 2):
+        a, b = off[k], off[k + 1] - 2
+        bad[a:b] = (b"\xFF\x00" * (b - a))[:b - a] if (b - a) % 2 == 0 else (b"\xFF\x00" * (b - a))[:b - a - 1] + b"\x00"
+    with pytest.raises(M.MjdError) as ei:
+        M.entropy_decode(bytes(bad), n_threads=4)
+    assert "interval 2" in str(ei.value)
