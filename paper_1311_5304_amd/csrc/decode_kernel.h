@@ -250,6 +250,128 @@ __device__ __forceinline__ void idct_block_regs(const v4i rows[8], const __attri
   }
 }
 
+// --- both passes as int16 dot products ---------------------------------------
+// The row pass can also run on v_dot2_i32_i16 when every pass-1 result fits
+// int16.  That holds whenever every dequantised coefficient lies in
+// [-1024, 1023]: each pass-1 output is a linear form whose weights sum in
+// magnitude to at most 61214, so |sum| < 61214 * 1024 + 1024 < 2^26 and the
+// descaled value (sum >> 11) stays inside +-30607.  A conforming 8-bit
+// stream stays far inside (pass 1 of an exact DCT is bounded by 4096, and
+// quantisation adds at most Q/2 per coefficient).  A wave that holds a block
+// outside that range takes the int32 row pass instead, so the result is the
+// same on the whole documented domain.
+//
+// Scaled pass 1: inputs d' = 16 d (a 16-bit product with 16 Q) and doubled
+// weights give 32 times the pass-1 sum, so its high half is already the
+// descaled value (floor(32 s / 2^16) == floor(s / 2^11)) and one byte
+// permute packs two results as the int16 pair the row pass needs.  Each
+// input carries a bias of 2^14 (d' + 2^14 lies in [0, 2^15) exactly when d
+// lies in [-1024, 1023], so an OR over all pairs tests the range through
+// bits 15 and 31); the bias's contribution to every output is a constant,
+// folded into the first accumulator of each chain.
+constexpr int kInBias = 1 << 14;
+constexpr int kP1ScaledBias = 1 << 15;  // 32 * 2^10
+constexpr uint32_t kInBiasPair = (static_cast<uint32_t>(kInBias) << 16) | static_cast<uint32_t>(kInBias);
+
+// Even part of output k (x0, x4, x2, x6 weights; k = 0..3) and odd part
+// (x1, x3, x5, x7 weights) of the flowgraph's linear form, before doubling.
+constexpr int kEw[4][4] = {
+    {1 << kConstBits, 1 << kConstBits, kE2a, kE6a},
+    {1 << kConstBits, -(1 << kConstBits), kE2b, kE6b},
+    {1 << kConstBits, -(1 << kConstBits), -kE2b, -kE6b},
+    {1 << kConstBits, 1 << kConstBits, -kE2a, -kE6a},
+};
+constexpr int even_corr(int k) {
+  return kP1ScaledBias - kInBias * 2 * (kEw[k][0] + kEw[k][1] + kEw[k][2] + kEw[k][3]);
+}
+constexpr int odd_corr(int k) { return -kInBias * 2 * (kO[k][0] + kO[k][1] + kO[k][2] + kO[k][3]); }
+
+// One column of the scaled pass 1 from biased pairs (x0, x4), (x2, x6),
+// (x1, x3), (x5, x7): y[n] = 32 * (pass-1 sum of output n, rounding bias
+// included), exact in 32 bits (every partial sum stays inside +-2^31).
+template <int K>
+__device__ __forceinline__ void p1_outputs(uint32_t p04, uint32_t p26, uint32_t p13, uint32_t p57, int y[8]) {
+  const int e = dot2(p26, wpair(2 * kEw[K][2], 2 * kEw[K][3]),
+                     dot2(p04, wpair(2 * kEw[K][0], 2 * kEw[K][1]), even_corr(K)));
+  const int o = dot2(p13, wpair(2 * kO[K][0], 2 * kO[K][1]),
+                     dot2(p57, wpair(2 * kO[K][2], 2 * kO[K][3]), odd_corr(K)));
+  y[K] = e + o;
+  y[7 - K] = e - o;
+}
+__device__ __forceinline__ void idct8_p1_scaled(uint32_t p04, uint32_t p26, uint32_t p13, uint32_t p57, int y[8]) {
+  p1_outputs<0>(p04, p26, p13, p57, y);
+  p1_outputs<1>(p04, p26, p13, p57, y);
+  p1_outputs<2>(p04, p26, p13, p57, y);
+  p1_outputs<3>(p04, p26, p13, p57, y);
+}
+
+// Dequantise + 2-D IDCT of one block (Sec. 4.1: columns first, Eq. 1, then
+// rows, Eq. 2) as idct_block_regs computes it, with both passes as dot
+// products when the whole wave's blocks allow it.  q16: the block's 64
+// factors times 16 as 32 dwords of uint16 pairs (LDS, 16-byte aligned).
+__device__ __forceinline__ void idct_block_fast(const v4i rows[8], const __attribute__((address_space(3))) uint32_t* q,
+                                                const __attribute__((address_space(3))) uint32_t* q16,
+                                                uint32_t out[16]) {
+  typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+  uint32_t e[8][4];
+  uint32_t any = 0;
+  {
+    const __attribute__((address_space(3))) v4i* qv = reinterpret_cast<const __attribute__((address_space(3))) v4i*>(q16);
+    const u16x2 bias = __builtin_bit_cast(u16x2, kInBiasPair);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const v4i v = rows[r];
+      const v4i qq = qv[r];
+      const int w[4] = {v.x, v.y, v.z, v.w};
+      const int qw[4] = {qq.x, qq.y, qq.z, qq.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        e[r][i] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, w[i]) * __builtin_bit_cast(u16x2, qw[i]) + bias);
+        any |= e[r][i];
+      }
+    }
+  }
+  if (__builtin_amdgcn_ballot_w64((any & 0x80008000u) != 0) != 0) {
+    idct_block_regs(rows, q, out);
+    return;
+  }
+  // pass 1 by column pairs (0,4), (2,6), (1,3), (5,7): the two columns'
+  // results for sample row n form the pair the row pass reads for row n
+  // (pr[0] (x0, x4), pr[1] (x2, x6), pr[2] (x1, x3), pr[3] (x5, x7)).  The
+  // pairs are formed in the order (0,4), (1,3), (5,7), (2,6), which retires
+  // the input dwords of e[][0], then e[][2], then the rest.
+  uint32_t pr[4][8];
+#pragma unroll
+  for (int step = 0; step < 4; ++step) {
+    const int cp = step == 0 ? 0 : (step == 1 ? 2 : (step == 2 ? 3 : 1));
+    const int ua = cp == 0 ? 0 : (cp == 1 ? 2 : (cp == 2 ? 1 : 5));
+    const int ub = cp == 0 ? 4 : (cp == 1 ? 6 : (cp == 2 ? 3 : 7));
+    int ya[8], yb[8];
+    {
+      const int i = ua >> 1;
+      const uint32_t sel = (ua & 1) ? 0x07060302u : 0x05040100u;
+      idct8_p1_scaled(__builtin_amdgcn_perm(e[4][i], e[0][i], sel), __builtin_amdgcn_perm(e[6][i], e[2][i], sel),
+                      __builtin_amdgcn_perm(e[3][i], e[1][i], sel), __builtin_amdgcn_perm(e[7][i], e[5][i], sel), ya);
+    }
+    {
+      const int i = ub >> 1;
+      const uint32_t sel = (ub & 1) ? 0x07060302u : 0x05040100u;
+      idct8_p1_scaled(__builtin_amdgcn_perm(e[4][i], e[0][i], sel), __builtin_amdgcn_perm(e[6][i], e[2][i], sel),
+                      __builtin_amdgcn_perm(e[3][i], e[1][i], sel), __builtin_amdgcn_perm(e[7][i], e[5][i], sel), yb);
+    }
+#pragma unroll
+    for (int n = 0; n < 8; ++n) pr[cp][n] = hi_halves(ya[n], yb[n]);
+  }
+  // pass 2: the same linear forms on the int16 pairs
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    int s[8];
+    idct8_dot(pr[0][n], pr[1][n], pr[2][n], pr[3][n], kPass2Bias, s);
+    out[2 * n] = descale_pack4(s[0], s[1], s[2], s[3]);
+    out[2 * n + 1] = descale_pack4(s[4], s[5], s[6], s[7]);
+  }
+}
+
 // --- YCbCr -> RGB, 16 fraction bits ----------------------------------------
 // Constants round(2^16 * k) of 1.402, 0.34414, 0.71414, 1.772 (Algorithm 2).
 constexpr int kCrR = 91881;

@@ -99,13 +99,17 @@ struct SegCfg {
   static constexpr int OFF_STAGE = 0;
   static constexpr int OFF_Y = OFF_STAGE + N_SLOT * 128;
   static constexpr int OFF_C = OFF_Y + Y_BYTES;
-  static constexpr int OFF_Q = OFF_C + 2 * CROWS * CWD * 4;
-  static constexpr int OFF_WT = OFF_Q + 3 * 128;
-  static constexpr int LDS_BYTES = OFF_WT + (N_TB > 0 ? N_TB * 32 : 16);
-  // Waves per SIMD that the LDS footprint allows (160 KB per CU, at most 3
-  // asked of the register allocator).
+  static constexpr int OFF_Q = OFF_C + 2 * CROWS * CWD * 4;     // quant tables, uint16 pairs
+  static constexpr int OFF_Q16 = OFF_Q + 3 * 128;               // the same times 16
+  static constexpr int LDS_BYTES = OFF_Q16 + 3 * 128;
+  // Waves per SIMD that the LDS footprint allows (160 KB per CU), at most 3
+  // asked of the register allocator; the 4:2:0 fancy class, which holds the
+  // most state (neighbour rows and row pairs of chroma), asks for 2, which
+  // leaves it 256 registers.
   static constexpr int WAVES_PER_SIMD_LDS = (160 * 1024 / LDS_BYTES) * (NT / 64) / 4;
-  static constexpr int WAVES_PER_SIMD = WAVES_PER_SIMD_LDS < 1 ? 1 : (WAVES_PER_SIMD_LDS > 3 ? 3 : WAVES_PER_SIMD_LDS);
+  static constexpr int WAVES_CAP = HALO_Y ? 2 : 3;
+  static constexpr int WAVES_PER_SIMD =
+      WAVES_PER_SIMD_LDS < 1 ? 1 : (WAVES_PER_SIMD_LDS > WAVES_CAP ? WAVES_CAP : WAVES_PER_SIMD_LDS);
   static_assert(P1_LANES <= NT, "one phase-1 round per sub-tile");
   static_assert(NT % 64 == 0 && NT >= 96, "whole waves; quant table load needs 96 lanes");
   static_assert(N_MAIN % 64 == 0, "tile blocks fill whole waves");
@@ -138,16 +142,16 @@ struct SegmentDecoder {
   __device__ lds32* luma() const { return reinterpret_cast<lds32*>(lds + C::OFF_Y); }
   __device__ lds32* cring(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_C) + c * (CROWS * CWD); }
   __device__ lds32* qtab(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q) + c * 32; }
-  __device__ ldsi* wtb() const { return reinterpret_cast<ldsi*>(lds + C::OFF_WT); }
+  __device__ lds32* qtab16(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q16) + c * 32; }
 
   // Luma row r (0 <= r < YROWS) of sub-tile k lives in row ybase(k) + r of
   // the luma area, taken modulo YRING for the ring.  ybase is uniform.
   __device__ static int ybase(int k) { return HALO_Y ? (YROWS * k) % YRING : (k % NYB) * YROWS; }
-  __device__ lds32* yrow(int base, int r) const {
-    int i = base + r;
+  __device__ static int ywrap(int i) {
     if constexpr (HALO_Y) i = i >= YRING ? i - YRING : i;
-    return luma() + i * YWD;
+    return i;
   }
+  __device__ lds32* yrow(int base, int r) const { return luma() + ywrap(base + r) * YWD; }
   // Chroma row r (0 <= r < CR) of sub-tile k is ring row cbase(k) + r (CROWS
   // is a multiple of CR, so a sub-tile never wraps).  The row above the
   // segment is ring row CROWS - 1, the row below it ring row below_row().
@@ -165,34 +169,37 @@ struct SegmentDecoder {
 
   // ---- coefficient DMA ----
   // 16-byte chunk i of the staging buffer holds row ((i & 7) - j) & 7 of
-  // staged block j = i / 8: blocks j < N_MAIN are block j / SM of MCU j % SM
-  // of the sub-tile, the rest the chroma blocks of the MCUs left and right of
-  // the strip.  Row c of block j lands at ((c + j) & 7) * 16, so lanes that
-  // read whole blocks later hit distinct banks, while the 8 lanes of a block
-  // still read one 128-byte line.
+  // staged block j = i / 8.  Blocks j < N_MAIN are the sub-tile's MCUs in
+  // memory order (block j % BPM of MCU j / BPM, MCUs row by row), so each
+  // MCU row of the sub-tile is one contiguous run of RUNB blocks; the rest
+  // are the chroma blocks of the MCUs left and right of the strip.  Row c
+  // of block j lands at ((c + j) & 7) * 16, so lanes that read whole blocks
+  // later hit distinct banks, while the 8 lanes of a block still read one
+  // 128-byte line.
+  //
+  // A DMA instruction moves 64 chunks = 8 whole blocks J..J+7 with J a
+  // multiple of 8, so (RUNB being a multiple of 8) the run, and with it the
+  // source base, is uniform per instruction, and a lane's offset inside the
+  // 8 blocks depends on its lane number only: block J + (lane >> 3), row
+  // (lane - (lane >> 3)) & 7.
   static constexpr int DMA_CHUNKS = N_SLOT * 8;
-  static constexpr int kNoChunk = -0x7FFFFFFF - 1;
+  static constexpr int RUNB = SX * BPM;
+  static_assert(RUNB % 8 == 0 && N_MAIN % 64 == 0, "DMA instructions never straddle a run or the side blocks");
 
-  // Byte offset of chunk i from the sub-tile's first MCU (negative for the
-  // MCU left of the strip), or kNoChunk when the chunk lies outside the
-  // image or below the sub-tile's nmy MCU rows.  All products stay far
-  // inside 32 bits (a sub-tile spans SY MCU rows).
-  __device__ int chunk_offset(int i, int nmy, int row_bytes) const {
+  __device__ static int lane_chunk_offset(int lane) { return ((lane >> 3) << 7) | (((lane - (lane >> 3)) & 7) << 4); }
+
+  // Side chunk i (i >= 8 N_MAIN): byte offset from the sub-tile's first MCU
+  // (negative for the MCU left of the strip), or -1 when the MCU lies outside
+  // the image or below the sub-tile's nmy rows.
+  __device__ bool side_chunk(int i, int nmy, int row_bytes, int* off) const {
     const int j = i >> 3;
     const int c = ((i & 7) - j) & 7;
-    if (j < N_MAIN) {
-      const int b = j / SM;
-      const int m = j - b * SM;
-      const int lmy = m / SX, lmx = m - (m / SX) * SX;
-      if (lmx >= nmx || lmy >= nmy) return kNoChunk;
-      return lmy * row_bytes + lmx * (BPM * 128) + b * 128 + c * 16;
-    }
     const int t = j - N_MAIN;  // (row << 2) | (right << 1) | chroma component
     const int pos = t >> 2;
     const int dx = ((t >> 1) & 1) ? nmx : -1;
     const int mx = mx0 + dx;
-    if (pos >= nmy || mx < 0 || mx >= im.mcus_x) return kNoChunk;
-    return pos * row_bytes + dx * (BPM * 128) + (NY + (t & 1)) * 128 + c * 16;
+    *off = pos * row_bytes + dx * (BPM * 128) + (NY + (t & 1)) * 128 + c * 16;
+    return pos < nmy && mx >= 0 && mx < im.mcus_x;
   }
 
   // Copy sub-tile k's blocks into the staging buffer.
@@ -200,12 +207,26 @@ struct SegmentDecoder {
     const uint8_t* src0 = reinterpret_cast<const uint8_t*>(block_ptr(sub_r0(k), mx0, 0));
     const int nmy = sub_rows(k);
     const int row_bytes = im.mcus_x * (BPM * 128);
-    for (int base = (tid & ~63); base < DMA_CHUNKS; base += NT) {
-      const int i = base + (tid & 63);
-      const int off = i < DMA_CHUNKS ? chunk_offset(i, nmy, row_bytes) : kNoChunk;
-      if (off != kNoChunk)
-        __builtin_amdgcn_global_load_lds(static_cast<const void*>(src0 + off), (lds_void_t*)(stage() + base * 16),
-                                         16, 0, 0);
+    const int lane = tid & 63;
+    const uint32_t lane_off = static_cast<uint32_t>(lane_chunk_offset(lane));
+    const int main_blocks = nmx * BPM;  // staged blocks of each run that exist
+    // the wave's first chunk, as a scalar (every lane of a wave has the same)
+    const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
+    for (int base = wave0; base < DMA_CHUNKS; base += NT) {
+      lds_void_t* dst = (lds_void_t*)(stage() + base * 16);
+      const int J = base >> 3;
+      if (J < N_MAIN) {
+        const int run = J / RUNB;
+        const int jr = J - run * RUNB;
+        const uint8_t* src = src0 + (run * row_bytes + jr * 128);
+        if (run < nmy && (lane >> 3) < main_blocks - jr)
+          __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + lane_off), dst, 16, 0, 0);
+      } else {
+        const int i = base + lane;
+        int off;
+        if (i < DMA_CHUNKS && side_chunk(i, nmy, row_bytes, &off))
+          __builtin_amdgcn_global_load_lds(static_cast<const void*>(src0 + off), dst, 16, 0, 0);
+      }
     }
   }
 
@@ -219,7 +240,10 @@ struct SegmentDecoder {
       asm volatile("" : "+v"(idx));
       const __attribute__((address_space(1))) uint16_t* q =
           (const __attribute__((address_space(1))) uint16_t*)im.qt + idx;
-      qtab(c)[tid & 31] = static_cast<uint32_t>(q[0]) | (static_cast<uint32_t>(q[1]) << 16);
+      const uint32_t pair = static_cast<uint32_t>(q[0]) | (static_cast<uint32_t>(q[1]) << 16);
+      qtab(c)[tid & 31] = pair;
+      // 16 Q per half, modulo 2^16 (the products are only used modulo 2^16)
+      qtab16(c)[tid & 31] = ((pair << 4) & 0xFFFFu) | ((pair >> 16) << 20);
     }
   }
 
@@ -251,44 +275,49 @@ struct SegmentDecoder {
     }
   }
 
-  // Step A: lanes (task, column u) read one staged column and form the single
-  // pass-1 output of the sample row the filter needs (7 for the block above,
-  // 0 for the block below).
-  __device__ void tb_step_a(bool below) const {
-    const int my = below ? r1 : r0 - 1;
-    if (my < 0 || my >= im.mcus_y) return;
-    const lds8* area = tb_area(below);
-    for (int s = tid; s < 8 * N_TB; s += NT) {
-      const int t = s >> 3, u = s & 7;
-      const int pos = t >> 1;
-      const int mx = mx0 - 1 + pos;
-      if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) continue;
-      const int comp = t & 1;
-      const lds8* blk = area + t * 128 + 2 * u;
-      const ldsu16* q = reinterpret_cast<const ldsu16*>(qtab(1 + comp)) + u;
-      int x[8];
-#pragma unroll
-      for (int v = 0; v < 8; ++v)
-        x[v] = *reinterpret_cast<const lds16*>(blk + (((v + t) & 7) << 4)) * static_cast<int>(q[8 * v]);
-      const int o = below ? idct8_edge_raw<false>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias)
-                          : idct8_edge_raw<true>(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass1Bias);
-      wtb()[t * 8 + u] = o >> kPass1Shift;
-    }
-  }
-
-  // Step B: one lane per neighbour block finishes the row pass and writes
-  // the 8 samples into the ring row above/below the segment; at the true
-  // left edge and at the true right chroma edge it also writes the
-  // replicated sample the filter reads beyond the edge.
-  __device__ void tb_step_b(bool below) const {
+  // One lane per neighbour block forms the one sample row the filter needs
+  // (row 7 of the block above, row 0 of the block below): dequantisation,
+  // that row's output of the column pass for each of the 8 columns (its
+  // integer linear form, four dot products per column), then the row pass
+  // over the 8 results; the samples go into the ring row above/below the
+  // segment.  At the true left edge and at the true right chroma edge the
+  // lane also writes the replicated sample the filter reads beyond the edge.
+  __device__ void tb_edge(bool below) const {
     const int my = below ? r1 : r0 - 1;
     if (my < 0 || my >= im.mcus_y || tid >= N_TB) return;
     const int t = tid, pos = t >> 1;
     const int mx = mx0 - 1 + pos;
     if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) return;
-    const ldsi* w = wtb() + t * 8;
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    const lds8* blk = tb_area(below) + t * 128;
+    const __attribute__((address_space(3))) v4i* qv =
+        reinterpret_cast<const __attribute__((address_space(3))) v4i*>(qtab(1 + (t & 1)));
+    uint32_t d[8][4];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const v4i v = *reinterpret_cast<const __attribute__((address_space(3))) v4i*>(blk + (((c + t) & 7) << 4));
+      const v4i qq = qv[c];
+      const int w[4] = {v.x, v.y, v.z, v.w};
+      const int qw[4] = {qq.x, qq.y, qq.z, qq.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        d[c][i] = __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, w[i]) * __builtin_bit_cast(u16x2, qw[i]));
+    }
+    int x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = u >> 1;
+      const uint32_t sel = (u & 1) ? 0x07060302u : 0x05040100u;
+      const uint32_t p04 = __builtin_amdgcn_perm(d[4][i], d[0][i], sel);
+      const uint32_t p26 = __builtin_amdgcn_perm(d[6][i], d[2][i], sel);
+      const uint32_t p13 = __builtin_amdgcn_perm(d[3][i], d[1][i], sel);
+      const uint32_t p57 = __builtin_amdgcn_perm(d[7][i], d[5][i], sel);
+      const int e0 = dot2(p26, wpair(kE2a, kE6a), dot2(p04, wpair(1 << kConstBits, 1 << kConstBits), kPass1Bias));
+      const int o0 = dot2(p13, wpair(kO[0][0], kO[0][1]), dot2z(p57, wpair(kO[0][2], kO[0][3])));
+      x[u] = (below ? e0 + o0 : e0 - o0) >> kPass1Shift;
+    }
     int y[8];
-    idct8_raw(w[0], w[1], w[2], w[3], w[4], w[5], w[6], w[7], kPass2Bias, y);
+    idct8_raw(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass2Bias, y);
 #pragma unroll
     for (int i = 0; i < 8; ++i) y[i] >>= kPass2Shift;
     lds32* row = cring(t & 1) + (below ? below_row() : CROWS - 1) * CWD;
@@ -299,8 +328,7 @@ struct SegmentDecoder {
     if (mx0 == 0 && mx == 0) row8[7] = static_cast<uint8_t>(clamp255i(y[0]));
     // the true right chroma edge lies in this strip: x = cw repeats x = cw - 1
     const int cw = im.chroma_w;
-    if (cw - 1 < gcx0 + 8 * nmx && mx == ((cw - 1) >> 3))
-    {
+    if (cw - 1 < gcx0 + 8 * nmx && mx == ((cw - 1) >> 3)) {
       int e = y[0];
 #pragma unroll
       for (int i = 1; i < 8; ++i)
@@ -354,14 +382,14 @@ struct SegmentDecoder {
     const int nmy = sub_rows(k);
     if (tid < N_MAIN) {
       const int j = tid;
-      const int b = j / SM;
-      const int m = j - b * SM;
+      const int m = j / BPM;
+      const int b = j - m * BPM;
       const int lmy = m / SX, lmx = m - (m / SX) * SX;
       if (lmx >= nmx || lmy >= nmy) return;
       const int comp = b < NY ? 0 : b - NY + 1;
       uint32_t o[16];
       const v4i rows[8] = {h.r0, h.r1, h.r2, h.r3, h.r4, h.r5, h.r6, h.r7};
-      idct_block_regs(rows, qtab(comp), o);
+      idct_block_fast(rows, qtab(comp), qtab16(comp), o);
       if (comp == 0) {
         const int by = b / HF, bx = b - (b / HF) * HF;
         lds32* dst = yrow(ybase(k), lmy * 8 * VF + by * 8) + lmx * 2 * HF + bx * 2;
@@ -529,25 +557,151 @@ struct SegmentDecoder {
     }
   }
 
-  // 4:2:0 fancy, step k: every chroma row of sub-tile k-1 but its last, and
-  // the last row of sub-tile k-2, whose row below is the first of k-1.
-  __device__ void phase2_split(int k) const {
+  // 4:2:0 fancy, step k: every chroma row of sub-tile k-1 but its last two,
+  // and the last two rows of sub-tile k-2 (the last of which needs the first
+  // row of k-1), as pairs of rows: one pair of rows and 4 samples per lane.
+  __device__ void phase2_pairs(int k) const {
+    static_assert(NT == 8 * C::UX, "the row pairs of a sub-tile fill the workgroup once");
     const bool has_a = k >= 1 && k <= K;
     const bool has_b = k >= 2 && k <= K + 1;
     if (!has_a && !has_b) return;
     const SubInfo sa = uniform(sub_info(has_a ? k - 1 : 0)), sb = uniform(sub_info(has_b ? k - 2 : 0));
-    constexpr int V_MAIN = (CR - 1) * C::UX;
-    for (int v = tid; v < C::UNITS; v += NT) {
-      const bool tail = v >= V_MAIN;
-      const int cr_a = v / C::UX;
-      const int g = v - cr_a * C::UX;
-      if (g >= 2 * nmx || (tail ? !has_b : (!has_a || cr_a >= sa.rows - 1))) continue;
-      SubInfo si;
-      si.rgb = tail ? sb.rgb : sa.rgb;
-      si.gcy0 = tail ? sb.gcy0 : sa.gcy0;
-      si.yb = tail ? sb.yb : sa.yb;
-      si.cb = tail ? sb.cb : sa.cb;
-      unit(si, tail ? sb.rows - 1 : cr_a, g);
+    const int g = tid % C::UX, rp = tid / C::UX;
+    const bool tail = rp == 0;
+    if (g >= 2 * nmx || (tail ? !has_b : !has_a)) return;
+    SubInfo si;
+    si.rgb = tail ? sb.rgb : sa.rgb;
+    si.gcy0 = tail ? sb.gcy0 : sa.gcy0;
+    si.yb = tail ? sb.yb : sa.yb;
+    si.cb = tail ? sb.cb : sa.cb;
+    const int cr = tail ? sb.rows - 2 : 2 * (rp - 1);
+    if (!tail && cr >= sa.rows - 2) return;
+    // every unit of the strip is whole and its rows 4-byte aligned: the
+    // plain store path alone
+    if (im.aligned_out && (gcx0 + 8 * nmx) * 2 <= im.width)
+      unit_pair<true>(si, cr, g);
+    else
+      unit_pair<false>(si, cr, g);
+  }
+
+  // 3 a + b on 16-bit halves (every value here is below 2^12)
+  __device__ static u16x2 mad3(u16x2 a, u16x2 b) {
+    uint32_t r;
+    asm("v_pk_mad_u16 %0, %1, 3, %2 op_sel_hi:[1,0,1]"
+        : "=v"(r) : "v"(__builtin_bit_cast(uint32_t, a)), "v"(__builtin_bit_cast(uint32_t, b)));
+    return __builtin_bit_cast(u16x2, r);
+  }
+
+  // One horizontal output row of the fancy h2v2 filter from the vertical
+  // sums s0..s5 (as pairs): sample j (1..4) gives the even pixel
+  // (3 s_j + s_{j-1} + 8) >> 4 and the odd one (3 s_j + s_{j+1} + 7) >> 4,
+  // each minus 128.  The bias (8 - 2048 or 7 - 2048) is added to the
+  // neighbour term, so each 16-bit half holds the biased sum as an int16 in
+  // [-2040, 2040], and one signed bit-field extract (bits 4..15) both
+  // shifts and unpacks it.
+  __device__ static void h2v2_row_x(const u16x2 s[3], int o[8]) {
+    const u16x2 s12 = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, s[1]),
+                                                                       __builtin_bit_cast(uint32_t, s[0]), 0x05040302u));
+    const u16x2 s34 = __builtin_bit_cast(u16x2, __builtin_amdgcn_perm(__builtin_bit_cast(uint32_t, s[2]),
+                                                                       __builtin_bit_cast(uint32_t, s[1]), 0x05040302u));
+    const u16x2 three = {3, 3};
+    const u16x2 eb = {static_cast<unsigned short>(8 - 2048), static_cast<unsigned short>(8 - 2048)};
+    const u16x2 ob = {static_cast<unsigned short>(7 - 2048), static_cast<unsigned short>(7 - 2048)};
+    const uint32_t e01 = __builtin_bit_cast(uint32_t, static_cast<u16x2>(s12 * three + (s[0] + eb)));
+    const uint32_t o01 = __builtin_bit_cast(uint32_t, static_cast<u16x2>(s12 * three + (s[1] + ob)));
+    const uint32_t e23 = __builtin_bit_cast(uint32_t, static_cast<u16x2>(s34 * three + (s[1] + eb)));
+    const uint32_t o23 = __builtin_bit_cast(uint32_t, static_cast<u16x2>(s34 * three + (s[2] + ob)));
+    o[0] = __builtin_amdgcn_sbfe(static_cast<int>(e01), 4, 12);
+    o[1] = __builtin_amdgcn_sbfe(static_cast<int>(o01), 4, 12);
+    o[2] = __builtin_amdgcn_sbfe(static_cast<int>(e01), 20, 12);
+    o[3] = __builtin_amdgcn_sbfe(static_cast<int>(o01), 20, 12);
+    o[4] = __builtin_amdgcn_sbfe(static_cast<int>(e23), 4, 12);
+    o[5] = __builtin_amdgcn_sbfe(static_cast<int>(o23), 4, 12);
+    o[6] = __builtin_amdgcn_sbfe(static_cast<int>(e23), 20, 12);
+    o[7] = __builtin_amdgcn_sbfe(static_cast<int>(o23), 20, 12);
+  }
+
+  // Chroma rows cr and cr + 1 of a sub-tile's strip, samples 4g..4g+3
+  // (4:2:0 fancy): four output rows of 8 pixels.  Each chroma row is read
+  // once, with its neighbours above and below, for all four rows.
+  template <bool PLAIN>
+  __device__ void unit_pair(const SubInfo& si, const int cr, const int g) const {
+    const int W = im.width, H = im.height;
+    const int px0 = (gcx0 + 4 * g) * 2;
+    const int gy = si.gcy0 + cr;
+    const int py0 = 2 * gy;
+    if (px0 >= W || py0 >= H) return;
+    const int ch = im.chroma_h;
+    const int rc = si.cb + cr;  // ring row of row cr; rc + 1 is row cr + 1 (a sub-tile never wraps the ring)
+    // neighbours, repeated at the true top and bottom chroma edges
+    const int ru = gy == 0 ? rc : ring_prev(rc);
+    const bool last0 = gy == ch - 1;  // row cr is the last chroma row (row cr + 1 lies below the image)
+    const int rd = gy + 1 >= ch - 1 ? rc + 1 : ring_next(rc + 1);
+    u16x2 pu[2][3], p0[2][3], p1[2][3], pd[2][3];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const lds32* ring = cring(c) + (g + 2);
+      chroma_pairs(ring + mul24(ru, CWD), pu[c]);
+      chroma_pairs(ring + mul24(rc, CWD), p0[c]);
+      chroma_pairs(ring + mul24(rc + 1, CWD), p1[c]);
+      chroma_pairs(ring + mul24(rd, CWD), pd[c]);
+    }
+    // the luma of the four rows, fetched together
+    uint32_t yl[4][2];
+    {
+      const int ly = si.yb + 2 * cr;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const lds32* ysrc = luma() + (mul24(ywrap(ly + j), YWD) + 2 * g);
+        yl[j][0] = ysrc[0];
+        yl[j][1] = ysrc[1];
+      }
+    }
+    // the lower neighbour of row cr: row cr + 1, or row cr itself at the
+    // true bottom edge
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (last0) p1[c][i] = p0[c][i];
+    const int nv = min(8, W - px0);
+    const int pitch24 = static_cast<int>(im.pitch);
+    gbl8* row = si.rgb + (mul24(2 * cr, pitch24) + 24 * g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (py0 + j >= H) break;
+      int xs[2][8];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        u16x2 sv[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          // vertical 3:1 sums (rows cr-1|cr+1 around cr, then cr|cr+2 around cr+1)
+          if (j == 0) sv[i] = mad3(p0[c][i], pu[c][i]);
+          else if (j == 1) sv[i] = mad3(p0[c][i], p1[c][i]);
+          else if (j == 2) sv[i] = mad3(p1[c][i], p0[c][i]);
+          else sv[i] = mad3(p1[c][i], pd[c][i]);
+        }
+        h2v2_row_x(sv, xs[c]);
+      }
+      uint32_t w[6];
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        RGBWide px[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) px[i] = ycc_wide(y16_of(yl[j][kk], i), xs[0][4 * kk + i], xs[1][4 * kk + i]);
+        pack_rgb4(px, w + 3 * kk);
+      }
+      if (PLAIN || (nv == 8 && im.aligned_out)) {
+        gbl32* wd = reinterpret_cast<gbl32*>(row);
+#pragma unroll
+        for (int kk = 0; kk < 6; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
+      } else if (nv == 8) {
+        store_shifted(row, w);
+      } else {
+        store_ragged(row, w, 3 * nv);
+      }
+      row += pitch24;
     }
   }
 
@@ -705,6 +859,7 @@ struct SegmentDecoder {
     gcx0 = 8 * mx0;
 
     __syncthreads();  // the previous segment's readers are done with every buffer
+    __builtin_amdgcn_s_setprio(3);
     load_qtabs();
     dma(0);
     if constexpr (HALO_Y) {
@@ -712,7 +867,10 @@ struct SegmentDecoder {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     }
     __syncthreads();  // quant tables (and the blocks above) visible
-    if constexpr (HALO_Y) tb_step_a(false);
+    // the row above: phase 1 first writes the luma ring (where its blocks
+    // sit) after the next barrier; phase 2 first reads the ring row one step
+    // later
+    if constexpr (HALO_Y) tb_edge(false);
 
     for (int k = 0; k < K + LAG; ++k) {
       Held h{};  // per step, fully defined so it stays in registers
@@ -720,16 +878,22 @@ struct SegmentDecoder {
       // RGB stores, so the steps with no DMA in flight skip it).
       if (k < K || (HALO_Y && k == K)) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();  // staging of k landed; last step's LDS writes visible
+      // the step's priority falls as the segment advances, so the
+      // workgroup that is behind on a CU catches up
+      if (k == 0) __builtin_amdgcn_s_setprio(3);
+      else if (k == 1) __builtin_amdgcn_s_setprio(2);
+      else if (k == 2) __builtin_amdgcn_s_setprio(1);
+      else __builtin_amdgcn_s_setprio(0);
       if constexpr (HALO_Y) {
-        if (k == 0) tb_step_b(false);
-        if (k == K) tb_step_a(true);
+        // the row below (its blocks were staged after the last sub-tile):
+        // phase 2 of the next step reads it
+        if (k == K) tb_edge(true);
         if (k < K) read_stage(k, h);
         // Phase 2 reads the luma rows that phase 1 of k overwrites in the
         // ring, so it goes first, in the interval that also frees the
         // staging buffer; its stores drain while the IDCT runs.
-        phase2_split(k);
+        phase2_pairs(k);
         __syncthreads();  // staging free; phase 2's luma rows read
-        if (k == K) tb_step_b(true);   // the row below: phase 2 of the next step reads it
         if (k + 1 < K) dma(k + 1);
         if (k + 1 == K) dma_tb(true);  // staging is idle from here on
       } else {

@@ -89,6 +89,39 @@ def test_random_coefficients_bit_exact(M, ctx, samp):
                         f"random {samp} {mode}")
 
 
+@pytest.mark.parametrize("samp", ["444", "422", "420"])
+def test_dot_product_and_int32_row_pass_paths_bit_exact(M, ctx, samp):
+    """The row pass runs as int16 dot products for a wave whose dequantised
+    coefficients all lie in [-1024, 1023] and in int32 otherwise; both give
+    the oracle's bits.  Cases: every coefficient at the ends of that range
+    (the largest pass-1 results the dot-product path meets), a few blocks
+    reaching 1024..1155 among conforming ones (mixed waves), and the whole
+    documented domain (+-1155) densely."""
+    w, h = 203, 77
+    frame = encode.make_frame(w, h, samp)
+    base = workloads.random_coefficients(frame, seed=w * 31 + h, density=0.6)
+    rng = np.random.default_rng(4242)
+    extremes = rng.choice(np.array([-1024, 1023], dtype=np.int16), size=base.shape)
+    mixed = base.copy()
+    few = rng.random(len(mixed)) < 0.02
+    mixed[few, rng.integers(0, 64, few.sum())] = rng.choice(np.array([-1155, -1100, 1024, 1155], dtype=np.int16),
+                                                           few.sum())
+    dense = rng.integers(-1155, 1156, size=base.shape).astype(np.int16)
+    qt = np.ones((4, 64), dtype=np.uint16)
+    for name, coef in (("extremes", extremes), ("mixed", mixed), ("dense", dense)):
+        for mode in ("simple", "fancy"):
+            say(f"row-pass paths {samp} {mode} {name}")
+            assert_same(gpu_decode(M, ctx, frame, coef, qt, mode), oracle.decode(frame, coef, qt, mode),
+                        f"{name} {samp} {mode}")
+    # the same ranges reached through quantisation factors: c * Q near the ends
+    q2 = np.full((4, 64), 5, dtype=np.uint16)
+    coef = rng.choice(np.array([-231, -205, 204, 231], dtype=np.int16), size=base.shape)
+    for mode in ("simple", "fancy"):
+        say(f"row-pass paths {samp} {mode} c*Q")
+        assert_same(gpu_decode(M, ctx, frame, coef, q2, mode), oracle.decode(frame, coef, q2, mode),
+                    f"c*Q {samp} {mode}")
+
+
 @pytest.mark.parametrize("samp", ["422", "420"])
 def test_band_decode_equals_whole_decode(M, ctx, samp):
     rgb = images.texture_rgb(300, 203, 77, sigma=12)
