@@ -292,6 +292,23 @@ int mjd_batch_info(const mjd_batch* batch, uint32_t* segments, uint32_t* workgro
 /* Synchronise the device and free the batch's tables and graph. */
 void mjd_batch_destroy(mjd_batch* batch);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * decode as mjd_batch_create + mjd_batch_launch(direct) + destroy, in one
+ * call that allocates no device memory.  The batch tables (queue counters,
+ * image views, segment queue) go into a fixed 4 MiB device array of the
+ * library, one per GPU and held until the process ends, by one host-to-device
+ * copy on `stream`, followed by the persistent kernel on `stream`.
+ *   jobs, n, upsample: as for mjd_batch_create (host array, read during the
+ *     call only); the jobs' device buffers must stay valid until the kernel
+ *     has finished.
+ * Returns MJD_EBUDGET (nothing enqueued) when the tables would exceed 4 MiB,
+ * e.g. more than about 58000 images or 130000 segments.  Every call on one
+ * GPU shares that array, which keeps the last call's contents: calls that
+ * overlap on one GPU (different streams, or another context on the same
+ * device) race, so they must be ordered by one stream or a synchronisation. */
+int mjd_decode_batch_noalloc(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, void* stream);
+
 /* ---------------------------------------------------------------------
  * Host side: baseline JPEG bitstreams -> coefficient blocks.
  *

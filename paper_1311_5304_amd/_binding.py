@@ -182,6 +182,8 @@ def lib() -> ctypes.CDLL:
         L.mjd_batch_launch.restype = i32
         L.mjd_batch_info.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(ctypes.c_uint64)]
         L.mjd_batch_info.restype = i32
+        L.mjd_decode_batch_noalloc.argtypes = [vp, ctypes.POINTER(mjd_job), sz, i32, vp]
+        L.mjd_decode_batch_noalloc.restype = i32
         L.mjd_batch_destroy.argtypes = [vp]
         L.mjd_batch_destroy.restype = None
         L.mjd_parse.argtypes = [vp, sz, ctypes.POINTER(mjd_scan), vp]
@@ -370,17 +372,22 @@ def mjd_copy(ctx: Context, dst, src, nbytes: int, stream=None):
     _check(lib().mjd_copy(ctx.handle, _ptr(dst), _ptr(src), int(nbytes), _stream(stream)))
 
 
+def _job_array(jobs):
+    arr = (mjd_job * len(jobs))()
+    for i, (frame, coef, qt, rgb, pitch) in enumerate(jobs):
+        arr[i].frame = make_frame(frame)
+        arr[i].d_coef = _ptr(coef)
+        arr[i].d_qt = _ptr(qt)
+        arr[i].d_rgb = _ptr(rgb)
+        arr[i].pitch = int(pitch)
+    return arr
+
+
 class Batch:
     """Owns an mjd_batch*: a planned set of images decoded by one persistent launch."""
 
     def __init__(self, ctx: Context, jobs, upsample: int):
-        arr = (mjd_job * len(jobs))()
-        for i, (frame, coef, qt, rgb, pitch) in enumerate(jobs):
-            arr[i].frame = make_frame(frame)
-            arr[i].d_coef = _ptr(coef)
-            arr[i].d_qt = _ptr(qt)
-            arr[i].d_rgb = _ptr(rgb)
-            arr[i].pitch = int(pitch)
+        arr = _job_array(jobs)
         p = ctypes.c_void_p()
         _check(lib().mjd_batch_create(ctx.handle, arr, len(jobs), int(upsample), ctypes.byref(p)))
         self.handle = p
@@ -417,6 +424,14 @@ def mjd_batch_launch(batch: Batch, use_graph: bool = False, stream=None):
 
 def mjd_batch_destroy(batch: Batch):
     batch.close()
+
+
+def mjd_decode_batch_noalloc(ctx: Context, jobs, upsample: int, stream=None):
+    """The batch decode of mjd_batch_create + launch, with no device allocation
+    (the tables go into the library's fixed per-GPU array).  jobs: sequence of
+    (frame, coef, qt, rgb, pitch); the buffers must outlive the kernel."""
+    arr = _job_array(jobs)
+    _check(lib().mjd_decode_batch_noalloc(ctx.handle, arr, len(jobs), int(upsample), _stream(stream)))
 
 
 # ---- host side: bitstreams -> coefficients -------------------------------------------

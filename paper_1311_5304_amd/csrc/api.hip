@@ -106,6 +106,11 @@ int mjd_ctx_create(mjd_ctx** out, int device) {
   ctx->device = device;
   ctx->cu_count = prop.multiProcessorCount;
   ctx->device_name = prop.gcnArchName;
+  e = mjd::noalloc_scratch_address(device, &ctx->noalloc_scratch);
+  if (e != hipSuccess) {
+    delete ctx;
+    return mjd::fail(MJD_EDEVICE, "scratch address on device %d: %s", device, hipGetErrorString(e));
+  }
   *out = ctx;
   return MJD_OK;
 }

@@ -9,6 +9,8 @@
 // leaves it resets the counters, so the same launch (or a hipGraph holding
 // it) can simply be replayed.
 #include <algorithm>
+#include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -186,6 +188,36 @@ int batch_plan(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, BatchP
   return MJD_OK;
 }
 
+// ---- the no-allocation entry point ----
+// The batch tables of mjd_decode_batch_noalloc live in this fixed device
+// array (one copy per GPU, held until the process ends): the queue counters
+// first, then the image views, then the segment queue.  In host code the
+// array's name is not a device address; every use goes through the address
+// looked up with hipGetSymbolAddress once per device.
+constexpr size_t kNoAllocScratchBytes = size_t(4) << 20;
+constexpr size_t kNoAllocHeader = 256;  // the two queue counters, padded
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
+
 hipError_t batch_enqueue(const ImageView* d_views, const BatchItem* d_items, int n_items, unsigned* d_counters,
                          int grid, hipStream_t stream) {
   hipLaunchKernelGGL(decode_batch, dim3(grid), dim3(kBatchThreads), 0, stream, d_views, d_items, n_items,
@@ -291,6 +323,43 @@ int mjd_batch_info(const mjd_batch* batch, uint32_t* segments, uint32_t* workgro
   if (segments) *segments = static_cast<uint32_t>(batch->n_items);
   if (workgroups) *workgroups = static_cast<uint32_t>(batch->grid);
   if (pixels) *pixels = batch->pixels;
+  return MJD_OK;
+}
+
+int mjd_decode_batch_noalloc(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, void* stream) {
+  if (!ctx) return mjd::fail(MJD_EINVAL, "null context");
+  if (!jobs && n) return mjd::fail(MJD_EINVAL, "null jobs");
+  if (!ctx->noalloc_scratch) return mjd::fail(MJD_EDEVICE, "no scratch address for device %d", ctx->device);
+  mjd::BatchPlan plan;
+  int rc = mjd::batch_plan(ctx, jobs, n, upsample, &plan);
+  if (rc != MJD_OK) return rc;
+  const size_t views_bytes = plan.views.size() * sizeof(mjd::ImageView);
+  const size_t items_bytes = plan.items.size() * sizeof(mjd::BatchItem);
+  const size_t items_off = mjd::kNoAllocHeader + ((views_bytes + 255) & ~size_t(255));
+  const size_t need = items_off + items_bytes;
+  if (need > mjd::kNoAllocScratchBytes)
+    return mjd::fail(MJD_EBUDGET, "batch tables need %zu bytes; the no-allocation entry point holds at most %zu",
+                     need, mjd::kNoAllocScratchBytes);
+  // the tables as they go to the device, in this thread's reusable buffer
+  // (host memory; its capacity only grows)
+  thread_local std::vector<uint8_t> host;
+  if (host.size() < need) host.resize(need);
+  std::memset(host.data(), 0, mjd::kNoAllocHeader);  // both queue counters start at zero
+  std::memcpy(host.data() + mjd::kNoAllocHeader, plan.views.data(), views_bytes);
+  std::memcpy(host.data() + items_off, plan.items.data(), items_bytes);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != ctx->device && hipSetDevice(ctx->device) != hipSuccess)
+    return mjd::fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+  uint8_t* base = static_cast<uint8_t*>(ctx->noalloc_scratch);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(base, host.data(), need, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = mjd::batch_enqueue(reinterpret_cast<const mjd::ImageView*>(base + mjd::kNoAllocHeader),
+                           reinterpret_cast<const mjd::BatchItem*>(base + items_off),
+                           static_cast<int>(plan.items.size()), reinterpret_cast<unsigned*>(base), plan.grid, st);
+  if (cur != ctx->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return mjd::fail(MJD_EDEVICE, "no-allocation batch launch failed: %s", hipGetErrorString(e));
   return MJD_OK;
 }
 

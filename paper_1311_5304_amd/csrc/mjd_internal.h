@@ -16,6 +16,7 @@ struct mjd_ctx {
   int xcd_count = 8;
   std::string device_name;
   mjd_tuning tuning{0, 0};
+  void* noalloc_scratch = nullptr;  // device address of the no-allocation batch scratch on `device`
 };
 
 namespace mjd {
@@ -52,5 +53,9 @@ int batch_plan(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, BatchP
 // d_counters (2 words) must be zero; the kernel leaves them zero.
 hipError_t batch_enqueue(const ImageView* d_views, const BatchItem* d_items, int n_items, unsigned* d_counters,
                          int grid, hipStream_t stream);
+
+// Device address of the no-allocation batch scratch on the current device
+// (looked up once per device, then cached).
+hipError_t noalloc_scratch_address(int device, void** out);
 
 }  // namespace mjd
