@@ -16,7 +16,7 @@ BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["api.hip", "decode.hip", "batch.hip", "copy.hip", "server.hip", "entropy.hip", "variants.hip"]
 # host-only C++ (no device code): built with the host compiler
-HOST_SOURCES = ["host_jpeg.cpp", "pipeline.cpp", "model.cpp", "cpu_decode.cpp", "hetero.cpp"]
+HOST_SOURCES = ["host_common.cpp", "host_jpeg.cpp", "pipeline.cpp", "model.cpp", "cpu_decode.cpp", "hetero.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

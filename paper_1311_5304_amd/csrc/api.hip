@@ -6,48 +6,7 @@
 
 #include "mjd_internal.h"
 
-namespace {
-thread_local char g_err[512] = "";
-}
-
 namespace mjd {
-
-int fail(int code, const char* fmt, ...) {
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(g_err, sizeof(g_err), fmt, ap);
-  va_end(ap);
-  return code;
-}
-
-int frame_geometry(const mjd_frame* f, mjd_geometry* g) {
-  if (!f || !g) return fail(MJD_EINVAL, "null frame or geometry pointer");
-  if (f->width < 1 || f->width > 65535 || f->height < 1 || f->height > 65535)
-    return fail(MJD_EINVAL, "image size %ux%u outside 1..65535", f->width, f->height);
-  for (int c = 0; c < 3; ++c) {
-    if (f->h[c] < 1 || f->h[c] > 4 || f->v[c] < 1 || f->v[c] > 4)
-      return fail(MJD_EINVAL, "component %d sampling factors (%u,%u) outside 1..4", c, f->h[c], f->v[c]);
-    if (f->qsel[c] > 3) return fail(MJD_EINVAL, "component %d quant table selector %u > 3", c, f->qsel[c]);
-  }
-  if (f->reserved != 0) return fail(MJD_EINVAL, "reserved frame field must be 0");
-  const bool luma_ok = (f->h[0] == 1 && f->v[0] == 1) || (f->h[0] == 2 && f->v[0] == 1) ||
-                       (f->h[0] == 2 && f->v[0] == 2);
-  if (!luma_ok || f->h[1] != 1 || f->v[1] != 1 || f->h[2] != 1 || f->v[2] != 1)
-    return fail(MJD_EUNSUPPORTED, "sampling Y(%u,%u) Cb(%u,%u) Cr(%u,%u) not supported (4:4:4, 4:2:2, 4:2:0 only)",
-                f->h[0], f->v[0], f->h[1], f->v[1], f->h[2], f->v[2]);
-  const uint32_t hmax = f->h[0], vmax = f->v[0];
-  g->mcu_w = 8 * hmax;
-  g->mcu_h = 8 * vmax;
-  g->mcus_x = (f->width + g->mcu_w - 1) / g->mcu_w;
-  g->mcus_y = (f->height + g->mcu_h - 1) / g->mcu_h;
-  g->blocks_per_mcu = hmax * vmax + 2;
-  for (int c = 0; c < 3; ++c) {
-    g->comp_w[c] = (f->width * f->h[c] + hmax - 1) / hmax;
-    g->comp_h[c] = (f->height * f->v[c] + vmax - 1) / vmax;
-  }
-  g->n_blocks = static_cast<uint64_t>(g->mcus_x) * g->mcus_y * g->blocks_per_mcu;
-  return MJD_OK;
-}
 
 int ctx_device(const mjd_ctx* ctx) { return ctx->device; }
 
@@ -83,15 +42,8 @@ int job_view(const mjd_job* j, int upsample, ImageView* im, mjd_geometry* g) {
 
 extern "C" {
 
-const char* mjd_last_error(void) { return g_err; }
-
-int mjd_geometry_of(const mjd_frame* frame, mjd_geometry* out) {
-  g_err[0] = 0;
-  return mjd::frame_geometry(frame, out);
-}
-
 int mjd_ctx_create(mjd_ctx** out, int device) {
-  g_err[0] = 0;
+  mjd::clear_error();
   if (!out) return mjd::fail(MJD_EINVAL, "null context out-pointer");
   *out = nullptr;
   int n = 0;
@@ -127,7 +79,7 @@ void mjd_ctx_destroy(mjd_ctx* ctx) {
 int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef, const uint16_t* d_qt,
                int upsample, uint8_t* d_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1,
                void* stream) {
-  g_err[0] = 0;
+  mjd::clear_error();
   if (!ctx) return mjd::fail(MJD_EINVAL, "null context");
   if (!frame) return mjd::fail(MJD_EINVAL, "null frame");
   mjd_job job{*frame, d_coef, d_qt, d_rgb, pitch};
@@ -150,7 +102,7 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef, cons
 }
 
 int mjd_ctx_set_tuning(mjd_ctx* ctx, const mjd_tuning* tuning) {
-  g_err[0] = 0;
+  mjd::clear_error();
   if (!ctx || !tuning) return mjd::fail(MJD_EINVAL, "null context or tuning");
   if (tuning->seg_subtiles > 65536 || tuning->max_workgroups > (1u << 20))
     return mjd::fail(MJD_EINVAL, "tuning values out of range");
@@ -159,14 +111,14 @@ int mjd_ctx_set_tuning(mjd_ctx* ctx, const mjd_tuning* tuning) {
 }
 
 int mjd_ctx_get_tuning(const mjd_ctx* ctx, mjd_tuning* tuning) {
-  g_err[0] = 0;
+  mjd::clear_error();
   if (!ctx || !tuning) return mjd::fail(MJD_EINVAL, "null context or tuning");
   *tuning = ctx->tuning;
   return MJD_OK;
 }
 
 int mjd_copy(mjd_ctx* ctx, void* d_dst, const void* d_src, size_t bytes, void* stream) {
-  g_err[0] = 0;
+  mjd::clear_error();
   if (!ctx) return mjd::fail(MJD_EINVAL, "null context");
   if (!d_dst || !d_src) return mjd::fail(MJD_EINVAL, "null device buffer");
   if (reinterpret_cast<uintptr_t>(d_dst) % 16 || reinterpret_cast<uintptr_t>(d_src) % 16 || bytes % 16)

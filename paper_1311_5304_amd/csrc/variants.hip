@@ -549,74 +549,9 @@ hipError_t launch_idct(const View& v, const Consts& k, uint64_t n_tiles, int cu_
 
 }  // namespace var
 
-// Geometry of a variant frame and the workspace its planes need.
-static int variant_geometry(const mjd_variant* vr, mjd_geometry* g, uint64_t* work, uint32_t plane_pitch[3],
-                            uint64_t plane_off[3]) {
-  if (!vr || !g) return fail(MJD_EINVAL, "null variant or geometry pointer");
-  const mjd_frame& f = vr->frame;
-  if (f.reserved != 0) return fail(MJD_EINVAL, "reserved frame field must be 0");
-  const uint32_t scale = vr->scale ? vr->scale : 1;
-  if (scale != 1 && scale != 2 && scale != 4 && scale != 8)
-    return fail(MJD_EINVAL, "scale 1/%u is not 1, 1/2, 1/4 or 1/8", vr->scale);
-  if (f.width < 1 || f.width > 65535 || f.height < 1 || f.height > 65535)
-    return fail(MJD_EINVAL, "image size %ux%u outside 1..65535", f.width, f.height);
-  if (vr->ncomp != 1 && vr->ncomp != 3) return fail(MJD_EINVAL, "ncomp %u is neither 1 nor 3", vr->ncomp);
-  if (vr->idct != MJD_IDCT_ISLOW && vr->idct != MJD_IDCT_IFAST && vr->idct != MJD_IDCT_FLOAT)
-    return fail(MJD_EINVAL, "IDCT method %d unknown", vr->idct);
-  if (vr->upsample != MJD_UPSAMPLE_SIMPLE && vr->upsample != MJD_UPSAMPLE_FANCY)
-    return fail(MJD_EINVAL, "upsample mode %d unknown", vr->upsample);
-  if (scale > 1 && vr->idct != MJD_IDCT_ISLOW)
-    return fail(MJD_EUNSUPPORTED, "scaled decoding has the islow-style reduced transform only");
-  const int nc = static_cast<int>(vr->ncomp);
-  for (int c = 0; c < nc; ++c)
-    if (f.qsel[c] > 3) return fail(MJD_EINVAL, "component %d quant table selector %u > 3", c, f.qsel[c]);
-  uint32_t hy = 1, vy = 1;
-  if (nc == 3) {
-    hy = f.h[0];
-    vy = f.v[0];
-    const bool luma_ok = (hy == 1 && vy == 1) || (hy == 2 && vy == 1) || (hy == 1 && vy == 2) ||
-                         (hy == 2 && vy == 2) || (hy == 4 && vy == 1);
-    if (!luma_ok || f.h[1] != 1 || f.v[1] != 1 || f.h[2] != 1 || f.v[2] != 1)
-      return fail(MJD_EUNSUPPORTED, "sampling Y(%u,%u) Cb(%u,%u) Cr(%u,%u) not supported", f.h[0], f.v[0], f.h[1],
-                  f.v[1], f.h[2], f.v[2]);
-  }
-  g->mcu_w = 8 * hy;
-  g->mcu_h = 8 * vy;
-  g->mcus_x = (f.width + g->mcu_w - 1) / g->mcu_w;
-  g->mcus_y = (f.height + g->mcu_h - 1) / g->mcu_h;
-  g->blocks_per_mcu = nc == 1 ? 1 : hy * vy + 2;
-  g->n_blocks = static_cast<uint64_t>(g->mcus_x) * g->mcus_y * g->blocks_per_mcu;
-  // component sizes at the output scale; planes of whole blocks of n
-  // samples, rows padded to 16 bytes
-  const uint32_t n = 8 / scale;
-  uint64_t total = 0;
-  for (int c = 0; c < 3; ++c) {
-    const uint32_t hc = c == 0 ? hy : 1, vc = c == 0 ? vy : 1;
-    const uint32_t cw = (f.width * hc + hy - 1) / hy, ch = (f.height * vc + vy - 1) / vy;
-    g->comp_w[c] = c < nc ? (cw + scale - 1) / scale : 0;
-    g->comp_h[c] = c < nc ? (ch + scale - 1) / scale : 0;
-    plane_pitch[c] = (g->mcus_x * hc * n + 15) & ~15u;
-    plane_off[c] = total;
-    if (nc == 3) total += (static_cast<uint64_t>(plane_pitch[c]) * g->mcus_y * vc * n + 255) & ~255ull;
-  }
-  *work = total;
-  return MJD_OK;
-}
-
 }  // namespace mjd
 
 extern "C" {
-
-int mjd_variant_geometry(const mjd_variant* variant, mjd_geometry* out, uint64_t* work_bytes) {
-  uint32_t pp[3];
-  uint64_t po[3], wb = 0;
-  mjd_geometry g;
-  const int rc = mjd::variant_geometry(variant, &g, &wb, pp, po);
-  if (rc != MJD_OK) return rc;
-  if (out) *out = g;
-  if (work_bytes) *work_bytes = wb;
-  return MJD_OK;
-}
 
 int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* d_coef, const uint16_t* d_qt,
                        uint8_t* d_out, size_t pitch, void* d_work, uint64_t work_bytes, void* stream) {
