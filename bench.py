@@ -39,7 +39,10 @@ def parse():
                     help="budget of each oracle baseline leg (one core, then all cores)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true", help="skip the small-image latency loop")
-    ap.add_argument("--tune", action="store_true", help="autotune the launch shape before timing")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="launch with the library's default shape instead of the tuned one")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every launch shape again even when the tuning cache holds this workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the mixed 256-image batch measurement")
     ap.add_argument("--batch-images", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=10)
@@ -79,6 +82,17 @@ def profiled_traffic():
     return int(m_bytes.group(1)) if h.hexdigest() == m_hash.group(1) else None
 
 
+def tuning_report(entry, source):
+    """The launch shape a measurement ran with: where it came from (the
+    tuning cache or a fresh search), the ranges searched and whether the
+    winner lies inside them on each ordered axis."""
+    best = entry["best"]
+    keep = ("shape", "sx", "sy", "threads", "resident_per_cu", "workgroups_per_cu", "workgroups", "seg_subtiles",
+            "ms", "ms_refined", "segments", "launched")
+    return {"source": source, "choice": {k: best[k] for k in keep if k in best}, "interior": entry["interior"],
+            "ranges": entry["ranges"], "candidates": entry["candidates"]}
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -101,7 +115,7 @@ def batch_workload(args, M, ctx, dev, stream):
 
     Reports the batched persistent launch (hipGraph replay and direct) against
     per-image launches (back-to-back on one stream, and synchronised after each
-    image), all on the same resident buffers, plus the autotuner's table and a
+    image), all on the same resident buffers, plus the tuned launch shape and a
     sampled bit-exactness check against the oracle."""
     import torch
 
@@ -130,14 +144,15 @@ def batch_workload(args, M, ctx, dev, stream):
                 "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
                 "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
-    log("autotuning the batch")
-    best, table = autotune.tune_batch(ctx, jobs, M.MJD_UPSAMPLE_FANCY, reps=3)
-    log("timing batched and per-image launches")
-    res["autotune"] = {"best": best, "table": table}
     saved = M.mjd_ctx_get_tuning(ctx)
-    M.mjd_ctx_set_tuning(ctx, best["seg_subtiles"], best["max_workgroups"])
+    if not args.no_tune:
+        log("batch launch shape (tuning cache, else the autotuner)")
+        entry, source = autotune.tuned_batch(ctx, jobs, M.MJD_UPSAMPLE_FANCY,
+                                             f"{len(jobs)} images 320..4096 px mixed samplings", retune=args.retune)
+        res["tuning"] = tuning_report(entry, source)
     batch = M.Batch(ctx, jobs, M.MJD_UPSAMPLE_FANCY)
-    M.mjd_ctx_set_tuning(ctx, saved["seg_subtiles"], saved["max_workgroups"])
+    M.mjd_ctx_set_tuning(ctx, saved["seg_subtiles"], saved["workgroups"], saved["shape"])
+    log("timing batched and per-image launches")
     res["plan"] = batch.info()
     batch.launch(use_graph=True)
     torch.cuda.synchronize()
@@ -145,6 +160,9 @@ def batch_workload(args, M, ctx, dev, stream):
                                                  args.batch_reps))
     res["fancy_batched_direct"] = rate(_events_ms(torch, stream, lambda: batch.launch(use_graph=False),
                                                   args.batch_reps))
+
+    # the per-image launches run with the library's default launch shape
+    M.mjd_ctx_set_tuning(ctx, 0, 0, 0)
 
     def per_image():
         for frame, c, q, o, pitch, _ in imgs:
@@ -178,6 +196,7 @@ def batch_workload(args, M, ctx, dev, stream):
                                                   args.batch_reps))
     simple.close()
     batch.close()
+    M.mjd_ctx_set_tuning(ctx, saved["seg_subtiles"], saved["workgroups"], saved["shape"])
     return res
 
 
@@ -805,14 +824,13 @@ def main():
     o_sets = [torch.empty((H, W, 3), dtype=torch.uint8, device=dev) for _ in range(args.sets)]
     stream = torch.cuda.current_stream()
 
-    if args.tune:
+    tuning = None
+    if not args.no_tune:
         from paper_1311_5304_amd import autotune
-        best, table = autotune.tune(ctx, frame, c_sets, q_dev, M.MJD_UPSAMPLE_FANCY, o_sets,
-                                    wg_candidates=(0, 256, 512, 768, 1024))
-        M.mjd_ctx_set_tuning(ctx, best["seg_subtiles"], best["max_workgroups"])
-        tuned = {"best": best, "table": table}
-    else:
-        tuned = None
+        log("headline launch shape (tuning cache, else the autotuner)")
+        entry, source = autotune.tuned_image(ctx, frame, M.MJD_UPSAMPLE_FANCY, c_sets, q_dev, o_sets,
+                                             retune=args.retune)
+        tuning = tuning_report(entry, source)
 
     def step(i):
         k = i % args.sets
@@ -838,12 +856,14 @@ def main():
 
     # parity spot check of the timed output against the oracle (full image)
     out = {}
-    extras = {"generation_s": round(gen_s, 2), "tuning": M.mjd_ctx_get_tuning(ctx)}
-    if tuned:
-        extras["autotune"] = tuned
+    extras = {"generation_s": round(gen_s, 2), "tuning": tuning or {"source": "library default",
+                                                                     **M.mjd_ctx_get_tuning(ctx)}}
     if ref is not None:
         gpu_out = o_sets[(args.steps - 1) % args.sets].cpu().numpy()
         extras["bit_exact_vs_oracle"] = bool(np.array_equal(gpu_out, ref))
+
+    # the workloads below decode other sizes: library default launch shape
+    M.mjd_ctx_set_tuning(ctx, 0, 0, 0)
 
     # copy-kernel bandwidth over the same byte count (read half, write half)
     n = (algo_bytes // 2) // 16 * 16

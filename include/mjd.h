@@ -103,26 +103,60 @@ typedef struct mjd_geometry {
 typedef struct mjd_ctx mjd_ctx;
 
 /* Launch shape of the decode kernels (paper Sec. 4.1 and Sec. 5: the best
- * work-group size is hardware specific and chosen by profiling).  A
- * workgroup walks a segment of `seg_subtiles` consecutive sub-tile rows of
- * one strip of MCU columns, prefetching the next sub-tile while it decodes
- * the current one; at most `max_workgroups` workgroups are launched and each
- * takes further segments when it finishes one.  0 in either field selects
- * the automatic choice (enough segments to fill every resident slot once).
+ * work-group size is hardware specific and chosen by profiling).  The image
+ * is cut into strips of sub-tiles; a workgroup walks a segment of
+ * `seg_subtiles` consecutive sub-tile rows of one strip, prefetching the
+ * next sub-tile while it decodes the current one, and takes further
+ * segments when it finishes one.
+ *   seg_subtiles  sub-tile rows per segment; 0: the automatic choice
+ *                 (single image: enough segments to fill every resident
+ *                 slot once; batch: about four segments per slot).
+ *   workgroups    workgroups launched; 0: as many as the device keeps
+ *                 resident.  A larger count is allowed: the extra
+ *                 workgroups start as resident ones finish.  Never more
+ *                 than there are segments.
+ *   shape         sub-tile shape of the single-image kernel, an index into
+ *                 the sampling class's list (mjd_shape_count /
+ *                 mjd_shape_info); 0 is the class's default, and an index
+ *                 past the end of a class's list selects that default.  The
+ *                 batch kernel has one fixed shape per class.
  * The values change only speed, never the output. */
 typedef struct mjd_tuning {
   uint32_t seg_subtiles;
-  uint32_t max_workgroups;
+  uint32_t workgroups;
+  uint32_t shape;
 } mjd_tuning;
+
+/* One sub-tile shape of the single-image kernel. */
+typedef struct mjd_shape {
+  uint32_t mcus_x;          /* sub-tile width in MCUs */
+  uint32_t mcus_y;          /* sub-tile height in MCUs */
+  uint32_t threads;         /* lanes per workgroup */
+  uint32_t lds_bytes;       /* LDS per workgroup */
+  uint32_t resident_per_cu; /* workgroups one compute unit holds at once */
+  uint32_t cu_count;        /* compute units of the context's device */
+} mjd_shape;
 
 /* Create a context on HIP device `device` (makes it current while creating). */
 int mjd_ctx_create(mjd_ctx** out, int device);
 /* Release a context and its device workspace.  Synchronises the device. */
 void mjd_ctx_destroy(mjd_ctx* ctx);
 
-/* Set / read the context's launch shape (see mjd_tuning).  Host only. */
+/* Set / read the context's launch shape (see mjd_tuning).  Host only.
+ * Returns MJD_EINVAL for null pointers, seg_subtiles > 65536,
+ * workgroups > 2^20 or shape > 255. */
 int mjd_ctx_set_tuning(mjd_ctx* ctx, const mjd_tuning* tuning);
 int mjd_ctx_get_tuning(const mjd_ctx* ctx, mjd_tuning* tuning);
+
+/* The sub-tile shapes the autotuner searches (paper Sec. 4.1: work-group
+ * size per platform by profiling) for the sampling class of luma factors
+ * h x v (1x1, 2x1 or 2x2, chroma 1x1) and upsampling mode.
+ * mjd_shape_count: host only, writes the number of shapes to *count.
+ * mjd_shape_info: fills *out for shape `index`, with the occupancy on the
+ * context's device.  Return MJD_EINVAL for null pointers, an unknown mode or
+ * an index past the list, MJD_EUNSUPPORTED for other sampling factors. */
+int mjd_shape_count(uint32_t h, uint32_t v, int upsample, uint32_t* count);
+int mjd_shape_info(mjd_ctx* ctx, uint32_t h, uint32_t v, int upsample, uint32_t index, mjd_shape* out);
 
 /* Host-only: validate `frame` and compute its geometry.  Needs no GPU.
  * Returns MJD_EINVAL for null pointers or out-of-range fields and

@@ -9,7 +9,7 @@ from ._binding import (MJD_IDCT_FLOAT, MJD_IDCT_IFAST, MJD_IDCT_ISLOW, MJD_PART_
                        Batch, Context, EntropyBatch, Hetero, MjdError, Pipeline, Server, make_variant, mjd_decode_variant, mjd_partition_rows,
                        mjd_repartition_rows, mjd_variant, mjd_variant_geometry,
                        mjd_batch_create, mjd_batch_destroy, mjd_batch_launch, mjd_decode_batch_noalloc,
-                       mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning,
+                       mjd_copy, mjd_ctx_create, mjd_ctx_destroy, mjd_ctx_get_tuning, mjd_ctx_set_tuning, mjd_shape_count, mjd_shape_info,
                        mjd_decode, mjd_decode_host, mjd_entropy_batch_create, mjd_entropy_batch_destroy,
                        mjd_entropy_batch_info, mjd_entropy_batch_launch, mjd_entropy_batch_status,
                        mjd_entropy_decode, mjd_geometry_of, mjd_model, mjd_model_predict, mjd_poly1, mjd_poly2,

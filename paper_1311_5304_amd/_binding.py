@@ -57,7 +57,12 @@ class mjd_geometry(ctypes.Structure):
 
 
 class mjd_tuning(ctypes.Structure):
-    _fields_ = [("seg_subtiles", ctypes.c_uint32), ("max_workgroups", ctypes.c_uint32)]
+    _fields_ = [("seg_subtiles", ctypes.c_uint32), ("workgroups", ctypes.c_uint32), ("shape", ctypes.c_uint32)]
+
+
+class mjd_shape(ctypes.Structure):
+    _fields_ = [("mcus_x", ctypes.c_uint32), ("mcus_y", ctypes.c_uint32), ("threads", ctypes.c_uint32),
+                ("lds_bytes", ctypes.c_uint32), ("resident_per_cu", ctypes.c_uint32), ("cu_count", ctypes.c_uint32)]
 
 
 class mjd_job(ctypes.Structure):
@@ -176,6 +181,10 @@ def lib() -> ctypes.CDLL:
         L.mjd_ctx_set_tuning.restype = i32
         L.mjd_ctx_get_tuning.argtypes = [vp, ctypes.POINTER(mjd_tuning)]
         L.mjd_ctx_get_tuning.restype = i32
+        L.mjd_shape_count.argtypes = [u32, u32, i32, ctypes.POINTER(u32)]
+        L.mjd_shape_count.restype = i32
+        L.mjd_shape_info.argtypes = [vp, u32, u32, i32, u32, ctypes.POINTER(mjd_shape)]
+        L.mjd_shape_info.restype = i32
         L.mjd_batch_create.argtypes = [vp, ctypes.POINTER(mjd_job), sz, i32, ctypes.POINTER(vp)]
         L.mjd_batch_create.restype = i32
         L.mjd_batch_launch.argtypes = [vp, i32, vp]
@@ -343,15 +352,27 @@ def mjd_ctx_destroy(ctx: Context):
     ctx.close()
 
 
-def mjd_ctx_set_tuning(ctx: Context, seg_subtiles: int = 0, max_workgroups: int = 0):
-    t = mjd_tuning(int(seg_subtiles), int(max_workgroups))
+def mjd_ctx_set_tuning(ctx: Context, seg_subtiles: int = 0, workgroups: int = 0, shape: int = 0):
+    t = mjd_tuning(int(seg_subtiles), int(workgroups), int(shape))
     _check(lib().mjd_ctx_set_tuning(ctx.handle, ctypes.byref(t)))
 
 
 def mjd_ctx_get_tuning(ctx: Context) -> dict:
     t = mjd_tuning()
     _check(lib().mjd_ctx_get_tuning(ctx.handle, ctypes.byref(t)))
-    return {"seg_subtiles": t.seg_subtiles, "max_workgroups": t.max_workgroups}
+    return {"seg_subtiles": t.seg_subtiles, "workgroups": t.workgroups, "shape": t.shape}
+
+
+def mjd_shape_count(h: int, v: int, upsample: int) -> int:
+    n = ctypes.c_uint32()
+    _check(lib().mjd_shape_count(int(h), int(v), int(upsample), ctypes.byref(n)))
+    return n.value
+
+
+def mjd_shape_info(ctx: Context, h: int, v: int, upsample: int, index: int) -> dict:
+    s = mjd_shape()
+    _check(lib().mjd_shape_info(ctx.handle, int(h), int(v), int(upsample), int(index), ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in mjd_shape._fields_}
 
 
 def mjd_decode(ctx: Context, frame, coef, qt, upsample: int, rgb, pitch: int,

@@ -104,7 +104,7 @@ int mjd_decode(mjd_ctx* ctx, const mjd_frame* frame, const int16_t* d_coef, cons
 int mjd_ctx_set_tuning(mjd_ctx* ctx, const mjd_tuning* tuning) {
   mjd::clear_error();
   if (!ctx || !tuning) return mjd::fail(MJD_EINVAL, "null context or tuning");
-  if (tuning->seg_subtiles > 65536 || tuning->max_workgroups > (1u << 20))
+  if (tuning->seg_subtiles > 65536 || tuning->workgroups > (1u << 20) || tuning->shape > 255)
     return mjd::fail(MJD_EINVAL, "tuning values out of range");
   ctx->tuning = *tuning;
   return MJD_OK;
@@ -114,6 +114,48 @@ int mjd_ctx_get_tuning(const mjd_ctx* ctx, mjd_tuning* tuning) {
   mjd::clear_error();
   if (!ctx || !tuning) return mjd::fail(MJD_EINVAL, "null context or tuning");
   *tuning = ctx->tuning;
+  return MJD_OK;
+}
+
+static int shape_class(uint32_t h, uint32_t v, int upsample) {
+  if (upsample != MJD_UPSAMPLE_SIMPLE && upsample != MJD_UPSAMPLE_FANCY)
+    return mjd::fail(MJD_EINVAL, "upsample mode %d unknown", upsample);
+  if (!((h == 1 && v == 1) || (h == 2 && v == 1) || (h == 2 && v == 2)))
+    return mjd::fail(MJD_EUNSUPPORTED, "no fused kernel for luma sampling %ux%u", h, v);
+  return MJD_OK;
+}
+
+int mjd_shape_count(uint32_t h, uint32_t v, int upsample, uint32_t* count) {
+  mjd::clear_error();
+  if (!count) return mjd::fail(MJD_EINVAL, "null count");
+  const int rc = shape_class(h, v, upsample);
+  if (rc != MJD_OK) return rc;
+  *count = static_cast<uint32_t>(mjd::shape_count(static_cast<int>(h), static_cast<int>(v), upsample == MJD_UPSAMPLE_FANCY));
+  return MJD_OK;
+}
+
+int mjd_shape_info(mjd_ctx* ctx, uint32_t h, uint32_t v, int upsample, uint32_t index, mjd_shape* out) {
+  mjd::clear_error();
+  if (!ctx || !out) return mjd::fail(MJD_EINVAL, "null context or shape");
+  const int rc = shape_class(h, v, upsample);
+  if (rc != MJD_OK) return rc;
+  const bool fancy = upsample == MJD_UPSAMPLE_FANCY;
+  const int n = mjd::shape_count(static_cast<int>(h), static_cast<int>(v), fancy);
+  if (index >= static_cast<uint32_t>(n)) return mjd::fail(MJD_EINVAL, "shape %u outside 0..%d", index, n - 1);
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != ctx->device) (void)hipSetDevice(ctx->device);
+  int sx, sy, nt, lds, per_cu;
+  const hipError_t e = mjd::shape_info(static_cast<int>(h), static_cast<int>(v), fancy, static_cast<int>(index), &sx,
+                                       &sy, &nt, &lds, &per_cu);
+  if (cur != ctx->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return mjd::fail(MJD_EDEVICE, "occupancy query failed: %s", hipGetErrorString(e));
+  out->mcus_x = static_cast<uint32_t>(sx);
+  out->mcus_y = static_cast<uint32_t>(sy);
+  out->threads = static_cast<uint32_t>(nt);
+  out->lds_bytes = static_cast<uint32_t>(lds);
+  out->resident_per_cu = static_cast<uint32_t>(per_cu);
+  out->cu_count = static_cast<uint32_t>(ctx->cu_count);
   return MJD_OK;
 }
 

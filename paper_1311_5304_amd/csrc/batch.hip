@@ -182,8 +182,11 @@ int batch_plan(mjd_ctx* ctx, const mjd_job* jobs, size_t n, int upsample, BatchP
     return (a.r1 - a.r0) > (c.r1 - c.r0);
   });
   if (plan->items.size() > 0x7FFFFFF0u) return fail(MJD_EINVAL, "batch needs too many segments");
-  int grid = std::min(static_cast<int>(plan->items.size()), slots);
-  if (ctx->tuning.max_workgroups > 0) grid = std::min(grid, static_cast<int>(ctx->tuning.max_workgroups));
+  // every resident slot by default; a tuned count may be smaller or larger
+  // (workgroups beyond the resident ones start as others leave and find
+  // what is left of the queue)
+  int grid = ctx->tuning.workgroups > 0 ? static_cast<int>(ctx->tuning.workgroups) : slots;
+  grid = std::min(grid, static_cast<int>(plan->items.size()));
   plan->grid = grid;
   return MJD_OK;
 }

@@ -38,22 +38,20 @@ __global__ __launch_bounds__(C::NT, C::WAVES_PER_SIMD) void decode_segments(cons
   }
 }
 
-// Sub-tile shapes: a sub-tile's blocks fill whole waves (one block per lane)
-// and the neighbour-column tasks of the fancy filter take the remaining
-// lanes of the workgroup.
-using Cfg420F = SegCfg<2, 2, true, 16, 2, 256>;
-using Cfg420S = SegCfg<2, 2, false, 16, 2, 192>;
-using Cfg422F = SegCfg<2, 1, true, 16, 2, 192>;
-using Cfg422S = SegCfg<2, 1, false, 16, 2, 128>;
-using Cfg444 = SegCfg<1, 1, false, 16, 4, 192>;
+template <class C>
+static hipError_t resident_per_cu(int* per_cu) {
+  *per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, decode_segments<C>, C::NT, 0);
+  if (e == hipSuccess && *per_cu < 1) *per_cu = 1;
+  return e;
+}
 
 template <class C>
 static hipError_t launch_cfg(const ImageView& im, int row0, int row1, int cu_count, const mjd_tuning& tu,
                              hipStream_t stream) {
   int per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_segments<C>, C::NT, 0);
+  hipError_t e = resident_per_cu<C>(&per_cu);
   if (e != hipSuccess) return e;
-  if (per_cu < 1) per_cu = 1;
   const int slots = per_cu * (cu_count > 0 ? cu_count : 256);
   SegGrid sg;
   sg.row0 = row0;
@@ -74,21 +72,82 @@ static hipError_t launch_cfg(const ImageView& im, int row0, int row1, int cu_cou
   sg.seg_rows = seg_sub * C::SY;
   sg.segs_per_strip = (rows + sg.seg_rows - 1) / sg.seg_rows;
   sg.segments = sg.strips * sg.segs_per_strip;
-  int grid = sg.segments < slots ? sg.segments : slots;
-  if (tu.max_workgroups > 0 && grid > static_cast<int>(tu.max_workgroups)) grid = static_cast<int>(tu.max_workgroups);
+  // the grid: every resident slot by default; a tuned count may be smaller
+  // or larger (workgroups beyond the resident ones start as others finish)
+  int grid = tu.workgroups > 0 ? static_cast<int>(tu.workgroups) : slots;
+  if (grid > sg.segments) grid = sg.segments;
   grid = (grid + 7) & ~7;
   hipLaunchKernelGGL(decode_segments<C>, dim3(grid), dim3(C::NT), 0, stream, im, sg);
   return hipGetLastError();
 }
 
+// Sub-tile shapes of each sampling class, the default first.  A sub-tile's
+// blocks fill whole waves (one block per lane: SX * SY * blocks-per-MCU is a
+// multiple of 64) and the neighbour-column tasks of the fancy filter take
+// the remaining lanes of the workgroup; the 4:2:0 fancy class further needs
+// its row pairs to fill the workgroup (NT = 4 * SY * 2 * SX), which leaves
+// no shape with SX = 8.
+struct Shape {
+  int sx, sy, nt, lds_bytes;
+  hipError_t (*launch)(const ImageView&, int, int, int, const mjd_tuning&, hipStream_t);
+  hipError_t (*per_cu)(int*);
+};
+
+template <class C>
+constexpr Shape shape_of() {
+  return Shape{C::SX, C::SY, C::NT, C::LDS_BYTES, &launch_cfg<C>, &resident_per_cu<C>};
+}
+
+static constexpr Shape k420F[] = {shape_of<SegCfg<2, 2, true, 16, 2, 256>>(), shape_of<SegCfg<2, 2, true, 32, 1, 256>>(),
+                                  shape_of<SegCfg<2, 2, true, 16, 4, 512>>()};
+static constexpr Shape k420S[] = {shape_of<SegCfg<2, 2, false, 16, 2, 192>>(), shape_of<SegCfg<2, 2, false, 32, 1, 192>>(),
+                                  shape_of<SegCfg<2, 2, false, 8, 4, 192>>(), shape_of<SegCfg<2, 2, false, 16, 4, 384>>()};
+static constexpr Shape k422F[] = {shape_of<SegCfg<2, 1, true, 16, 2, 192>>(), shape_of<SegCfg<2, 1, true, 32, 1, 192>>(),
+                                  shape_of<SegCfg<2, 1, true, 8, 4, 256>>(), shape_of<SegCfg<2, 1, true, 16, 1, 128>>()};
+static constexpr Shape k422S[] = {shape_of<SegCfg<2, 1, false, 16, 2, 128>>(), shape_of<SegCfg<2, 1, false, 32, 1, 128>>(),
+                                  shape_of<SegCfg<2, 1, false, 8, 4, 128>>(), shape_of<SegCfg<2, 1, false, 16, 4, 256>>()};
+static constexpr Shape k444[] = {shape_of<SegCfg<1, 1, false, 16, 4, 192>>(), shape_of<SegCfg<1, 1, false, 32, 2, 192>>(),
+                                 shape_of<SegCfg<1, 1, false, 8, 8, 192>>(), shape_of<SegCfg<1, 1, false, 16, 8, 384>>()};
+
+template <size_t N>
+static void pick(const Shape (&l)[N], const Shape** list, int* n) {
+  *list = l;
+  *n = static_cast<int>(N);
+}
+
+// The shape list of a sampling class (hf, vf in {1, 2}).
+static void class_shapes(int hf, int vf, bool fancy, const Shape** list, int* n) {
+  if (hf == 1 && vf == 1) return pick(k444, list, n);
+  if (hf == 2 && vf == 1) return fancy ? pick(k422F, list, n) : pick(k422S, list, n);
+  return fancy ? pick(k420F, list, n) : pick(k420S, list, n);
+}
+
+int shape_count(int hf, int vf, bool fancy) {
+  const Shape* l;
+  int n;
+  class_shapes(hf, vf, fancy, &l, &n);
+  return n;
+}
+
+hipError_t shape_info(int hf, int vf, bool fancy, int index, int* sx, int* sy, int* nt, int* lds_bytes, int* per_cu) {
+  const Shape* l;
+  int n;
+  class_shapes(hf, vf, fancy, &l, &n);
+  const Shape& s = l[index];
+  *sx = s.sx;
+  *sy = s.sy;
+  *nt = s.nt;
+  *lds_bytes = s.lds_bytes;
+  return s.per_cu(per_cu);
+}
+
 hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf, bool fancy, int cu_count,
                         const mjd_tuning& tu, hipStream_t stream) {
-  if (hf == 1 && vf == 1) return launch_cfg<Cfg444>(im, row0, row1, cu_count, tu, stream);
-  if (hf == 2 && vf == 1)
-    return fancy ? launch_cfg<Cfg422F>(im, row0, row1, cu_count, tu, stream)
-                 : launch_cfg<Cfg422S>(im, row0, row1, cu_count, tu, stream);
-  return fancy ? launch_cfg<Cfg420F>(im, row0, row1, cu_count, tu, stream)
-               : launch_cfg<Cfg420S>(im, row0, row1, cu_count, tu, stream);
+  const Shape* l;
+  int n;
+  class_shapes(hf, vf, fancy, &l, &n);
+  const int i = static_cast<int>(tu.shape) < n ? static_cast<int>(tu.shape) : 0;
+  return l[i].launch(im, row0, row1, cu_count, tu, stream);
 }
 
 }  // namespace mjd

@@ -15,7 +15,7 @@ struct mjd_ctx {
   int cu_count = 0;
   int xcd_count = 8;
   std::string device_name;
-  mjd_tuning tuning{0, 0};
+  mjd_tuning tuning{0, 0, 0};
   void* noalloc_scratch = nullptr;  // device address of the no-allocation batch scratch on `device`
 };
 
@@ -24,6 +24,11 @@ namespace mjd {
 // Enqueues the segment kernel for MCU rows [row0, row1) of one image.
 hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf, bool fancy, int cu_count,
                         const mjd_tuning& tuning, hipStream_t stream);
+// Sub-tile shapes of the single-image kernel per sampling class: how many,
+// and one's tile (SX x SY MCUs), lanes, LDS bytes and resident workgroups
+// per CU (index < shape_count).
+int shape_count(int hf, int vf, bool fancy);
+hipError_t shape_info(int hf, int vf, bool fancy, int index, int* sx, int* sy, int* nt, int* lds_bytes, int* per_cu);
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 

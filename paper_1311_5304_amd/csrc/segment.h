@@ -561,7 +561,7 @@ struct SegmentDecoder {
   // and the last two rows of sub-tile k-2 (the last of which needs the first
   // row of k-1), as pairs of rows: one pair of rows and 4 samples per lane.
   __device__ void phase2_pairs(int k) const {
-    static_assert(NT == 8 * C::UX, "the row pairs of a sub-tile fill the workgroup once");
+    static_assert(NT == (C::CR / 2) * C::UX, "the row pairs of a sub-tile fill the workgroup once");
     const bool has_a = k >= 1 && k <= K;
     const bool has_b = k >= 2 && k <= K + 1;
     if (!has_a && !has_b) return;

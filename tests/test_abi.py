@@ -66,12 +66,28 @@ def test_geometry_rejects_bad_frames(bad, code):
 
 
 def test_tuning_rejects_null_context():
-    t = B.mjd_tuning(2, 8)
+    t = B.mjd_tuning(2, 8, 1)
     assert B.lib().mjd_ctx_set_tuning(None, ctypes.byref(t)) == B.MJD_EINVAL
     assert B.lib().mjd_ctx_get_tuning(None, ctypes.byref(t)) == B.MJD_EINVAL
+    s = B.mjd_shape()
+    assert B.lib().mjd_shape_info(None, 2, 2, B.MJD_UPSAMPLE_FANCY, 0, ctypes.byref(s)) == B.MJD_EINVAL
 
 
-STRUCTS = [B.mjd_frame, B.mjd_geometry, B.mjd_tuning, B.mjd_job, B.mjd_huffman, B.mjd_scan,
+def test_shape_lists_per_sampling_class():
+    """Every fused sampling class offers several sub-tile shapes to the
+    autotuner; other samplings and modes are refused without a GPU."""
+    for h, v in ((1, 1), (2, 1), (2, 2)):
+        for mode in (B.MJD_UPSAMPLE_SIMPLE, B.MJD_UPSAMPLE_FANCY):
+            assert B.mjd_shape_count(h, v, mode) >= 3
+    with pytest.raises(B.MjdError) as ei:
+        B.mjd_shape_count(1, 2, B.MJD_UPSAMPLE_FANCY)
+    assert ei.value.code == B.MJD_EUNSUPPORTED
+    with pytest.raises(B.MjdError) as ei:
+        B.mjd_shape_count(2, 2, 7)
+    assert ei.value.code == B.MJD_EINVAL
+
+
+STRUCTS = [B.mjd_frame, B.mjd_geometry, B.mjd_tuning, B.mjd_shape, B.mjd_job, B.mjd_huffman, B.mjd_scan,
            B.mjd_pipeline_config, B.mjd_pipeline_stats, B.mjd_server_config, B.mjd_request,
            B.mjd_request_times, B.mjd_entropy_job, B.mjd_poly1, B.mjd_poly2, B.mjd_model, B.mjd_prediction, B.mjd_partition, B.mjd_hetero_times,
            B.mjd_hetero_plan, B.mjd_variant]

@@ -59,7 +59,9 @@ def _device_jobs(batch_inputs):
 def test_batch_matches_oracle(M, ctx, batch_inputs, mode):
     exp = [oracle.decode(f, c, q, mode) for f, c, q in batch_inputs]
     jobs, outs = _device_jobs(batch_inputs)
-    for seg, wgs, graph in ((0, 0, False), (1, 0, False), (3, 8, False), (0, 0, True), (2, 16, True)):
+    # workgroups 2048: more than stay resident, the rest start as others leave
+    for seg, wgs, graph in ((0, 0, False), (1, 0, False), (3, 8, False), (0, 0, True), (2, 16, True),
+                            (1, 2048, False), (1, 2048, True)):
         M.mjd_ctx_set_tuning(ctx, seg, wgs)
         say(f"batch {mode} seg={seg} wgs={wgs} graph={graph}")
         b = M.Batch(ctx, jobs, M.UPSAMPLE[mode])

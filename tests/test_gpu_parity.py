@@ -167,10 +167,28 @@ def test_unaligned_output_pitch_and_base(M, ctx, samp, mode):
 
 
 def test_large_420_fancy_full_image_bit_exact(M, ctx):
+    """The headline image whole, under the library's default launch, under
+    every sub-tile shape at the launch sizes the autotuner searches (fewer,
+    as many and more workgroups than stay resident), and under the launch
+    the tuning cache holds for this workload on this device, if any."""
+    from paper_1311_5304_amd import autotune
     say("4096x3072 4:2:0 q90 fancy (full image)")
     frame, coef, qt = workloads.large_420_fancy()
-    assert_same(gpu_decode(M, ctx, frame, coef, qt, "fancy"), oracle.decode(frame, coef, qt, "fancy"),
-                "4096x3072 fancy")
+    exp = oracle.decode(frame, coef, qt, "fancy")
+    assert_same(gpu_decode(M, ctx, frame, coef, qt, "fancy"), exp, "4096x3072 fancy")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    try:
+        for shape in range(M.mjd_shape_count(2, 2, M.MJD_UPSAMPLE_FANCY)):
+            for seg, k in ((3, 2), (1, 1), (6, 4)):
+                M.mjd_ctx_set_tuning(ctx, seg, k * cus, shape)
+                say(f"4096x3072 fancy shape {shape} seg {seg} workgroups {k * cus}")
+                assert_same(gpu_decode(M, ctx, frame, coef, qt, "fancy"), exp,
+                            f"4096x3072 fancy shape={shape} seg={seg} wgs={k * cus}")
+        if autotune.apply_cached(ctx, frame, M.MJD_UPSAMPLE_FANCY):
+            say(f"4096x3072 fancy cached tuning {M.mjd_ctx_get_tuning(ctx)}")
+            assert_same(gpu_decode(M, ctx, frame, coef, qt, "fancy"), exp, "4096x3072 fancy, cached tuning")
+    finally:
+        M.mjd_ctx_set_tuning(ctx, 0, 0, 0)
 
 
 @pytest.mark.parametrize("w,h,samp", [(65535, 16, "420"), (16, 65535, "422"), (65535, 9, "444")])
@@ -211,28 +229,33 @@ def test_copy_probe_copies(M, ctx):
 @pytest.mark.parametrize("samp,mode", [("420", "fancy"), ("420", "simple"), ("422", "fancy"),
                                        ("422", "simple"), ("444", "simple")])
 def test_launch_shapes_bit_exact(M, ctx, samp, mode):
-    """Segments of several sub-tiles (the prefetch pipeline and the chroma
-    ring), few workgroups (each takes many segments), and bands: the output
+    """Every sub-tile shape of the class, segments of several sub-tiles (the
+    prefetch pipeline and the chroma ring), few workgroups (each takes many
+    segments), more workgroups than stay resident, and bands: the output
     never depends on the launch shape."""
     rgb = images.texture_rgb(523, 437, 31, sigma=12)
     frame, coef, qt = encode.encode_rgb(rgb, samp, 83)
     exp = oracle.decode(frame, coef, qt, mode)
     g = oracle.geometry(frame)
     c, q = to_dev(coef, qt)
+    h, v = frame["h"][0], frame["v"][0]
+    n_shapes = M.mjd_shape_count(h, v, M.UPSAMPLE[mode])
     try:
-        for seg, wgs in ((1, 0), (2, 0), (3, 8), (7, 0), (64, 0), (5, 16), (0, 8)):
-            M.mjd_ctx_set_tuning(ctx, seg, wgs)
-            say(f"shape {samp} {mode} seg_subtiles={seg} max_workgroups={wgs}")
-            out = M.decode(ctx, frame, c, q, mode)
-            torch.cuda.synchronize()
-            assert_same(out.cpu().numpy(), exp, f"{samp} {mode} seg={seg} wgs={wgs}")
-            for r0, r1 in ((3, g["mcus_y"] - 2), (g["mcus_y"] - 5, g["mcus_y"])):
-                band = torch.full((frame["height"], frame["width"], 3), 5, dtype=torch.uint8, device="cuda")
-                M.decode(ctx, frame, c, q, mode, out=band, rows=(r0, r1))
+        for shape in range(n_shapes):
+            info = M.mjd_shape_info(ctx, h, v, M.UPSAMPLE[mode], shape)
+            for seg, wgs in ((1, 0), (2, 0), (3, 8), (7, 0), (64, 0), (5, 16), (0, 8), (1, 4096)):
+                M.mjd_ctx_set_tuning(ctx, seg, wgs, shape)
+                say(f"shape {samp} {mode} {info} seg_subtiles={seg} workgroups={wgs}")
+                out = M.decode(ctx, frame, c, q, mode)
                 torch.cuda.synchronize()
-                got = band.cpu().numpy()
-                y0, y1 = r0 * g["mcu_h"], min(frame["height"], r1 * g["mcu_h"])
-                assert_same(got[y0:y1], exp[y0:y1], f"band {r0}..{r1} seg={seg} wgs={wgs}")
-                assert np.all(got[:y0] == 5) and np.all(got[y1:] == 5)
+                assert_same(out.cpu().numpy(), exp, f"{samp} {mode} shape={shape} seg={seg} wgs={wgs}")
+                for r0, r1 in ((3, g["mcus_y"] - 2), (g["mcus_y"] - 5, g["mcus_y"])):
+                    band = torch.full((frame["height"], frame["width"], 3), 5, dtype=torch.uint8, device="cuda")
+                    M.decode(ctx, frame, c, q, mode, out=band, rows=(r0, r1))
+                    torch.cuda.synchronize()
+                    got = band.cpu().numpy()
+                    y0, y1 = r0 * g["mcu_h"], min(frame["height"], r1 * g["mcu_h"])
+                    assert_same(got[y0:y1], exp[y0:y1], f"band {r0}..{r1} shape={shape} seg={seg} wgs={wgs}")
+                    assert np.all(got[:y0] == 5) and np.all(got[y1:] == 5)
     finally:
         M.mjd_ctx_set_tuning(ctx, 0, 0)
