@@ -289,7 +289,8 @@ def model_workload(args, M, ctx, dev):
     to 25 MP (qualities 50-95, texture and gradient content, like the paper's
     crops of a few photographs to many sizes), each timed in its four phases;
     then a held-out set of 16 other images (1-24 MP, inside the training
-    grid), predicted and measured."""
+    grid), predicted and measured, the host parts of the partitioning
+    (p_cpu, t_dispatch) at each one's quarter splits too."""
     import torch
 
     from paper_1311_5304_amd import perfmodel
@@ -325,6 +326,7 @@ def model_workload(args, M, ctx, dev):
     model, info = perfmodel.fit(train)
     log("performance model: held-out images")
     errs = {"t_huff": [], "p_gpu": [], "total": []}
+    held_out = []
     for i in range(16):
         while True:  # inside the training domain
             mp = rng.uniform(1.0, 24.0)
@@ -335,17 +337,30 @@ def model_workload(args, M, ctx, dev):
                 break
         q = int(rng.integers(50, 96))
         content = "texture" if i % 2 == 0 else "gradient"
-        s = perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(8, i), content), reps=3)
+        s = perfmodel.measure(ctx, bitstream(w, h, q, workloads.seed_of(8, i), content), reps=3, hetero=hetero)
+        held_out.append(s)
         p = perfmodel.predict(model, s["width"], s["height"], s["bytes"])
         meas = {"t_huff": s["t_huff"], "p_gpu": s["o_w"] + s["t_kernel"] + s["o_r"]}
         meas["total"] = meas["t_huff"] + meas["p_gpu"]
         for key in errs:
             errs[key].append(abs(p[key] - meas[key]) / meas[key])
+    # the host parts of the partitioning at the held-out images' quarter splits
+    errs.update(perfmodel.host_errors(model, held_out))
+    abs_us = {k: round(float(np.mean(v)) * 1e6, 2) for k, v in perfmodel.host_errors(model, held_out, True).items()}
+
+    def pct(v):
+        return {q: round(float(np.percentile(v, q)) * 1e6, 2) for q in (10, 50, 90, 100)}
+    host_spread = {"training_us": {k: pct(v) for k, v in perfmodel.host_times(train).items()},
+                   "held_out_us": {k: pct(v) for k, v in perfmodel.host_times(held_out).items()},
+                   "held_out_mean_abs_error_us": abs_us}
     part = partition_experiment(M, model, hetero, n_threads, bitstream, workloads)
     hetero.close()
     return {
         "training_images": len(train), "held_out_images": 16,
         "degrees_and_aic": {k: {"degree": v[0], "aic": round(v[1], 1)} for k, v in info.items()},
+        "host_parts": {**host_spread, "max_degree": perfmodel.HOST_MAX_DEGREE, "monotone_in_rows": {
+            k: perfmodel.rows_monotone(getattr(model, k), 1.0, 6656 / 1024.0, 4224 / 1024.0)
+            for k in perfmodel.HOST_PARTS}},
         "held_out_abs_rel_error": {k: {"mean": round(float(np.mean(v)), 4), "max": round(float(np.max(v)), 4)}
                                    for k, v in errs.items()},
         "profiling_s": round(time.time() - t0, 1),
@@ -381,8 +396,14 @@ def partition_experiment(M, model, hetero, n_threads, bitstream, workloads):
                 if best is None or t["total_s"] < best["total_s"]:
                     best = t
             if dst is not ref:
-                same[0] &= bool(torch.equal(dst, ref))
+                # numpy, one thread: torch's CPU ops would leave its OpenMP
+                # threads spinning on the cores the next runs' host side uses
+                same[0] &= bool(np.array_equal(dst.numpy(), ref.numpy()))
             return best
+
+        # warm the host pool and the caches on this image before timing it
+        for _ in range(3):
+            hetero.decode(jpg, rgb, 3 * w, h // 2 // mcu_h * mcu_h, M.MJD_PART_SPS, M.MJD_UPSAMPLE_FANCY)
 
         def ms(t):
             return {(k[:-2] + "_ms" if k.endswith("_s") else k): (round(v * 1e3, 3) if k.endswith("_s") else v)
@@ -395,8 +416,11 @@ def partition_experiment(M, model, hetero, n_threads, bitstream, workloads):
                  "predicted_cpu_side_ms": round(p["t_cpu"] * 1e3, 3),
                  "predicted_gpu_side_ms": round(p["t_gpu"] * 1e3, 3)}
             if sides:
-                d["measured_cpu_side_ms"] = round((t["dispatch_s"] + t["huff_cpu_s"] + t["cpu_s"]) * 1e3, 3)
+                cpu_side = t["dispatch_s"] + t["huff_cpu_s"] + t["cpu_s"]
+                d["measured_cpu_side_ms"] = round(cpu_side * 1e3, 3)
                 d["measured_gpu_side_ms"] = round(t["gpu_s"] * 1e3, 3)
+                d["cpu_side_rel_error"] = round((cpu_side - p["t_cpu"]) / p["t_cpu"], 4) if p["t_cpu"] else None
+                d["gpu_side_rel_error"] = round((t["gpu_s"] - p["t_gpu"]) / p["t_gpu"], 4) if p["t_gpu"] else None
             d.update(ms(t))
             d["speedup_vs_gpu_only"] = round(gpu_only["total_s"] / t["total_s"], 3)
             return d

@@ -262,7 +262,11 @@ typedef struct mjd_hetero_times {
 } mjd_hetero_times;
 
 /* max_blocks / max_pixels: the largest image; n_threads (1..256) host
- * threads for Huffman decoding and the CPU rows. */
+ * threads for Huffman decoding and the CPU rows (the caller's thread is one
+ * of them).  When the process may run on at least n_threads CPUs, each
+ * thread is pinned to a CPU of its own (the caller's thread only while a
+ * decode runs, its affinity restored afterwards), so the host side runs on
+ * as many distinct cores as the performance model was fitted with. */
 int mjd_hetero_create(mjd_ctx* ctx, uint64_t max_blocks, uint64_t max_pixels, int n_threads, mjd_hetero** out);
 
 /* How one image is shared. */

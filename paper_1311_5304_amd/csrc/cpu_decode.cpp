@@ -13,9 +13,9 @@
 //   16x scale;
 // - colour (Sec. 4.3, Algorithm 2): constants round(k * 2^16), one rounding
 //   per chroma term, clamp.
-// Bands run on n host threads; each thread decodes the component block rows
-// its output rows need (one chroma row more above and below for fancy
-// filtering).
+// Host threads first transform every block row the output needs into shared
+// planes, then form the output rows from them, both from queues of small
+// tasks.
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "cpu_decode.h"
+#include "host_pool.h"
 #include "mjd.h"
 #include "mjd_common.h"
 
@@ -109,58 +110,58 @@ struct Plan {
   int bpm;
 };
 
-// Sample rows [r0, r1) of component c, decoded into rows of `plane`
-// (stride bw*8, row 0 = component row r0 rounded down to a block row).
-struct CompRows {
+// Block rows [br0, br1) of component c, transformed into `plane` (stride
+// bw*8 samples, plane row 0 = sample row 8*br0).
+struct CompPlane {
   std::vector<uint8_t> plane;
-  int row0 = 0;  // component row of plane row 0
+  int br0 = 0, br1 = 0;
   size_t stride = 0;
 };
 
-static void decode_comp_rows(const Plan& p, const int16_t* coef, const uint16_t* qt, int c, int r0, int r1,
-                             CompRows* out) {
-  const int br0 = r0 / 8, br1 = (r1 + 7) / 8;
+static void decode_block_row(const Plan& p, const int16_t* coef, const uint16_t* qt, int c, int br,
+                             CompPlane* out) {
   const int hc = p.f.h[c], vc = p.f.v[c];
-  out->row0 = 8 * br0;
-  out->stride = static_cast<size_t>(p.bw[c]) * 8;
-  out->plane.assign(static_cast<size_t>(br1 - br0) * 8 * out->stride, 0);
   const uint16_t* q = qt + 64 * p.f.qsel[c];
-  for (int br = br0; br < br1; ++br) {
-    const int my = br / vc, by = br % vc;
-    for (int bx = 0; bx < p.bw[c]; ++bx) {
-      const int mx = bx / hc, bxi = bx % hc;
-      const size_t mcu = static_cast<size_t>(my) * p.g.mcus_x + mx;
-      const int16_t* blk = coef + (mcu * p.bpm + p.first[c] + by * hc + bxi) * 64;
-      idct_block(blk, q, &out->plane[static_cast<size_t>(br - br0) * 8 * out->stride + 8 * bx], out->stride);
-    }
+  const int my = br / vc, by = br % vc;
+  uint8_t* dst = &out->plane[static_cast<size_t>(br - out->br0) * 8 * out->stride];
+  for (int bx = 0; bx < p.bw[c]; ++bx) {
+    const int mx = bx / hc, bxi = bx % hc;
+    const size_t mcu = static_cast<size_t>(my) * p.g.mcus_x + mx;
+    const int16_t* blk = coef + (mcu * p.bpm + p.first[c] + by * hc + bxi) * 64;
+    idct_block(blk, q, dst + 8 * bx, out->stride);
   }
 }
 
-// Output pixel rows [y0, y1) of the image, row y at rgb + y * pitch.
-static void decode_band(const Plan& p, const int16_t* coef, const uint16_t* qt, bool fancy, int y0, int y1,
-                        uint8_t* rgb, size_t pitch) {
+// Output pixel rows [y0, y1) of the image from the transformed planes, row
+// y at rgb + y * pitch.
+static void output_rows(const Plan& p, const CompPlane* planes, bool fancy, int y0, int y1, uint8_t* rgb,
+                        size_t pitch) {
   const int W = static_cast<int>(p.f.width);
-  CompRows rows[3];
   int fhs[3], fvs[3];
   for (int c = 0; c < 3; ++c) {
     fhs[c] = p.hmax / p.f.h[c];
     fvs[c] = p.vmax / p.f.v[c];
-    const int ch = static_cast<int>(p.g.comp_h[c]);
-    int r0 = y0 / fvs[c], r1 = (y1 - 1) / fvs[c] + 1;
-    if (fancy && fvs[c] == 2) {
-      r0 = std::max(0, r0 - 1);
-      r1 = std::min(ch, r1 + 1);
-    }
-    decode_comp_rows(p, coef, qt, c, r0, r1, &rows[c]);
   }
   std::vector<int> up[3];
   for (int c = 0; c < 3; ++c) up[c].resize(W);
   std::vector<int> srow;
+  // the planes' rows as plain pointers (the output stores are byte stores,
+  // which may alias anything the loops would otherwise reload)
+  const uint8_t* base[3];
+  size_t stride[3];
+  int row0[3];
+  for (int c = 0; c < 3; ++c) {
+    base[c] = planes[c].plane.data();
+    stride[c] = planes[c].stride;
+    row0[c] = 8 * planes[c].br0;
+  }
   for (int y = y0; y < y1; ++y) {
     for (int c = 0; c < 3; ++c) {
-      const CompRows& cr = rows[c];
+      const uint8_t* const pl = base[c];
+      const size_t st = stride[c];
+      const int rz = row0[c];
       const int fh = fhs[c], fv = fvs[c], cw = static_cast<int>(p.g.comp_w[c]), ch = static_cast<int>(p.g.comp_h[c]);
-      auto at = [&](int r, int x) { return static_cast<int>(cr.plane[(r - cr.row0) * cr.stride + x]); };
+      auto at = [=](int r, int x) { return static_cast<int>(pl[(r - rz) * st + x]); };
       int* o = up[c].data();
       if (fh == 1 && fv == 1) {
         for (int x = 0; x < W; ++x) o[x] = at(y, x);
@@ -226,19 +227,70 @@ int mjd::cpu::decode_host_with(const mjd_frame* frame, const int16_t* h_coef, co
   const int mh = static_cast<int>(p.g.mcu_h);
   const int H = static_cast<int>(frame->height);
   const bool fancy = upsample == MJD_UPSAMPLE_FANCY;
-  // split the rows into per-thread bands of whole MCU rows
+  // The rows go in chunks of about 4 MCU rows per thread, so the planes of
+  // a chunk stay in the caches between its two phases.  Phase 1: every
+  // block row the chunk's output rows read (for fancy vertical filtering
+  // one chroma row above and below), transformed once into planes the
+  // threads share; a block row the previous chunk already holds is copied
+  // from it.  Phase 2: the output rows in bands of 8.  Both phases hand out
+  // small tasks, so a thread that is held up delays the chunk by one task at
+  // most.
   const int nrows = static_cast<int>(mcu_row1 - mcu_row0);
-  const int nt = std::min(n_threads, nrows);
-  pf(nt, [&](int t) {
-    const int ra = static_cast<int>(mcu_row0) + nrows * t / nt, rb = static_cast<int>(mcu_row0) + nrows * (t + 1) / nt;
-    const int ya = ra * mh, yb = std::min(H, rb * mh);
-    if (ya < yb) decode_band(p, h_coef, h_qt, fancy, ya, yb, h_rgb, pitch);
-  });
+  const int max_chunk = std::max(8, 4 * n_threads);
+  const int n_chunks = (nrows + max_chunk - 1) / max_chunk;
+  CompPlane bufs[2][3];
+  struct Task {
+    int c, br;
+    bool copy;
+  };
+  std::vector<Task> tasks;
+  for (int k = 0; k < n_chunks; ++k) {
+    CompPlane* cur = bufs[k & 1];
+    const CompPlane* prev = k ? bufs[(k - 1) & 1] : nullptr;
+    const int ra = static_cast<int>(mcu_row0) + nrows * k / n_chunks;
+    const int rb = static_cast<int>(mcu_row0) + nrows * (k + 1) / n_chunks;
+    const int y0 = ra * mh, y1 = std::min(H, rb * mh);
+    tasks.clear();
+    for (int c = 0; c < 3; ++c) {
+      const int fv = p.vmax / frame->v[c];
+      const int ch = static_cast<int>(p.g.comp_h[c]);
+      int r0 = y0 / fv, r1 = (y1 - 1) / fv + 1;
+      if (fancy && fv == 2) {
+        r0 = std::max(0, r0 - 1);
+        r1 = std::min(ch, r1 + 1);
+      }
+      CompPlane& cp = cur[c];
+      cp.br0 = r0 / 8;
+      cp.br1 = (r1 + 7) / 8;
+      cp.stride = static_cast<size_t>(p.bw[c]) * 8;
+      cp.plane.resize(static_cast<size_t>(cp.br1 - cp.br0) * 8 * cp.stride);
+      for (int br = cp.br0; br < cp.br1; ++br)
+        tasks.push_back(Task{c, br, prev && br >= prev[c].br0 && br < prev[c].br1});
+    }
+    pf(static_cast<int>(tasks.size()), [&](int t) {
+      const Task& tk = tasks[t];
+      CompPlane& cp = cur[tk.c];
+      if (tk.copy) {
+        const size_t n = 8 * cp.stride;
+        memcpy(&cp.plane[(tk.br - cp.br0) * n], &prev[tk.c].plane[(tk.br - prev[tk.c].br0) * n], n);
+      } else {
+        decode_block_row(p, h_coef, h_qt, tk.c, tk.br, &cp);
+      }
+    });
+    constexpr int kBand = 8;
+    pf((y1 - y0 + kBand - 1) / kBand, [&](int t) {
+      const int ya = y0 + kBand * t;
+      output_rows(p, cur, fancy, ya, std::min(y1, ya + kBand), h_rgb, pitch);
+    });
+  }
   return MJD_OK;
 }
 
 extern "C" int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, const uint16_t* h_qt, int upsample,
                                uint8_t* h_rgb, size_t pitch, uint32_t mcu_row0, uint32_t mcu_row1, int n_threads) {
+  if (n_threads < 1 || n_threads > 256) return mjd::fail(MJD_EINVAL, "thread count outside 1..256");
+  // threads for the whole call (each decode runs several parallel loops)
+  mjd::WorkerPool pool(n_threads);
   return mjd::cpu::decode_host_with(frame, h_coef, h_qt, upsample, h_rgb, pitch, mcu_row0, mcu_row1, n_threads,
-                                    [n_threads](int n, const mjd::TaskFn& fn) { mjd::spawn_for(n_threads, n, fn); });
+                                    [&pool](int n, const mjd::TaskFn& fn) { pool.run(n, fn); });
 }

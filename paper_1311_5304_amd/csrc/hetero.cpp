@@ -95,7 +95,9 @@ int mjd_hetero_create(mjd_ctx* ctx, uint64_t max_blocks, uint64_t max_pixels, in
     delete h;
     return mjd::fail(MJD_ENOMEM, "heterogeneous decoder buffers: %s", hipGetErrorString(e));
   }
-  h->pool = new (std::nothrow) mjd::WorkerPool(n_threads);
+  // pinned, so that the host's rows of a split run on as many distinct
+  // cores as the model was fitted with
+  h->pool = new (std::nothrow) mjd::WorkerPool(n_threads, true);
   if (!h->pool) {
     release(h);
     delete h;

@@ -25,6 +25,11 @@ from . import _binding as B
 
 PARTS = ("o_w", "t_kernel", "o_r")
 HOST_PARTS = ("p_cpu", "t_dispatch")
+# The host parts are fitted at degree 3 at most and must not fall as their
+# side's rows grow: a high-degree surface through times measured at only a
+# few row counts per width swings between them, where the partition solve
+# then looks.
+HOST_MAX_DEGREE = 3
 
 
 def measure(ctx, jpg: bytes, reps: int = 3, upsample: int = B.MJD_UPSAMPLE_FANCY, hetero=None) -> dict:
@@ -103,10 +108,46 @@ def fit(samples, max_degree: int = B.MJD_POLY_MAX_DEGREE) -> tuple:
     for part in HOST_PARTS:  # against (width, rows) of the part's side
         pts = np.array([x[1:] for s in samples for x in s.get("host", ()) if x[0] == part], np.float64)
         if len(pts):
-            p2, aic = B.mjd_poly2_fit(pts[:, 0] / 1024.0, pts[:, 1] / 1024.0, pts[:, 2], max_degree)
+            a, b = pts[:, 0] / 1024.0, pts[:, 1] / 1024.0
+            for deg in range(min(max_degree, HOST_MAX_DEGREE), -1, -1):
+                p2, aic = B.mjd_poly2_fit(a, b, pts[:, 2], deg)
+                if rows_monotone(p2, a.min(), a.max(), b.max()):
+                    break
             setattr(model, part, p2)
             info[part] = (p2.degree, aic)
     return model, info
+
+
+def rows_monotone(p2, a_lo: float, a_hi: float, b_hi: float, n: int = 48) -> bool:
+    """True when the fitted surface does not fall as its second argument
+    (rows / 1024) grows from 0 to b_hi, at every width of [a_lo, a_hi]
+    (checked on an n x n grid)."""
+    for a in np.linspace(a_lo, a_hi, n):
+        v = [B.mjd_poly2_eval(p2, float(a), float(b)) for b in np.linspace(0.0, b_hi, n)]
+        if any(y1 < y0 - 1e-9 for y0, y1 in zip(v, v[1:])):
+            return False
+    return True
+
+
+def host_errors(model, samples, absolute: bool = False) -> dict:
+    """Errors of the host parts' predictions against `measure` results taken
+    with a heterogeneous decoder: {part: [|pred - meas| / meas]}, or in
+    seconds with absolute=True."""
+    out = {part: [] for part in HOST_PARTS}
+    for s in samples:
+        for part, w, rows, t in s.get("host", ()):
+            pred = B.mjd_poly2_eval(getattr(model, part), w / 1024.0, rows / 1024.0)
+            out[part].append(abs(pred - t) if absolute else abs(pred - t) / t)
+    return out
+
+
+def host_times(samples) -> dict:
+    """{part: [measured seconds]} of the host parts in `measure` results."""
+    out = {part: [] for part in HOST_PARTS}
+    for s in samples:
+        for part, _, _, t in s.get("host", ()):
+            out[part].append(t)
+    return out
 
 
 def predict(model, width: int, height: int, file_bytes: int) -> dict:

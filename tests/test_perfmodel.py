@@ -359,6 +359,45 @@ def test_fit_recovers_host_parts_against_rows(M):
     assert back.p_cpu.degree == 2 and math.isclose(back.t_dispatch.c[0], 5e-5, rel_tol=1e-9)
 
 
+def test_host_parts_are_capped_and_never_fall_with_rows(M):
+    # host times with a dip between their row counts (t = u^3 - 1.5 u^2 +
+    # 0.6 u + 1 in u = rows / 4096, falling for u in (0.28, 0.72)): the
+    # unconstrained degree-3 surface follows the dip; the fit used for the
+    # host parts stays at degree 3 or below and picks one that does not fall
+    # as rows grow.  Exact bilinear data are predicted with no error.
+    from paper_1311_5304_amd import perfmodel
+    rng = np.random.default_rng(9)
+
+    def dip(x):
+        u = x / 4096.0
+        return 1e-3 * (u ** 3 - 1.5 * u ** 2 + 0.6 * u + 1.0)
+
+    samples = []
+    for _ in range(40):
+        w = int(rng.integers(1024, 6000))
+        h = int(rng.integers(768, 4096))
+        s = {"width": w, "height": h, "bytes": w * h // 4, "t_huff": 2e-9 * w * h,
+             "o_w": 1e-4 + 1e-3 * w * h / 2 ** 20, "t_kernel": 2e-5 * w * h / 2 ** 20, "o_r": 1e-3 * w * h / 2 ** 20}
+        host = []
+        for x in (h // 4, h // 2, 3 * h // 4, h):
+            host.append(("p_cpu", w, x, dip(x)))
+            host.append(("t_dispatch", w, h - x + 1, 5e-5))
+        s["host"] = host
+        samples.append(s)
+    pts = np.array([x[1:] for s in samples for x in s["host"] if x[0] == "p_cpu"], np.float64)
+    free, _ = M.mjd_poly2_fit(pts[:, 0] / 1024.0, pts[:, 1] / 1024.0, pts[:, 2], 3)
+    assert free.degree == 3 and not perfmodel.rows_monotone(free, 1.0, 6000 / 1024.0, 4.0)
+    model, info = perfmodel.fit(samples)
+    assert info["p_cpu"][0] < 3
+    assert perfmodel.rows_monotone(model.p_cpu, 1.0, 6000 / 1024.0, 4.0)
+    exact = [dict(s, host=[(k, w, x, 3e-4 + 4e-3 * w * x / 2 ** 20) if k == "p_cpu" else (k, w, x, t)
+                           for k, w, x, t in s["host"]]) for s in samples]
+    m2, info2 = perfmodel.fit(exact)
+    assert info2["p_cpu"][0] == 2
+    errs = perfmodel.host_errors(m2, exact)
+    assert max(errs["p_cpu"]) < 1e-8 and max(errs["t_dispatch"]) < 1e-8
+
+
 def test_pps_with_a_whole_image_chunk_is_the_overlapped_scheme(M):
     # c = min(chunk, h - x) = h - x when chunk >= h, so the CPU's Huffman term
     # T_huff(w, h - c) becomes T_huff(w, x): exactly the overlapped scheme
