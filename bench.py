@@ -621,13 +621,53 @@ def gpu_entropy_workload(args, M, ctx, dev, jpgs, frames, sample_idx, sample):
     return res
 
 
+def pcie_bandwidth(dev, nbytes: int = 256 << 20, reps: int = 5):
+    """Pinned host<->device copy rates (GB/s): each direction alone, and both
+    at once on two streams (the link is full duplex)."""
+    import torch
+    h_src = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    h_dst = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    d_a = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    d_b = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+
+    def timed(fn):
+        best = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best
+
+    def h2d():
+        with torch.cuda.stream(s1):
+            d_a.copy_(h_src, non_blocking=True)
+
+    def d2h():
+        with torch.cuda.stream(s2):
+            h_dst.copy_(d_b, non_blocking=True)
+
+    t_h2d, t_d2h = timed(h2d), timed(d2h)
+    t_both = timed(lambda: (h2d(), d2h()))
+    gbs = lambda t, n=nbytes: round(n / t / 1e9, 2)
+    return {"h2d_GBps": gbs(t_h2d), "d2h_GBps": gbs(t_d2h), "both_directions_GBps": gbs(t_both, 2 * nbytes),
+            "bytes_per_copy": nbytes}
+
+
 def serve_workload(args, M, ctx, dev, model=None):
     """Serving loop: Poisson arrivals of requests log-uniform in 0.1..24 MP
-    (mixed samplings, quality 50..95, gradient content), coefficients and
-    RGB8 in pinned host memory, a 16 GiB device budget, continuous batching
-    against the synchronous one-at-a-time server on the same trace.  The
-    arrival rate is 0.7x (and 0.9x) of the batched capacity measured on a
-    saturating trace."""
+    (mixed samplings, quality 50..95, gradient content), coefficients in
+    pinned host memory, RGB8 back to pinned host memory (or left in device
+    memory, the path without the device->host copy), a 16 GiB device
+    budget.  Continuous batching, uncapped and with batches capped at 4 ms of
+    the performance model's predicted GPU time, against the synchronous
+    one-at-a-time server on the same trace.  The default policy is the one
+    with the higher capacity on a saturating trace; the arrival rates are
+    0.7x and 0.9x of its capacity.  Capacity is also stated against the
+    measured pinned PCIe rates, which bound it: every request's coefficients
+    cross host->device and its RGB device->host."""
     import torch
 
     import oracle
@@ -641,13 +681,18 @@ def serve_workload(args, M, ctx, dev, model=None):
         coef = c.cpu().pin_memory()
         q = torch.from_numpy(qt.view(np.int16).reshape(-1).copy()).pin_memory()
         out = torch.empty((frame["height"], frame["width"], 3), dtype=torch.uint8).pin_memory()
-        pool.append((frame, coef, q, out, qt))
+        d_out = torch.empty((frame["height"], frame["width"], 3), dtype=torch.uint8, device=dev)
+        pool.append((frame, coef, q, out, qt, d_out))
     px_of = [f["width"] * f["height"] for f, *_ in pool]
+    h2d_of = [c.numel() * 2 + 512 for _, c, *_ in pool]
+    d2h_of = [3 * p for p in px_of]
     budget = 16 << 30
     warm = 200
     n = max(args.serve_requests, warm + 100)
+    log("serving: pinned PCIe rates")
+    link = pcie_bandwidth(dev)
 
-    def run(mode, rate, cap_s=0.0):
+    def run(mode, rate, cap_s=0.0, device_out=False):
         trace = workloads.serving_trace(n, len(pool), rate if rate else 1.0)
         srv = M.Server(ctx, budget, M.MJD_UPSAMPLE_FANCY, mode=mode, max_batch=256, max_inflight=2,
                        model=model if cap_s else None, max_batch_s=cap_s)
@@ -655,44 +700,74 @@ def serve_workload(args, M, ctx, dev, model=None):
             t0 = srv.now_ns() + 2_000_000
             ids = []
             for (at, k) in trace:
-                f, c, q, o, _ = pool[k]
-                ids.append(srv.submit(f, c, q, o, 3 * f["width"], t0 + (at if rate else 0)))
+                f, c, q, o, _, d = pool[k]
+                ids.append(srv.submit(f, c, q, d if device_out else o, 3 * f["width"], t0 + (at if rate else 0)))
             times = [srv.wait(i) for i in ids]
         finally:
             srv.close()
         meas = times[warm:]
-        px = sum(px_of[k] for _, k in trace[warm:])
+        ks = [k for _, k in trace[warm:]]
+        px = sum(px_of[k] for k in ks)
         span = (max(t["done_ns"] for t in meas) - min(t["arrival_ns"] for t in meas)) * 1e-9
         lat = np.array([(t["done_ns"] - t["arrival_ns"]) * 1e-6 for t in meas])
+        h2d = sum(h2d_of[k] for k in ks) / span / 1e9
+        d2h = 0.0 if device_out else sum(d2h_of[k] for k in ks) / span / 1e9
         return {"MPix_s": round(px / span / 1e6, 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "mean_batch": round(float(np.mean([t["batch"] for t in meas])), 2)}
+                "mean_batch": round(float(np.mean([t["batch"] for t in meas])), 2),
+                "h2d_GBps": round(h2d, 2), "d2h_GBps": round(d2h, 2)}
 
-    log("serving: saturating trace (capacity)")
+    log("serving: saturating traces (capacity)")
     cap = run(M.MJD_SERVE_CONTINUOUS, 0)
     cap_model = run(M.MJD_SERVE_CONTINUOUS, 0, 4e-3) if model is not None else None
     mean_px = float(np.mean(px_of))
+    default_cap_s = 4e-3 if cap_model is not None and cap_model["MPix_s"] > cap["MPix_s"] else 0.0
+    best = cap_model if default_cap_s else cap
+    cap_dev = run(M.MJD_SERVE_CONTINUOUS, 0, default_cap_s, device_out=True)
+    # the link bound: requests cross host->device (coefficients) and back
+    # (RGB) on a full-duplex link, so the busier direction sets the rate
+    h2d_bpp = sum(h2d_of) / sum(px_of)
+    d2h_bpp = 3.0
+    bound = min(link["h2d_GBps"] / h2d_bpp, link["d2h_GBps"] / d2h_bpp) * 1e3
     res = {"pool_images": len(pool), "requests": n, "warmup": warm, "budget_GiB": budget >> 30,
-           "mean_request_MP": round(mean_px / 1e6, 3), "capacity_continuous": cap}
+           "mean_request_MP": round(mean_px / 1e6, 3), "pcie": link,
+           "default_policy": "continuous, model cap 4 ms" if default_cap_s else "continuous, uncapped",
+           "capacity_continuous": cap,
+           "capacity_default_rgb_in_device_memory": cap_dev,
+           "capacity_vs_link": {
+               "h2d_bytes_per_pixel": round(h2d_bpp, 3), "d2h_bytes_per_pixel": d2h_bpp,
+               "link_bound_MPix_s": round(bound, 1),
+               "default_fraction_of_link_bound": round(best["MPix_s"] / bound, 4),
+               "default_h2d_fraction": round(best["h2d_GBps"] / link["h2d_GBps"], 4),
+               "default_d2h_fraction": round(best["d2h_GBps"] / link["d2h_GBps"], 4)}}
     if cap_model is not None:
         res["capacity_continuous_model_cap_4ms"] = cap_model
     for frac in (0.7, 0.9):
-        rate = frac * cap["MPix_s"] * 1e6 / mean_px
+        rate = frac * best["MPix_s"] * 1e6 / mean_px
         log(f"serving: Poisson trace at {frac} x capacity ({rate:.0f} requests/s)")
-        res[f"continuous_{frac}x"] = dict(run(M.MJD_SERVE_CONTINUOUS, rate), rate_per_s=round(rate, 1))
+        res[f"default_{frac}x"] = dict(run(M.MJD_SERVE_CONTINUOUS, rate, default_cap_s), rate_per_s=round(rate, 1))
+        res[f"default_rgb_in_device_memory_{frac}x"] = dict(
+            run(M.MJD_SERVE_CONTINUOUS, rate, default_cap_s, device_out=True), rate_per_s=round(rate, 1))
         res[f"sync_{frac}x"] = dict(run(M.MJD_SERVE_SYNC, rate), rate_per_s=round(rate, 1))
+        res[f"sync_rgb_in_device_memory_{frac}x"] = dict(run(M.MJD_SERVE_SYNC, rate, device_out=True),
+                                                          rate_per_s=round(rate, 1))
         if model is not None:
-            # batches sized by the fitted performance model (paper Sec. 5.1):
-            # each closes once its predicted GPU time would pass the cap
-            for cap_ms in (4.0, 16.0):
+            # the other batching policies on the same trace: uncapped, or
+            # batches sized by the fitted performance model (paper Sec. 5.1),
+            # each closing once its predicted GPU time would pass the cap
+            if default_cap_s:
+                res[f"continuous_uncapped_{frac}x"] = dict(run(M.MJD_SERVE_CONTINUOUS, rate), rate_per_s=round(rate, 1))
+            for cap_ms in ((16.0,) if default_cap_s else (4.0, 16.0)):
                 res[f"continuous_model_cap_{cap_ms:g}ms_{frac}x"] = dict(
                     run(M.MJD_SERVE_CONTINUOUS, rate, cap_ms * 1e-3), rate_per_s=round(rate, 1))
-    # bit-exactness: the smallest pool image as served, against the oracle
+    # bit-exactness: the smallest pool image as served (host and device
+    # outputs), against the oracle
     k = min(range(len(pool)), key=lambda i: px_of[i])
-    f, c, q, o, qt = pool[k]
+    f, c, q, o, qt, d = pool[k]
+    ref = oracle.decode(f, c.numpy().reshape(-1, 64), qt, "fancy")
     res["bit_exact_sample"] = {"pool_image": k, "size": [f["width"], f["height"]],
-                               "equal": bool(np.array_equal(o.numpy(), oracle.decode(
-                                   f, c.numpy().reshape(-1, 64), qt, "fancy")))}
+                               "equal": bool(np.array_equal(o.numpy(), ref)),
+                               "equal_device_output": bool(np.array_equal(d.cpu().numpy(), ref))}
     return res
 
 

@@ -673,7 +673,8 @@ int mjd_repartition_rows(const mjd_model* model, uint32_t width, uint32_t height
 /* ---------------------------------------------------------------------
  * Serving: a request loop that decodes images of different sizes as they
  * arrive.  Requests carry quantised coefficients in host memory (the
- * paper's input, Sec. 7) and receive RGB8 in host memory.  The server keeps
+ * paper's input, Sec. 7) and receive RGB8 in host memory (or in device
+ * memory, for consumers on the GPU).  The server keeps
  * one device arena of `budget_bytes` for the coefficient and RGB buffers of
  * admitted requests (the paper's whole-image buffers, Sec. 4); a request is
  * admitted, in arrival order, once it has arrived and its buffers fit.
@@ -706,14 +707,18 @@ typedef struct mjd_server_config {
 
 /* One decode request.  All buffers belong to the caller and must stay valid
  * until the request is done; h_coef/h_qt are read, h_rgb written, by device
- * copies (pinned memory lets them overlap). */
+ * copies (pinned memory lets them overlap).  Exactly one of h_rgb and d_rgb
+ * is set: with d_rgb (device memory on the server's device, for consumers
+ * that stay on the GPU) the batch kernel writes the rows there itself, the
+ * arena holds no RGB buffer for the request and nothing is copied back. */
 typedef struct mjd_request {
   mjd_frame frame;
   const int16_t* h_coef; /* n_blocks * 64 int16, MCU order (as mjd_decode) */
   const uint16_t* h_qt;  /* uint16[4][64] */
-  uint8_t* h_rgb;        /* height rows of pitch bytes */
+  uint8_t* h_rgb;        /* height rows of pitch bytes in host memory, or NULL */
   uint64_t pitch;        /* >= 3 * width */
   uint64_t arrival_ns;   /* on the server clock (mjd_server_now_ns); earlier than now = arrived */
+  uint8_t* d_rgb;        /* height rows of pitch bytes in device memory, or NULL */
 } mjd_request;
 
 /* Server-clock timestamps of one request (0 while a stage has not happened). */
@@ -721,7 +726,7 @@ typedef struct mjd_request_times {
   uint64_t arrival_ns;
   uint64_t admit_ns;   /* buffers allocated, host->device copy enqueued */
   uint64_t launch_ns;  /* its batch (or its decode, in sync mode) enqueued */
-  uint64_t done_ns;    /* RGB8 in host memory (observed by the server) */
+  uint64_t done_ns;    /* RGB8 in h_rgb, or written to d_rgb (observed by the server) */
   int32_t status;      /* MJD_OK, or why it failed */
   uint32_t batch;      /* number of requests in its batch launch */
 } mjd_request_times;

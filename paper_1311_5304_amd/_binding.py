@@ -151,7 +151,8 @@ class mjd_server_config(ctypes.Structure):
 
 class mjd_request(ctypes.Structure):
     _fields_ = [("frame", mjd_frame), ("h_coef", ctypes.c_void_p), ("h_qt", ctypes.c_void_p),
-                ("h_rgb", ctypes.c_void_p), ("pitch", ctypes.c_uint64), ("arrival_ns", ctypes.c_uint64)]
+                ("h_rgb", ctypes.c_void_p), ("pitch", ctypes.c_uint64), ("arrival_ns", ctypes.c_uint64),
+                ("d_rgb", ctypes.c_void_p)]
 
 
 class mjd_request_times(ctypes.Structure):
@@ -753,8 +754,12 @@ class Server:
         return int(lib().mjd_server_now_ns(self.handle))
 
     def submit(self, frame, coef, qt, rgb, pitch: int, arrival_ns: int = 0) -> int:
-        """coef/qt/rgb: host buffers (pinned tensors or numpy arrays) that stay alive until done."""
-        r = mjd_request(frame=make_frame(frame), h_coef=_ptr(coef), h_qt=_ptr(qt), h_rgb=_ptr(rgb),
+        """coef/qt: host buffers (pinned tensors or numpy arrays); rgb: a host
+        buffer, or a CUDA tensor on the server's device (the kernel writes it,
+        nothing is copied back).  All stay alive until done."""
+        on_device = bool(getattr(rgb, "is_cuda", False))
+        r = mjd_request(frame=make_frame(frame), h_coef=_ptr(coef), h_qt=_ptr(qt),
+                        h_rgb=None if on_device else _ptr(rgb), d_rgb=_ptr(rgb) if on_device else None,
                         pitch=int(pitch), arrival_ns=int(arrival_ns))
         rid = ctypes.c_uint64()
         _check(lib().mjd_server_submit(self.handle, ctypes.byref(r), ctypes.byref(rid)))

@@ -6,8 +6,10 @@
 // start at once.  Whenever a batch-table slot is free, everything admitted
 // since the last launch becomes one persistent batch launch (the segment
 // queue of batch.hip); its RGB8 results go device->host on a third stream
-// and the arena space returns when that copy completes.  In sync mode the
-// same thread decodes one request at a time and waits for each.
+// and the arena space returns when that copy completes (requests whose RGB
+// goes to the caller's device memory are written there by the kernel and
+// copy nothing back).  In sync mode the same thread decodes one request at
+// a time and waits for each.
 #include <string.h>
 
 #include <algorithm>
@@ -170,6 +172,7 @@ static hipError_t copy_in(mjd_server* s, Request& q) {
 }
 
 static hipError_t copy_out(mjd_server* s, Request& q) {
+  if (q.r.d_rgb) return hipSuccess;  // the kernel wrote the caller's device rows
   const uint8_t* rgb = s->d_arena + q.off + q.coef_bytes + kQtBytes;
   // rows without padding on both sides: one linear copy (with padding, the
   // host bytes beyond 3 * width must stay untouched)
@@ -185,8 +188,8 @@ static mjd_job job_of(mjd_server* s, const Request& q) {
   uint8_t* base = s->d_arena + q.off;
   j.d_coef = reinterpret_cast<const int16_t*>(base);
   j.d_qt = reinterpret_cast<const uint16_t*>(base + q.coef_bytes);
-  j.d_rgb = base + q.coef_bytes + kQtBytes;
-  j.pitch = q.rgb_pitch;
+  j.d_rgb = q.r.d_rgb ? q.r.d_rgb : base + q.coef_bytes + kQtBytes;
+  j.pitch = q.r.d_rgb ? q.r.pitch : q.rgb_pitch;
   return j;
 }
 
@@ -471,16 +474,25 @@ int mjd_server_submit(mjd_server* srv, const mjd_request* req, uint64_t* id) {
   q.r = *req;
   int rc = mjd::frame_geometry(&req->frame, &q.g);
   if (rc != MJD_OK) return rc;
-  if (!req->h_coef || !req->h_qt || !req->h_rgb) return mjd::fail(MJD_EINVAL, "null request buffer");
+  if (!req->h_coef || !req->h_qt) return mjd::fail(MJD_EINVAL, "null request buffer");
+  if ((req->h_rgb == nullptr) == (req->d_rgb == nullptr))
+    return mjd::fail(MJD_EINVAL, "exactly one of h_rgb and d_rgb must be set");
   if (req->pitch < 3ull * req->frame.width) return mjd::fail(MJD_EINVAL, "pitch below 3*width");
   using mjd::serve::kAlign;
   using mjd::serve::round_up;
   q.coef_bytes = round_up(q.g.n_blocks * 128, kAlign);
-  // device rows match dense host rows, so results come back in one linear
-  // copy; otherwise they are padded to 16 bytes for the kernel's wide stores
-  q.rgb_pitch = req->pitch == 3ull * req->frame.width ? req->pitch : round_up(3ull * req->frame.width, 16);
-  if (q.rgb_pitch >= (1ull << 24)) return mjd::fail(MJD_EINVAL, "row too wide");
-  q.rgb_bytes = round_up(q.rgb_pitch * req->frame.height, kAlign);
+  if (req->d_rgb) {
+    // the kernel writes the caller's rows: no RGB buffer in the arena
+    if (req->pitch >= (1ull << 24)) return mjd::fail(MJD_EINVAL, "row too wide");
+    q.rgb_pitch = req->pitch;
+    q.rgb_bytes = 0;
+  } else {
+    // device rows match dense host rows, so results come back in one linear
+    // copy; otherwise they are padded to 16 bytes for the kernel's wide stores
+    q.rgb_pitch = req->pitch == 3ull * req->frame.width ? req->pitch : round_up(3ull * req->frame.width, 16);
+    if (q.rgb_pitch >= (1ull << 24)) return mjd::fail(MJD_EINVAL, "row too wide");
+    q.rgb_bytes = round_up(q.rgb_pitch * req->frame.height, kAlign);
+  }
   q.total = q.coef_bytes + mjd::serve::kQtBytes + q.rgb_bytes;
   if (srv->has_model) {
     mjd_prediction p;

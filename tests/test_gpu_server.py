@@ -154,6 +154,42 @@ def test_sync_server_and_padded_pitch(M, ctx, requests):
         srv.close()
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_device_outputs_match_host_outputs(M, ctx, requests, mode):
+    """Requests whose RGB goes to device memory (written by the kernel, not
+    copied back), mixed with host-output requests in one trace: both equal
+    the oracle; a padded device pitch keeps its padding bytes."""
+    exp = expected(requests, "fancy")
+    srv = M.Server(ctx, 64 << 20, M.MJD_UPSAMPLE_FANCY, mode=mode, max_batch=8)
+    try:
+        outs, ids = [], []
+        t0 = srv.now_ns() + 1_000_000
+        for i, (f, c, q, _, _) in enumerate(requests):
+            w, h = f["width"], f["height"]
+            if i % 2 == 0:
+                o = torch.full((h, 3 * w + 7), 6, dtype=torch.uint8, device="cuda")
+                pitch = 3 * w + 7
+            else:
+                o = torch.full((h, w, 3), 1, dtype=torch.uint8).pin_memory()
+                pitch = 3 * w
+            say(f"device-output mix mode {mode} request {i} {w}x{h} {'device' if i % 2 == 0 else 'host'}")
+            outs.append(o)
+            ids.append(srv.submit(f, c, q, o, pitch, t0 + 20_000 * i))
+        srv.drain()
+        torch.cuda.synchronize()
+        for i, (rid, o, e, (f, *_)) in enumerate(zip(ids, outs, exp, requests)):
+            check_times(srv.wait(rid))
+            w, h = f["width"], f["height"]
+            got = o.cpu().numpy()
+            if i % 2 == 0:
+                assert np.array_equal(got[:, :3 * w].reshape(h, w, 3), e), i
+                assert np.all(got[:, 3 * w:] == 6), i
+            else:
+                assert np.array_equal(got, e), i
+    finally:
+        srv.close()
+
+
 def test_server_rejects_bad_requests(M, ctx, requests):
     f, c, q, _, _ = requests[0]
     srv = M.Server(ctx, 64 << 20, M.MJD_UPSAMPLE_FANCY)
@@ -165,6 +201,14 @@ def test_server_rejects_bad_requests(M, ctx, requests):
         o = np.zeros((f["height"], f["width"], 3), np.uint8)
         with pytest.raises(M.MjdError):
             srv.submit(f, c, q, o, 3 * f["width"] - 1)
+        import ctypes
+
+        from paper_1311_5304_amd import _binding as B
+        rid = ctypes.c_uint64()
+        for h_rgb, d_rgb in ((None, None), (o.ctypes.data, o.ctypes.data)):  # no output, or both
+            r = B.mjd_request(frame=B.make_frame(f), h_coef=c.data_ptr(), h_qt=q.data_ptr(), h_rgb=h_rgb,
+                              d_rgb=d_rgb, pitch=3 * f["width"], arrival_ns=0)
+            assert B.lib().mjd_server_submit(srv.handle, ctypes.byref(r), ctypes.byref(rid)) == B.MJD_EINVAL
         t = srv.now_ns()
         srv.wait(srv.submit(f, c, q, o, 3 * f["width"], t + 1000))
         with pytest.raises(M.MjdError):
