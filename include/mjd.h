@@ -191,9 +191,12 @@ int mjd_decode_host(const mjd_frame* frame, const int16_t* h_coef, const uint16_
 /* ---------------------------------------------------------------------
  * Decoder variants (paper Sec. 2 and Sec. 3 name libjpeg's AAN-based and
  * integer-or-float IDCTs; Sec. 4.2 decodes samplings other than 4:4:4 and
- * 4:2:2 the same way).  A generic path of two launches: dequantise + IDCT
- * into per-component sample planes in a caller workspace, then upsampling
- * + colour conversion; grayscale writes its rows from the first launch.
+ * 4:2:2 the same way).  Full-size colour images decode in one launch of
+ * the fused segment kernel for their sampling and IDCT method (no sample
+ * planes in memory, no workspace).  Grayscale decodes in one launch that
+ * writes its rows directly; scaled decodes use two launches: dequantise +
+ * reduced IDCT into per-component sample planes in a caller workspace,
+ * then upsampling + colour conversion.
  * IDCT methods:
  *   MJD_IDCT_ISLOW  LL&M in 13-bit fixed point (mjd_decode's arithmetic);
  *   MJD_IDCT_IFAST  the AAN flowgraph (transposed forward graph) in fixed
@@ -224,7 +227,7 @@ typedef struct mjd_variant {
 /* Host only: validates `variant` and gives its geometry: the coefficient
  * layout (grayscale: 8x8 MCUs of one block), comp_w/comp_h at the output
  * scale (0 for absent components), and the workspace mjd_decode_variant
- * needs (0 for grayscale).  out and work_bytes
+ * needs (0 for grayscale and for full-size colour images).  out and work_bytes
  * may be NULL.  MJD_EINVAL for bad fields, MJD_EUNSUPPORTED for other
  * samplings. */
 int mjd_variant_geometry(const mjd_variant* variant, mjd_geometry* out, uint64_t* work_bytes);
@@ -232,10 +235,10 @@ int mjd_variant_geometry(const mjd_variant* variant, mjd_geometry* out, uint64_t
 /* Decodes a whole image.  d_coef: n_blocks * 64 int16 in MCU order,
  * 16-byte aligned (same numeric domain as mjd_decode); d_qt: uint16[4][64];
  * d_out: ceil(H / scale) rows of `pitch` bytes (pitch >= ncomp * ceil(W /
- * scale), < 2^31), only each row's first ncomp * ceil(W / scale) bytes
- * written; d_work: device workspace of at
- * least the size mjd_variant_geometry gives, 16-byte aligned, owned by the
- * caller, overwritten (may be NULL for grayscale).  Asynchronous on
+ * scale), < 2^31; < 2^24 for full-size colour images), only each row's
+ * first ncomp * ceil(W / scale) bytes written; d_work: device workspace of
+ * at least the size mjd_variant_geometry gives, 16-byte aligned, owned by
+ * the caller, overwritten (may be NULL when that size is 0).  Asynchronous on
  * `stream`.  MJD_EINVAL for bad arguments, MJD_EDEVICE for launch
  * failures. */
 int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* d_coef, const uint16_t* d_qt,

@@ -19,14 +19,14 @@ struct SegGrid {
 };
 
 template <class C>
-__global__ __launch_bounds__(C::NT, C::WAVES_PER_SIMD) void decode_segments(const ImageView im, const SegGrid sg) {
-  __shared__ __align__(16) uint8_t lds[C::LDS_BYTES];
+__device__ __forceinline__ void walk_segments(uint8_t* lds, const ImageView& im, const SegGrid& sg,
+                                              const AanConsts* ak) {
   // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a
   // contiguous run of segments (row-major over strips) so neighbouring
   // strips, whose chroma blocks each other's filter reads, share an L2.
   const int per_xcd = static_cast<int>(gridDim.x >> 3);
   const int v = static_cast<int>(blockIdx.x & 7u) * per_xcd + static_cast<int>(blockIdx.x >> 3);
-  SegmentDecoder<C> dec(lds, im, static_cast<int>(threadIdx.x));
+  SegmentDecoder<C> dec(lds, im, static_cast<int>(threadIdx.x), ak);
   for (int s = v; s < sg.segments; s += static_cast<int>(gridDim.x)) {
     const int sr = s / sg.strips;
     const int st = s - sr * sg.strips;
@@ -39,9 +39,25 @@ __global__ __launch_bounds__(C::NT, C::WAVES_PER_SIMD) void decode_segments(cons
 }
 
 template <class C>
+__global__ __launch_bounds__(C::NT, C::WAVES_PER_SIMD) void decode_segments(const ImageView im, const SegGrid sg) {
+  __shared__ __align__(16) uint8_t lds[C::LDS_BYTES];
+  walk_segments<C>(lds, im, sg, nullptr);
+}
+
+// The same walk with an AAN method's IDCT (its constants by value).
+template <class C>
+__global__ __launch_bounds__(C::NT, C::WAVES_PER_SIMD) void decode_segments_aan(const ImageView im, const SegGrid sg,
+                                                                                const AanConsts ak) {
+  __shared__ __align__(16) uint8_t lds[C::LDS_BYTES];
+  walk_segments<C>(lds, im, sg, &ak);
+}
+
+template <class C>
 static hipError_t resident_per_cu(int* per_cu) {
   *per_cu = 0;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, decode_segments<C>, C::NT, 0);
+  hipError_t e;
+  if constexpr (C::ISLOW) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, decode_segments<C>, C::NT, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, decode_segments_aan<C>, C::NT, 0);
   if (e == hipSuccess && *per_cu < 1) *per_cu = 1;
   return e;
 }
@@ -77,7 +93,8 @@ static hipError_t launch_cfg(const ImageView& im, int row0, int row1, int cu_cou
   int grid = tu.workgroups > 0 ? static_cast<int>(tu.workgroups) : slots;
   if (grid > sg.segments) grid = sg.segments;
   grid = (grid + 7) & ~7;
-  hipLaunchKernelGGL(decode_segments<C>, dim3(grid), dim3(C::NT), 0, stream, im, sg);
+  if constexpr (C::ISLOW) hipLaunchKernelGGL(decode_segments<C>, dim3(grid), dim3(C::NT), 0, stream, im, sg);
+  else hipLaunchKernelGGL(decode_segments_aan<C>, dim3(grid), dim3(C::NT), 0, stream, im, sg, aan_consts());
   return hipGetLastError();
 }
 
@@ -141,6 +158,31 @@ hipError_t shape_info(int hf, int vf, bool fancy, int index, int* sx, int* sy, i
   return s.per_cu(per_cu);
 }
 
+// The decoder variants on the fused path: every sampling (luma (1,1), (2,1),
+// (1,2), (2,2), (4,1)) with every IDCT method, one sub-tile shape each
+// (islow's 4:4:4 / 4:2:2 / 4:2:0 are the single-image kernel's defaults).
+// A factor of 4 is replicated in both modes.
+template <int M>
+static hipError_t launch_variant_method(const ImageView& im, int hf, int vf, bool fancy, int cu_count,
+                                       hipStream_t stream) {
+  const mjd_tuning tu{0, 0, 0};
+  const int rows = im.mcus_y;
+  if (hf == 4) return launch_cfg<SegCfg<4, 1, false, 8, 4, 192, M>>(im, 0, rows, cu_count, tu, stream);
+  if (hf == 1 && vf == 2)
+    return fancy ? launch_cfg<SegCfg<1, 2, true, 16, 2, 128, M>>(im, 0, rows, cu_count, tu, stream)
+                 : launch_cfg<SegCfg<1, 2, false, 16, 2, 128, M>>(im, 0, rows, cu_count, tu, stream);
+  if constexpr (M == 0) {
+    return launch_image(im, 0, rows, hf, vf, fancy, cu_count, tu, stream);
+  } else {
+    if (hf == 1) return launch_cfg<SegCfg<1, 1, false, 16, 4, 192, M>>(im, 0, rows, cu_count, tu, stream);
+    if (vf == 1)
+      return fancy ? launch_cfg<SegCfg<2, 1, true, 16, 2, 192, M>>(im, 0, rows, cu_count, tu, stream)
+                   : launch_cfg<SegCfg<2, 1, false, 16, 2, 128, M>>(im, 0, rows, cu_count, tu, stream);
+    return fancy ? launch_cfg<SegCfg<2, 2, true, 16, 2, 256, M>>(im, 0, rows, cu_count, tu, stream)
+                 : launch_cfg<SegCfg<2, 2, false, 16, 2, 192, M>>(im, 0, rows, cu_count, tu, stream);
+  }
+}
+
 hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf, bool fancy, int cu_count,
                         const mjd_tuning& tu, hipStream_t stream) {
   const Shape* l;
@@ -148,6 +190,14 @@ hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf,
   class_shapes(hf, vf, fancy, &l, &n);
   const int i = static_cast<int>(tu.shape) < n ? static_cast<int>(tu.shape) : 0;
   return l[i].launch(im, row0, row1, cu_count, tu, stream);
+}
+
+hipError_t launch_variant(const ImageView& im, int hf, int vf, bool fancy, int idct, int cu_count, hipStream_t stream) {
+  switch (idct) {
+    case 0: return launch_variant_method<0>(im, hf, vf, fancy, cu_count, stream);
+    case 1: return launch_variant_method<1>(im, hf, vf, fancy, cu_count, stream);
+    default: return launch_variant_method<2>(im, hf, vf, fancy, cu_count, stream);
+  }
 }
 
 }  // namespace mjd

@@ -98,7 +98,8 @@ int variant_geometry(const mjd_variant* vr, mjd_geometry* g, uint64_t* work, uin
     g->comp_h[c] = c < nc ? (ch + scale - 1) / scale : 0;
     plane_pitch[c] = (g->mcus_x * hc * n + 15) & ~15u;
     plane_off[c] = total;
-    if (nc == 3) total += (static_cast<uint64_t>(plane_pitch[c]) * g->mcus_y * vc * n + 255) & ~255ull;
+    // full-size colour images decode in one fused pass: no planes
+    if (nc == 3 && scale > 1) total += (static_cast<uint64_t>(plane_pitch[c]) * g->mcus_y * vc * n + 255) & ~255ull;
   }
   *work = total;
   return MJD_OK;

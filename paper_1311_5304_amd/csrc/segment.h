@@ -24,6 +24,7 @@
 // during phase 1.  Each step has two barriers.
 #pragma once
 
+#include "aan.h"
 #include "decode_kernel.h"
 
 namespace mjd {
@@ -62,12 +63,18 @@ struct SegmentRange {
   int mx0, r0, r1;
 };
 
-template <int HF_, int VF_, bool FANCY_, int SX_, int SY_, int NT_>
+// HF x VF: the luma blocks of an MCU, (1,1), (2,1), (1,2), (2,2) or (4,1),
+// chroma one block each.  IDCT: MJD_IDCT_ISLOW (0, the paper's LL&M with
+// the dot-product row pass), MJD_IDCT_IFAST (1) or MJD_IDCT_FLOAT (2), the
+// AAN methods of aan.h, one whole block per lane.
+template <int HF_, int VF_, bool FANCY_, int SX_, int SY_, int NT_, int IDCT_ = 0>
 struct SegCfg {
-  static constexpr int HF = HF_, VF = VF_, SX = SX_, SY = SY_, NT = NT_;
+  static constexpr int HF = HF_, VF = VF_, SX = SX_, SY = SY_, NT = NT_, IDCT = IDCT_;
+  static constexpr bool ISLOW = IDCT == 0;
   static constexpr bool FANCY = FANCY_;
   static constexpr int NY = HF * VF;
   static constexpr int BPM = NY + 2;
+  // fancy filtering applies to factors of 2 (a factor of 4 is replicated)
   static constexpr bool HALO_X = FANCY && HF == 2;
   static constexpr bool HALO_Y = FANCY && VF == 2;
   // Steps by which the last phase 2 trails the last phase 1.  For the 4:2:0
@@ -80,7 +87,9 @@ struct SegCfg {
   static constexpr int N_SIDE = HALO_X ? 4 * SY : 0;       // left/right neighbour chroma blocks
   static constexpr int N_SLOT = N_MAIN + N_SIDE;           // staged blocks
   static constexpr int SIDE_LANE0 = round64c(N_MAIN);      // first lane of the side tasks
-  static constexpr int P1_LANES = SIDE_LANE0 + 8 * N_SIDE;
+  // islow forms a side block's one column on 8 lanes; the AAN methods
+  // transform the whole block on one lane
+  static constexpr int P1_LANES = SIDE_LANE0 + (ISLOW ? 8 : 1) * N_SIDE;
   static constexpr int N_TB = HALO_Y ? 2 * (SX + 2) : 0;   // above or below neighbour blocks
   static constexpr int YWD = SX * 2 * HF;                  // luma sub-tile row, dwords
   static constexpr int YROWS = SY * 8 * VF;
@@ -99,19 +108,20 @@ struct SegCfg {
   static constexpr int OFF_STAGE = 0;
   static constexpr int OFF_Y = OFF_STAGE + N_SLOT * 128;
   static constexpr int OFF_C = OFF_Y + Y_BYTES;
-  static constexpr int OFF_Q = OFF_C + 2 * CROWS * CWD * 4;     // quant tables, uint16 pairs
-  static constexpr int OFF_Q16 = OFF_Q + 3 * 128;               // the same times 16
-  static constexpr int LDS_BYTES = OFF_Q16 + 3 * 128;
+  static constexpr int OFF_Q = OFF_C + 2 * CROWS * CWD * 4;     // islow: quant tables, uint16 pairs; AAN: 32-bit multipliers
+  static constexpr int OFF_Q16 = OFF_Q + (ISLOW ? 3 * 128 : 3 * 256);  // islow: the same times 16
+  static constexpr int LDS_BYTES = OFF_Q16 + (ISLOW ? 3 * 128 : 0);
   // Waves per SIMD that the LDS footprint allows (160 KB per CU), at most 3
   // asked of the register allocator; the 4:2:0 fancy class, which holds the
   // most state (neighbour rows and row pairs of chroma), asks for 2, which
   // leaves it 256 registers.
   static constexpr int WAVES_PER_SIMD_LDS = (160 * 1024 / LDS_BYTES) * (NT / 64) / 4;
-  static constexpr int WAVES_CAP = HALO_Y ? 2 : 3;
+  static constexpr int WAVES_CAP = HALO_Y && ISLOW ? 2 : 3;
   static constexpr int WAVES_PER_SIMD =
       WAVES_PER_SIMD_LDS < 1 ? 1 : (WAVES_PER_SIMD_LDS > WAVES_CAP ? WAVES_CAP : WAVES_PER_SIMD_LDS);
   static_assert(P1_LANES <= NT, "one phase-1 round per sub-tile");
   static_assert(NT % 64 == 0 && NT >= 96, "whole waves; quant table load needs 96 lanes");
+  static_assert(!HALO_Y || HF <= 2, "vertical fancy filtering with HF 1 or 2");
   static_assert(N_MAIN % 64 == 0, "tile blocks fill whole waves");
   static_assert(!HALO_Y || (N_TB * 128 <= Y_BYTES && N_TB <= N_SLOT),
                 "the neighbour rows' blocks fit the buffers they borrow");
@@ -130,18 +140,19 @@ struct SegmentDecoder {
 
   lds8* lds;
   const ImageView& im;
+  const AanConsts* ak;  // the AAN methods' constants (unused by islow)
   int tid;
   // segment geometry
   int mx0, nmx, r0, r1, K;
   int gcx0;  // global chroma column of the strip's first sample
 
-  __device__ SegmentDecoder(uint8_t* lds_, const ImageView& im_, int tid_)
-      : lds((lds8*)lds_), im(im_), tid(tid_) {}
+  __device__ SegmentDecoder(uint8_t* lds_, const ImageView& im_, int tid_, const AanConsts* ak_ = nullptr)
+      : lds((lds8*)lds_), im(im_), ak(ak_), tid(tid_) {}
 
   __device__ lds8* stage() const { return lds + C::OFF_STAGE; }
   __device__ lds32* luma() const { return reinterpret_cast<lds32*>(lds + C::OFF_Y); }
   __device__ lds32* cring(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_C) + c * (CROWS * CWD); }
-  __device__ lds32* qtab(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q) + c * 32; }
+  __device__ lds32* qtab(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q) + c * (C::ISLOW ? 32 : 64); }
   __device__ lds32* qtab16(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q16) + c * 32; }
 
   // Luma row r (0 <= r < YROWS) of sub-tile k lives in row ybase(k) + r of
@@ -231,6 +242,16 @@ struct SegmentDecoder {
   }
 
   __device__ void load_qtabs() const {
+    if constexpr (!C::ISLOW) {
+      // the method's 64 multipliers per component
+      for (int i = tid; i < 192; i += NT) {
+        const int c = i >> 6, e = i & 63;
+        const int sel = c == 0 ? im.qsel0 : (c == 1 ? im.qsel1 : im.qsel2);
+        const uint32_t q = im.qt[sel * 64 + e];
+        reinterpret_cast<ldsi*>(qtab(c))[e] = C::IDCT == 1 ? aan_ifast_mult(q, e, *ak) : aan_float_mult(q, e, *ak);
+      }
+      return;
+    }
     if (tid < 96) {
       const int c = tid >> 5;
       const int sel = c == 0 ? im.qsel0 : (c == 1 ? im.qsel1 : im.qsel2);
@@ -288,6 +309,27 @@ struct SegmentDecoder {
     const int t = tid, pos = t >> 1;
     const int mx = mx0 - 1 + pos;
     if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) return;
+    if constexpr (!C::ISLOW) {
+      // the AAN methods: the one row on this lane
+      const lds8* blk = tb_area(below) + t * 128;
+      v4i rows[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        rows[c] = *reinterpret_cast<const __attribute__((address_space(3))) v4i*>(blk + (((c + t) & 7) << 4));
+      uint32_t lo, hi;
+      aan_block_row<C::IDCT>(rows, reinterpret_cast<const ldsi*>(qtab(1 + (t & 1))), *ak, !below, &lo, &hi);
+      lds32* row = cring(t & 1) + (below ? below_row() : CROWS - 1) * CWD;
+      row[2 * pos] = lo;
+      row[2 * pos + 1] = hi;
+      lds8* row8 = reinterpret_cast<lds8*>(row);
+      if (mx0 == 0 && mx == 0) row8[7] = static_cast<uint8_t>(lo);
+      const int cw = im.chroma_w;
+      if (cw - 1 < gcx0 + 8 * nmx && mx == ((cw - 1) >> 3)) {
+        const int e = (cw - 1) & 7;
+        row8[cw - gcx0 + 8] = static_cast<uint8_t>((e < 4 ? lo : hi) >> (8 * (e & 3)));
+      }
+      return;
+    }
     typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
     const lds8* blk = tb_area(below) + t * 128;
     const __attribute__((address_space(3))) v4i* qv =
@@ -357,8 +399,11 @@ struct SegmentDecoder {
   };
 
   __device__ void read_stage(int k, Held& h) const {
-    if (tid < N_MAIN) {
-      const int j = tid;
+    // lanes that transform a whole block: the sub-tile's, and for the AAN
+    // methods also one per side block
+    const bool whole = tid < N_MAIN || (!C::ISLOW && HALO_X && tid >= C::SIDE_LANE0 && tid < C::P1_LANES);
+    if (whole) {
+      const int j = tid < N_MAIN ? tid : N_MAIN + (tid - C::SIDE_LANE0);
       const lds8* blk = stage() + j * 128;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
@@ -378,6 +423,14 @@ struct SegmentDecoder {
     (void)k;
   }
 
+  // Dequantise + IDCT of one block held in registers (rows in natural
+  // order), by the configured method: out[2r], out[2r + 1] the packed
+  // samples 0..3 and 4..7 of row r.
+  __device__ void block(const v4i rows[8], int comp, uint32_t out[16]) const {
+    if constexpr (C::ISLOW) idct_block_fast(rows, qtab(comp), qtab16(comp), out);
+    else aan_block<C::IDCT>(rows, reinterpret_cast<const ldsi*>(qtab(comp)), *ak, out);
+  }
+
   __device__ void phase1(int k, const Held& h) const {
     const int nmy = sub_rows(k);
     if (tid < N_MAIN) {
@@ -389,7 +442,7 @@ struct SegmentDecoder {
       const int comp = b < NY ? 0 : b - NY + 1;
       uint32_t o[16];
       const v4i rows[8] = {h.r0, h.r1, h.r2, h.r3, h.r4, h.r5, h.r6, h.r7};
-      idct_block_fast(rows, qtab(comp), qtab16(comp), o);
+      block(rows, comp, o);
       if (comp == 0) {
         const int by = b / HF, bx = b - (b / HF) * HF;
         lds32* dst = yrow(ybase(k), lmy * 8 * VF + by * 8) + lmx * 2 * HF + bx * 2;
@@ -426,6 +479,24 @@ struct SegmentDecoder {
               row8[r * CWD * 4 + e + 9] = static_cast<uint8_t>((o[2 * r] ^ ((o[2 * r] ^ o[2 * r + 1]) & hi)) >> sh);
           }
         }
+      }
+    } else if constexpr (HALO_X && !C::ISLOW) {
+      // a side block on one lane: the whole block, then the one column the
+      // filter reads (0 of the block right of the strip, 7 of the one left)
+      if (tid >= C::SIDE_LANE0 && tid < C::P1_LANES) {
+        const int t = tid - C::SIDE_LANE0;
+        const int pos = t >> 2;
+        const bool right = (t >> 1) & 1;
+        const int mx = right ? mx0 + nmx : mx0 - 1;
+        if (pos >= nmy || mx < 0 || mx >= im.mcus_x) return;
+        uint32_t o[16];
+        const v4i rows[8] = {h.r0, h.r1, h.r2, h.r3, h.r4, h.r5, h.r6, h.r7};
+        block(rows, 1 + (t & 1), o);
+        lds8* row8 = reinterpret_cast<lds8*>(cring(t & 1) + (cbase(k) + 8 * pos) * CWD);
+        const int x = right ? nmx * 8 + 8 : 7;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          row8[r * CWD * 4 + x] = static_cast<uint8_t>(right ? o[2 * r] : o[2 * r + 1] >> 24);
       }
     } else if constexpr (HALO_X) {
       if (tid >= C::SIDE_LANE0 && tid < C::P1_LANES) {
@@ -561,27 +632,37 @@ struct SegmentDecoder {
   // and the last two rows of sub-tile k-2 (the last of which needs the first
   // row of k-1), as pairs of rows: one pair of rows and 4 samples per lane.
   __device__ void phase2_pairs(int k) const {
-    static_assert(NT == (C::CR / 2) * C::UX, "the row pairs of a sub-tile fill the workgroup once");
+    // work items: (row pair rp, unit g), rp 0 the tail pair of k - 2; a
+    // workgroup of fewer lanes than items takes them in turns
+    constexpr int ITEMS = (C::CR / 2) * C::UX;
+    static_assert(ITEMS % NT == 0, "the row pairs of a sub-tile fill the workgroup a whole number of times");
     const bool has_a = k >= 1 && k <= K;
     const bool has_b = k >= 2 && k <= K + 1;
     if (!has_a && !has_b) return;
     const SubInfo sa = uniform(sub_info(has_a ? k - 1 : 0)), sb = uniform(sub_info(has_b ? k - 2 : 0));
-    const int g = tid % C::UX, rp = tid / C::UX;
-    const bool tail = rp == 0;
-    if (g >= 2 * nmx || (tail ? !has_b : !has_a)) return;
-    SubInfo si;
-    si.rgb = tail ? sb.rgb : sa.rgb;
-    si.gcy0 = tail ? sb.gcy0 : sa.gcy0;
-    si.yb = tail ? sb.yb : sa.yb;
-    si.cb = tail ? sb.cb : sa.cb;
-    const int cr = tail ? sb.rows - 2 : 2 * (rp - 1);
-    if (!tail && cr >= sa.rows - 2) return;
     // every unit of the strip is whole and its rows 4-byte aligned: the
     // plain store path alone
-    if (im.aligned_out && (gcx0 + 8 * nmx) * 2 <= im.width)
-      unit_pair<true>(si, cr, g);
-    else
-      unit_pair<false>(si, cr, g);
+    const bool plain = im.aligned_out && (gcx0 + 8 * nmx) * HF <= im.width;
+#pragma unroll
+    for (int it = tid; it < ITEMS; it += NT) {
+      const int g = it % C::UX, rp = it / C::UX;
+      const bool tail = rp == 0;
+      if (g >= 2 * nmx || (tail ? !has_b : !has_a)) continue;
+      SubInfo si;
+      si.rgb = tail ? sb.rgb : sa.rgb;
+      si.gcy0 = tail ? sb.gcy0 : sa.gcy0;
+      si.yb = tail ? sb.yb : sa.yb;
+      si.cb = tail ? sb.cb : sa.cb;
+      const int cr = tail ? sb.rows - 2 : 2 * (rp - 1);
+      if (!tail && cr >= sa.rows - 2) continue;
+      if constexpr (HF == 2) {
+        if (plain) unit_pair<true>(si, cr, g);
+        else unit_pair<false>(si, cr, g);
+      } else {
+        if (plain) unit_pair_v<true>(si, cr, g);
+        else unit_pair_v<false>(si, cr, g);
+      }
+    }
   }
 
   // 3 a + b on 16-bit halves (every value here is below 2^12)
@@ -705,6 +786,67 @@ struct SegmentDecoder {
     }
   }
 
+  // Chroma rows cr and cr + 1 of a sub-tile's strip, samples 4g..4g+3
+  // (h1v2 fancy: the 3:1 filter turned vertical, no horizontal filter):
+  // four output rows of 4 pixels.
+  template <bool PLAIN>
+  __device__ void unit_pair_v(const SubInfo& si, const int cr, const int g) const {
+    const int W = im.width, H = im.height;
+    const int px0 = gcx0 + 4 * g;
+    const int gy = si.gcy0 + cr;
+    const int py0 = 2 * gy;
+    if (px0 >= W || py0 >= H) return;
+    const int ch = im.chroma_h;
+    const int rc = si.cb + cr;  // ring row of row cr; rc + 1 is row cr + 1
+    const int ru = gy == 0 ? rc : ring_prev(rc);
+    const bool last0 = gy == ch - 1;
+    const int rd = gy + 1 >= ch - 1 ? rc + 1 : ring_next(rc + 1);
+    uint32_t cu[2], c0[2], c1[2], cd[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const lds32* ring = cring(c) + (g + 2);
+      cu[c] = ring[mul24(ru, CWD)];
+      c0[c] = ring[mul24(rc, CWD)];
+      c1[c] = ring[mul24(rc + 1, CWD)];
+      cd[c] = ring[mul24(rd, CWD)];
+      if (last0) c1[c] = c0[c];
+    }
+    const int ly = si.yb + 2 * cr;
+    const int nv = min(4, W - px0);
+    const int pitch24 = static_cast<int>(im.pitch);
+    gbl8* row = si.rgb + (mul24(2 * cr, pitch24) + 12 * g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (py0 + j >= H) break;
+      const uint32_t yd = luma()[mul24(ywrap(ly + j), YWD) + g];
+      int x[2][4];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        // (3 near + far + 1) >> 2 on even output rows, + 2 on odd ones
+        const uint32_t nr = j < 2 ? c0[c] : c1[c];
+        const uint32_t fr = j == 0 ? cu[c] : (j == 3 ? cd[c] : (j == 1 ? c1[c] : c0[c]));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          x[c][i] = ((3 * static_cast<int>(byte_at(nr, i)) + static_cast<int>(byte_at(fr, i)) + 1 + (j & 1)) >> 2) - 128;
+      }
+      RGBWide px[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) px[i] = ycc_wide(y16_of(yd, i), x[0][i], x[1][i]);
+      uint32_t w[3];
+      pack_rgb4(px, w);
+      if (PLAIN || (nv == 4 && im.aligned_out)) {
+        gbl32* wd = reinterpret_cast<gbl32*>(row);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
+      } else if (nv == 4) {
+        store_shifted(row, w);
+      } else {
+        store_ragged(row, w, 3 * nv);
+      }
+      row += pitch24;
+    }
+  }
+
   // One unit: chroma samples 4g..4g+3 of row cr_l of a sub-tile's strip,
   // i.e. 4*HF x VF pixels.
   __device__ void unit(const SubInfo& si, const int cr_l, const int g) const {
@@ -729,7 +871,7 @@ struct SegmentDecoder {
         const lds32* ring = cring(c);
         const lds32* plane = ring + (mul24(rc, CWD) + g + 2);
         int out[VF][4 * HF];
-        if constexpr (!FANCY || HF == 1) {
+        if constexpr (!FANCY || HF != 2) {
           const uint32_t w = plane[0];
 #pragma unroll
           for (int i = 0; i < 4; ++i)

@@ -29,6 +29,7 @@
 #include <atomic>
 #include <mutex>
 
+#include "aan.h"
 #include "mjd_internal.h"
 
 // The float method rounds once per operation, in the order written: no
@@ -41,21 +42,12 @@ namespace var {
 
 constexpr int kBlocksPerWG = 32;
 constexpr int kThreads = 8 * kBlocksPerWG;
-constexpr int kIfastFrac = 6;
-constexpr int kIfastConstBits = 9;
-constexpr int kIfastShift = kIfastFrac + 3;
+}  // namespace var
 
-// Scale factors and constants, computed once on the host with the C
-// library's cos and passed by value.
-struct Consts {
-  double ss8[64];   // 8 * (s(u) * s(v)), index 8u + v
-  int32_t a14[64];  // round(2^14 / (s(u) * s(v)))
-  int32_t ki[4];    // round(c * 2^9) of cos(pi/4), cos(3pi/8), cos(pi/8) -+ cos(3pi/8)
-  float kf[4];      // the same constants in fp32
-};
-
-const Consts& consts() {
-  static Consts k;
+// Scale factors and constants of the AAN methods (aan.h), from the C
+// library's cos, once.
+const AanConsts& aan_consts() {
+  static AanConsts k;
   static std::once_flag once;
   std::call_once(once, [] {
     double s[8];
@@ -76,6 +68,10 @@ const Consts& consts() {
   });
   return k;
 }
+
+namespace var {
+
+using Consts = AanConsts;
 
 // Constants of the reduced transforms: K[m][u] = round(2^13 sqrt(2)
 // cos((2m+1) u pi / 2N)), index N*m + u.
@@ -111,59 +107,6 @@ struct View {
   int qsel[3];
   int comp_w, comp_h;  // the chroma components' true size
 };
-
-// --- the transposed AAN flowgraph ------------------------------------------
-// Outputs in sample order from inputs in frequency order; sums left to right.
-struct IfastOps {
-  int r, c5, c2, c4;
-  __device__ int mul_r(int v) const { return (v * r) >> kIfastConstBits; }
-  __device__ int mul_c5(int v) const { return (v * c5) >> kIfastConstBits; }
-  __device__ int mul_c2(int v) const { return (v * c2) >> kIfastConstBits; }
-  __device__ int mul_c4(int v) const { return (v * c4) >> kIfastConstBits; }
-};
-struct FloatOps {
-  float r, c5, c2, c4;
-  __device__ float mul_r(float v) const { return v * r; }
-  __device__ float mul_c5(float v) const { return v * c5; }
-  __device__ float mul_c2(float v) const { return v * c2; }
-  __device__ float mul_c4(float v) const { return v * c4; }
-};
-
-__device__ __forceinline__ int add_(int a, int b) { return a + b; }
-__device__ __forceinline__ int sub_(int a, int b) { return a - b; }
-__device__ __forceinline__ float add_(float a, float b) { return a + b; }
-__device__ __forceinline__ float sub_(float a, float b) { return a - b; }
-
-template <class T, class Ops>
-__device__ __forceinline__ void aan8(const T y[8], T x[8], const Ops& k) {
-  // even part
-  const T t10 = add_(y[0], y[4]);
-  const T t11 = sub_(y[0], y[4]);
-  const T u = k.mul_r(sub_(y[2], y[6]));
-  const T t13 = add_(add_(y[2], y[6]), u);
-  const T e0 = add_(t10, t13), e3 = sub_(t10, t13);
-  const T e1 = add_(t11, u), e2 = sub_(t11, u);
-  // odd part
-  const T z13 = add_(y[5], y[3]);
-  const T z2 = sub_(y[5], y[3]);
-  const T z11 = add_(y[1], y[7]);
-  const T z4 = sub_(y[1], y[7]);
-  const T a11 = k.mul_r(sub_(z11, z13));
-  const T t = k.mul_c5(add_(z2, z4));
-  const T a10 = add_(k.mul_c2(z2), t);
-  const T a12 = sub_(k.mul_c4(z4), t);
-  const T o5 = add_(a10, a11);
-  const T o6 = add_(a11, a12);
-  const T o7 = add_(add_(z11, z13), a12);
-  x[0] = add_(e0, o7);
-  x[1] = add_(e1, o6);
-  x[2] = add_(e2, o5);
-  x[3] = add_(e3, a10);
-  x[4] = sub_(e3, a10);
-  x[5] = sub_(e2, o5);
-  x[6] = sub_(e1, o6);
-  x[7] = sub_(e0, o7);
-}
 
 __device__ __forceinline__ uint32_t clamp_u8(int v) { return static_cast<uint32_t>(min(max(v, 0), 255)); }
 
@@ -571,6 +514,37 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   const uint64_t row_bytes = static_cast<uint64_t>(nc) * out_w;
   if (pitch < row_bytes) return fail(MJD_EINVAL, "pitch %zu < %u*width", pitch, nc);
   if (pitch >= (1ull << 31)) return fail(MJD_EINVAL, "pitch %zu not below 2^31 bytes", pitch);
+  const bool fused = nc == 3 && scale == 1;
+  if (fused) {
+    // full-size colour images: the fused segment kernel of the sampling and
+    // IDCT method, one launch, no sample planes in memory
+    if (pitch >= (1ull << 24)) return fail(MJD_EINVAL, "pitch %zu not below 2^24 bytes", pitch);
+    ImageView im{};
+    im.coef = d_coef;
+    im.qt = d_qt;
+    im.rgb = d_out;
+    im.pitch = static_cast<uint32_t>(pitch);
+    im.width = static_cast<int>(variant->frame.width);
+    im.height = static_cast<int>(variant->frame.height);
+    im.mcus_x = static_cast<int>(g.mcus_x);
+    im.mcus_y = static_cast<int>(g.mcus_y);
+    im.chroma_w = static_cast<int>(g.comp_w[1]);
+    im.chroma_h = static_cast<int>(g.comp_h[1]);
+    im.qsel0 = static_cast<int>(variant->frame.qsel[0]);
+    im.qsel1 = static_cast<int>(variant->frame.qsel[1]);
+    im.qsel2 = static_cast<int>(variant->frame.qsel[2]);
+    im.aligned_out = (reinterpret_cast<uintptr_t>(d_out) % 4 == 0 && pitch % 4 == 0) ? 1 : 0;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
+      if (hipSetDevice(ctx->device) != hipSuccess) return fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    }
+    const hipError_t e = launch_variant(im, static_cast<int>(variant->frame.h[0]), static_cast<int>(variant->frame.v[0]),
+                                        variant->upsample == MJD_UPSAMPLE_FANCY, variant->idct, ctx->cu_count,
+                                        static_cast<hipStream_t>(stream));
+    if (cur != ctx->device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return fail(MJD_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    return MJD_OK;
+  }
   if (nc == 3) {
     if (!d_work) return fail(MJD_EINVAL, "null workspace");
     if (reinterpret_cast<uintptr_t>(d_work) % 16) return fail(MJD_EINVAL, "workspace not 16-byte aligned");
@@ -601,7 +575,7 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
     if (hipSetDevice(ctx->device) != hipSuccess) return fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
   }
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  const var::Consts& k = var::consts();
+  const AanConsts& k = aan_consts();
   const uint64_t n_tiles = (g.n_blocks + var::kBlocksPerWG - 1) / var::kBlocksPerWG;
   hipError_t e;
   const unsigned grid_red = static_cast<unsigned>((g.n_blocks + 255) / 256);

@@ -126,16 +126,23 @@ def test_bad_calls_are_refused(M, ctx):
     fr = {"width": 64, "height": 64, "h": (2, 1, 1), "v": (2, 1, 1), "qsel": (0, 1, 1)}
     v = M.make_variant(fr, 3, "ifast")
     g, wb = M.mjd_variant_geometry(v)
+    assert wb == 0  # full size: the fused pass needs no workspace
     cd = torch.zeros(g["n_blocks"] * 64, dtype=torch.int16, device="cuda")
     qd = torch.ones(256, dtype=torch.int16, device="cuda")
     out = torch.empty((64, 64, 3), dtype=torch.uint8, device="cuda")
-    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
-    for args in ((cd, qd, out, 192, work, wb - 1),      # workspace too small
-                 (cd, qd, out, 191, work, wb),          # pitch below 3 * width
-                 (cd, qd, out, 192, 0, wb),             # no workspace
-                 (cd.data_ptr() + 2, qd, out, 192, work, wb)):  # misaligned coefficients
+    for args in ((cd, qd, out, 191, 0, 0),                # pitch below 3 * width
+                 (cd, qd, out, 1 << 24, 0, 0),            # pitch not below 2^24 (fused pass)
+                 (cd.data_ptr() + 2, qd, out, 192, 0, 0)):  # misaligned coefficients
         with pytest.raises(M.MjdError):
             M.mjd_decode_variant(ctx, v, *args)
+    vs = M.make_variant(fr, 3, "islow", "fancy", 2)
+    gs, wbs = M.mjd_variant_geometry(vs)
+    work = torch.empty(wbs, dtype=torch.uint8, device="cuda")
+    small = torch.empty((32, 32, 3), dtype=torch.uint8, device="cuda")
+    for args in ((cd, qd, small, 96, work, wbs - 1),      # workspace too small
+                 (cd, qd, small, 96, 0, wbs)):            # no workspace
+        with pytest.raises(M.MjdError):
+            M.mjd_decode_variant(ctx, vs, *args)
     torch.cuda.synchronize()
 
 
