@@ -123,8 +123,7 @@ struct SegCfg {
   static_assert(NT % 64 == 0 && NT >= 96, "whole waves; quant table load needs 96 lanes");
   static_assert(!HALO_Y || HF <= 2, "vertical fancy filtering with HF 1 or 2");
   static_assert(N_MAIN % 64 == 0, "tile blocks fill whole waves");
-  static_assert(!HALO_Y || (N_TB * 128 <= Y_BYTES && N_TB <= N_SLOT),
-                "the neighbour rows' blocks fit the buffers they borrow");
+  static_assert(!HALO_Y || N_TB <= N_SLOT, "the blocks below a segment fit the staging buffer");
   static_assert(YROWS % 8 == 0 && CROWS % CR == 0, "blocks never straddle a ring's wrap");
 };
 
@@ -213,8 +212,9 @@ struct SegmentDecoder {
     return pos < nmy && mx >= 0 && mx < im.mcus_x;
   }
 
-  // Copy sub-tile k's blocks into the staging buffer.
-  __device__ void dma(int k) const {
+  // Copy sub-tile k's blocks into the staging buffer, on the lanes from
+  // lane0 (a multiple of 64) on.
+  __device__ void dma(int k, int lane0 = 0) const {
     const uint8_t* src0 = reinterpret_cast<const uint8_t*>(block_ptr(sub_r0(k), mx0, 0));
     const int nmy = sub_rows(k);
     const int row_bytes = im.mcus_x * (BPM * 128);
@@ -222,8 +222,8 @@ struct SegmentDecoder {
     const uint32_t lane_off = static_cast<uint32_t>(lane_chunk_offset(lane));
     const int main_blocks = nmx * BPM;  // staged blocks of each run that exist
     // the wave's first chunk, as a scalar (every lane of a wave has the same)
-    const int wave0 = __builtin_amdgcn_readfirstlane(tid & ~63);
-    for (int base = wave0; base < DMA_CHUNKS; base += NT) {
+    const int wave0 = __builtin_amdgcn_readfirstlane((tid - lane0) & ~63);
+    for (int base = wave0; base < DMA_CHUNKS; base += NT - lane0) {
       lds_void_t* dst = (lds_void_t*)(stage() + base * 16);
       const int J = base >> 3;
       if (J < N_MAIN) {
@@ -268,20 +268,19 @@ struct SegmentDecoder {
     }
   }
 
-  // ---- neighbour blocks above/below the segment (4:2:0 fancy) ----
-  // The chroma blocks of the MCU row above the segment (fetched with sub-tile
-  // 0, into the luma ring, which phase 1 first writes after they are read) and
-  // below it (fetched after the last sub-tile, into the then idle staging
-  // buffer) arrive by DMA like the sub-tiles, in the same rotated layout.
-  __device__ lds8* tb_area(bool below) const {
-    return below ? stage() : reinterpret_cast<lds8*>(luma());
-  }
+  // ---- neighbour blocks above/below the segment (vertical fancy filter) ----
+  // The chroma blocks of the MCU row below the segment are fetched after the
+  // last sub-tile into the then idle staging buffer, by DMA like the
+  // sub-tiles, in the same rotated layout.  Those of the row above are
+  // loaded straight into the registers of the lanes that form their row
+  // (run()'s prologue).
+  __device__ lds8* tb_area() const { return stage(); }
 
-  __device__ void dma_tb(bool below) const {
-    const int my = below ? r1 : r0 - 1;
-    if (my < 0 || my >= im.mcus_y) return;
+  __device__ void dma_tb_below() const {
+    const int my = r1;
+    if (my >= im.mcus_y) return;
     constexpr int CHUNKS = N_TB * 8;
-    lds8* area = tb_area(below);
+    lds8* area = tb_area();
     for (int base = (tid & ~63); base < CHUNKS; base += NT) {
       const int i = base + (tid & 63);
       if (i < CHUNKS) {
@@ -303,19 +302,45 @@ struct SegmentDecoder {
   // over the 8 results; the samples go into the ring row above/below the
   // segment.  At the true left edge and at the true right chroma edge the
   // lane also writes the replicated sample the filter reads beyond the edge.
-  __device__ void tb_edge(bool below) const {
+  // The neighbour block of lane t (< N_TB) above or below the segment, or
+  // false where that MCU lies outside the image.
+  __device__ bool tb_block(bool below, int* pos, int* mx) const {
     const int my = below ? r1 : r0 - 1;
-    if (my < 0 || my >= im.mcus_y || tid >= N_TB) return;
-    const int t = tid, pos = t >> 1;
-    const int mx = mx0 - 1 + pos;
-    if (pos >= nmx + 2 || mx < 0 || mx >= im.mcus_x) return;
+    *pos = tid >> 1;
+    *mx = mx0 - 1 + *pos;
+    return my >= 0 && my < im.mcus_y && tid < N_TB && *pos < nmx + 2 && *mx >= 0 && *mx < im.mcus_x;
+  }
+
+  // The staged block below the segment, rows in natural order.
+  __device__ void tb_rows_lds(v4i rows[8]) const {
+    const lds8* blk = tb_area() + tid * 128;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      rows[c] = *reinterpret_cast<const __attribute__((address_space(3))) v4i*>(blk + (((c + tid) & 7) << 4));
+  }
+
+  // The block above the segment straight from global memory (issued early,
+  // used after the quant tables are in LDS).
+  __device__ void tb_rows_global(int mx, v4i rows[8]) const {
+    const __attribute__((address_space(1))) v4i* src =
+        (const __attribute__((address_space(1))) v4i*)(block_ptr(r0 - 1, mx, NY + (tid & 1)));
+#pragma unroll
+    for (int c = 0; c < 8; ++c) rows[c] = src[c];
+  }
+
+  // The row below the segment, from the staged blocks.
+  __device__ void tb_edge_below() const {
+    int pos, mx;
+    if (!tb_block(true, &pos, &mx)) return;
+    v4i rows[8];
+    tb_rows_lds(rows);
+    tb_row(true, pos, mx, rows);
+  }
+
+  __device__ void tb_row(bool below, int pos, int mx, const v4i rows[8]) const {
+    const int t = tid;
     if constexpr (!C::ISLOW) {
       // the AAN methods: the one row on this lane
-      const lds8* blk = tb_area(below) + t * 128;
-      v4i rows[8];
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        rows[c] = *reinterpret_cast<const __attribute__((address_space(3))) v4i*>(blk + (((c + t) & 7) << 4));
       uint32_t lo, hi;
       aan_block_row<C::IDCT>(rows, reinterpret_cast<const ldsi*>(qtab(1 + (t & 1))), *ak, !below, &lo, &hi);
       lds32* row = cring(t & 1) + (below ? below_row() : CROWS - 1) * CWD;
@@ -331,13 +356,12 @@ struct SegmentDecoder {
       return;
     }
     typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-    const lds8* blk = tb_area(below) + t * 128;
     const __attribute__((address_space(3))) v4i* qv =
         reinterpret_cast<const __attribute__((address_space(3))) v4i*>(qtab(1 + (t & 1)));
     uint32_t d[8][4];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const v4i v = *reinterpret_cast<const __attribute__((address_space(3))) v4i*>(blk + (((c + t) & 7) << 4));
+      const v4i v = rows[c];
       const v4i qq = qv[c];
       const int w[4] = {v.x, v.y, v.z, v.w};
       const int qw[4] = {qq.x, qq.y, qq.z, qq.w};
@@ -1003,16 +1027,24 @@ struct SegmentDecoder {
     __syncthreads();  // the previous segment's readers are done with every buffer
     __builtin_amdgcn_s_setprio(3);
     load_qtabs();
-    dma(0);
     if constexpr (HALO_Y) {
-      dma_tb(false);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      // The first waves fetch the blocks above the segment straight into
+      // registers and form their one row (into the ring row above the
+      // segment, which phase 2 first reads one step later) while the other
+      // waves' DMA of sub-tile 0 is in flight.
+      constexpr int TBL = round64c(N_TB);
+      static_assert(TBL < NT, "waves left for the DMA");
+      int pos, mx;
+      const bool tb = tb_block(false, &pos, &mx);
+      v4i rows[8];
+      if (tb) tb_rows_global(mx, rows);
+      if (tid >= TBL) dma(0, TBL);
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");  // quant tables visible
+      if (tb) tb_row(false, pos, mx, rows);
+    } else {
+      dma(0);
+      __syncthreads();  // quant tables visible
     }
-    __syncthreads();  // quant tables (and the blocks above) visible
-    // the row above: phase 1 first writes the luma ring (where its blocks
-    // sit) after the next barrier; phase 2 first reads the ring row one step
-    // later
-    if constexpr (HALO_Y) tb_edge(false);
 
     for (int k = 0; k < K + LAG; ++k) {
       Held h{};  // per step, fully defined so it stays in registers
@@ -1029,7 +1061,7 @@ struct SegmentDecoder {
       if constexpr (HALO_Y) {
         // the row below (its blocks were staged after the last sub-tile):
         // phase 2 of the next step reads it
-        if (k == K) tb_edge(true);
+        if (k == K) tb_edge_below();
         if (k < K) read_stage(k, h);
         // Phase 2 reads the luma rows that phase 1 of k overwrites in the
         // ring, so it goes first, in the interval that also frees the
@@ -1037,7 +1069,7 @@ struct SegmentDecoder {
         phase2_pairs(k);
         __syncthreads();  // staging free; phase 2's luma rows read
         if (k + 1 < K) dma(k + 1);
-        if (k + 1 == K) dma_tb(true);  // staging is idle from here on
+        if (k + 1 == K) dma_tb_below();  // staging is idle from here on
       } else {
         if (k < K) read_stage(k, h);
         __syncthreads();  // staging free for the next sub-tile
