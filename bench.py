@@ -60,7 +60,7 @@ def parse():
 
 
 PROFILE = os.path.join(ROOT, "profiles", "decode_segments_420_fancy_4096x3072.md")
-KERNEL_SOURCES = ("segment.h", "decode_kernel.h", "decode.hip")
+KERNEL_SOURCES = ("segment.h", "decode_kernel.h", "aan.h", "decode.hip")
 
 
 def profiled_traffic():
@@ -89,8 +89,8 @@ def tuning_report(entry, source):
     best = entry["best"]
     keep = ("shape", "sx", "sy", "threads", "resident_per_cu", "workgroups_per_cu", "workgroups", "seg_subtiles",
             "ms", "ms_refined", "segments", "launched")
-    return {"source": source, "choice": {k: best[k] for k in keep if k in best}, "interior": entry["interior"],
-            "ranges": entry["ranges"], "candidates": entry["candidates"]}
+    return {"source": source, "cache_key": entry.get("key"), "choice": {k: best[k] for k in keep if k in best},
+            "interior": entry["interior"], "ranges": entry["ranges"], "candidates": entry["candidates"]}
 
 
 def log(msg):

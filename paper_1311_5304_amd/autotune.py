@@ -25,7 +25,7 @@ from . import _binding as B
 PKG = os.path.dirname(os.path.abspath(__file__))
 # sources the decode kernels are built from: a change to any of them
 # invalidates every cached choice
-KERNEL_SOURCES = ("segment.h", "decode_kernel.h", "decode.hip", "batch.hip", "mjd_internal.h", "mjd_common.h")
+KERNEL_SOURCES = ("segment.h", "decode_kernel.h", "aan.h", "decode.hip", "batch.hip", "mjd_internal.h", "mjd_common.h")
 DEFAULT_CACHE = os.path.join(PKG, "tune_cache.json")
 
 SEG_CANDIDATES = (1, 2, 3, 4, 6, 8, 12, 16)
@@ -42,9 +42,13 @@ def kernel_hash() -> str:
 
 
 def device_name(device: int = 0) -> str:
+    """The device's architecture (without its feature flags) and compute-unit
+    count: what a launch shape depends on.  (The marketing name is left out:
+    it reads differently depending on the installed ID tables and tools.)"""
     import torch
     p = torch.cuda.get_device_properties(device)
-    return f"{p.name}|{getattr(p, 'gcnArchName', '?')}|{p.multi_processor_count}CU"
+    arch = getattr(p, "gcnArchName", "?").split(":")[0]
+    return f"{arch}|{p.multi_processor_count}CU"
 
 
 def _time_ms(fn, reps: int, warmup: int = 3) -> float:
@@ -255,6 +259,7 @@ def tuned_image(ctx, frame, mode: int, coef_sets, qt, out_sets, cache: TuneCache
         e["table"] = table
         cache.put(key, e)
         source = "tuned"
+    e = dict(e, key=key)
     B.mjd_ctx_set_tuning(ctx, e["seg_subtiles"], e["workgroups"], e["shape"])
     return e, source
 
@@ -284,5 +289,6 @@ def tuned_batch(ctx, jobs, mode: int, workload: str, cache: TuneCache = None, de
         e["table"] = table
         cache.put(key, e)
         source = "tuned"
+    e = dict(e, key=key)
     B.mjd_ctx_set_tuning(ctx, e["seg_subtiles"], e["workgroups"], 0)
     return e, source
