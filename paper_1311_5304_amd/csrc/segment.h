@@ -6,22 +6,23 @@
 //   DMA      the coefficient blocks of sub-tile k+1 (and the chroma blocks of
 //            its left/right neighbour MCUs) are copied global -> LDS with
 //            global_load_lds_dwordx4, fully coalesced, into a swizzled staging
-//            buffer, while the lanes compute on sub-tile k;
+//            buffer, while the lanes compute on sub-tile k.  Each wave copies
+//            the blocks its own lanes read, so staging needs no barrier;
 //   phase 1  dequantise + 8x8 islow IDCT (paper Sec. 4.1), one block per
 //            lane, both passes in registers; samples go to an LDS luma
-//            buffer and an LDS chroma ring.  The neighbour chroma blocks the
+//            slot and an LDS chroma ring.  The neighbour chroma blocks the
 //            fancy filter needs (Sec. 4.2) are split 8 lanes per block, and
 //            only the one column the filter reads is formed, summed across
 //            the block's lanes in the wave;
 //   phase 2  upsampling + YCbCr->RGB (Sec. 4.3) + RGB8 stores (Fig. 5).
+// Step k runs phase 2 of sub-tile k-1 and then phase 1 of sub-tile k, in
+// different luma and chroma slots, so each step has one barrier, and a wave
+// goes from its stores to its transform without waiting for the others.
 // For the 4:2:0 fancy filter a sub-tile's last chroma row needs the first
-// chroma row of the next sub-tile: phase 2 of a sub-tile runs one step after
-// its phase 1 and its last row one step later still, so the rows above and
-// below a sub-tile come from the ring instead of being decoded twice; only
-// the rows above and below the whole segment are decoded as neighbour
-// blocks.  Phase 2 is issued before phase 1 of the current sub-tile, so its
-// stores drain while the IDCT runs, and the next sub-tile's DMA is in flight
-// during phase 1.  Each step has two barriers.
+// chroma row of the next sub-tile: that row pair is upsampled one step
+// later still (three slots), so the rows between sub-tiles come from the
+// ring instead of being decoded twice; only the rows just above and below
+// the whole segment are decoded as neighbour blocks, at its start.
 #pragma once
 
 #include "aan.h"
@@ -77,11 +78,6 @@ struct SegCfg {
   // fancy filtering applies to factors of 2 (a factor of 4 is replicated)
   static constexpr bool HALO_X = FANCY && HF == 2;
   static constexpr bool HALO_Y = FANCY && VF == 2;
-  // Steps by which the last phase 2 trails the last phase 1.  For the 4:2:0
-  // fancy filter a sub-tile's rows are upsampled one step after its
-  // transform, except its last chroma row, which needs the next sub-tile's
-  // first row and waits one step more.
-  static constexpr int LAG = HALO_Y ? 2 : 1;
   static constexpr int SM = SX * SY;                       // MCUs per sub-tile
   static constexpr int N_MAIN = BPM * SM;                  // blocks per sub-tile
   static constexpr int N_SIDE = HALO_X ? 4 * SY : 0;       // left/right neighbour chroma blocks
@@ -94,21 +90,23 @@ struct SegCfg {
   static constexpr int YWD = SX * 2 * HF;                  // luma sub-tile row, dwords
   static constexpr int YROWS = SY * 8 * VF;
   static constexpr int CR = 8 * SY;                        // chroma rows per sub-tile
-  // Luma: two sub-tile buffers in flight, or (4:2:0 fancy) one ring of a
-  // sub-tile plus one block row, which also keeps the previous sub-tile's
-  // last two rows while the next is transformed.
-  static constexpr int NYB = 2;
-  static constexpr int YRING = YROWS + 8;
-  static constexpr int Y_BYTES = (HALO_Y ? YRING : NYB * YROWS) * YWD * 4;
+  // Luma and chroma: one slot per sub-tile in flight, two (phase 2 of k - 1
+  // beside phase 1 of k), or three with the vertical fancy filter (the last
+  // row pair of k - 2 is also upsampled at step k).
+  static constexpr int NYB = HALO_Y ? 3 : 2;
+  static constexpr int Y_BYTES = NYB * YROWS * YWD * 4;
   static constexpr int CWD = (SX + 2) * 2;                 // chroma ring row, dwords (8-sample margins)
-  static constexpr int CROWS = (HALO_Y ? 3 : 2) * CR;      // chroma ring rows
+  static constexpr int CROWS = NYB * CR;                   // chroma ring rows
+  // with the vertical filter, one more chroma row after the ring: the row
+  // below the segment
+  static constexpr int CROWS_ALLOC = CROWS + (HALO_Y ? 1 : 0);
   static constexpr int UX = 2 * SX;                        // phase-2 units per chroma row
   static constexpr int UNITS = UX * 8 * SY;
   // LDS carve-up (bytes, 16-byte aligned pieces)
   static constexpr int OFF_STAGE = 0;
   static constexpr int OFF_Y = OFF_STAGE + N_SLOT * 128;
   static constexpr int OFF_C = OFF_Y + Y_BYTES;
-  static constexpr int OFF_Q = OFF_C + 2 * CROWS * CWD * 4;     // islow: quant tables, uint16 pairs; AAN: 32-bit multipliers
+  static constexpr int OFF_Q = OFF_C + 2 * CROWS_ALLOC * CWD * 4;     // islow: quant tables, uint16 pairs; AAN: 32-bit multipliers
   static constexpr int OFF_Q16 = OFF_Q + (ISLOW ? 3 * 128 : 3 * 256);  // islow: the same times 16
   static constexpr int LDS_BYTES = OFF_Q16 + (ISLOW ? 3 * 128 : 0);
   // Waves per SIMD that the LDS footprint allows (160 KB per CU), at most 3
@@ -123,8 +121,7 @@ struct SegCfg {
   static_assert(NT % 64 == 0 && NT >= 96, "whole waves; quant table load needs 96 lanes");
   static_assert(!HALO_Y || HF <= 2, "vertical fancy filtering with HF 1 or 2");
   static_assert(N_MAIN % 64 == 0, "tile blocks fill whole waves");
-  static_assert(!HALO_Y || N_TB <= N_SLOT, "the blocks below a segment fit the staging buffer");
-  static_assert(YROWS % 8 == 0 && CROWS % CR == 0, "blocks never straddle a ring's wrap");
+  static_assert(YROWS % 8 == 0, "whole block rows");
 };
 
 template <class C>
@@ -132,9 +129,8 @@ struct SegmentDecoder {
   static constexpr int HF = C::HF, VF = C::VF, SX = C::SX, SY = C::SY, NT = C::NT;
   static constexpr int NY = C::NY, BPM = C::BPM, SM = C::SM, N_MAIN = C::N_MAIN;
   static constexpr int N_SIDE = C::N_SIDE, N_SLOT = C::N_SLOT, N_TB = C::N_TB;
-  static constexpr int YWD = C::YWD, YROWS = C::YROWS, NYB = C::NYB, YRING = C::YRING;
+  static constexpr int YWD = C::YWD, YROWS = C::YROWS, NYB = C::NYB;
   static constexpr int CR = C::CR, CWD = C::CWD, CROWS = C::CROWS;
-  static constexpr int LAG = C::LAG;
   static constexpr bool FANCY = C::FANCY, HALO_X = C::HALO_X, HALO_Y = C::HALO_Y;
 
   lds8* lds;
@@ -150,25 +146,28 @@ struct SegmentDecoder {
 
   __device__ lds8* stage() const { return lds + C::OFF_STAGE; }
   __device__ lds32* luma() const { return reinterpret_cast<lds32*>(lds + C::OFF_Y); }
-  __device__ lds32* cring(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_C) + c * (CROWS * CWD); }
+  __device__ lds32* cring(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_C) + c * (C::CROWS_ALLOC * CWD); }
   __device__ lds32* qtab(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q) + c * (C::ISLOW ? 32 : 64); }
   __device__ lds32* qtab16(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q16) + c * 32; }
 
   // Luma row r (0 <= r < YROWS) of sub-tile k lives in row ybase(k) + r of
-  // the luma area, taken modulo YRING for the ring.  ybase is uniform.
-  __device__ static int ybase(int k) { return HALO_Y ? (YROWS * k) % YRING : (k % NYB) * YROWS; }
-  __device__ static int ywrap(int i) {
-    if constexpr (HALO_Y) i = i >= YRING ? i - YRING : i;
-    return i;
-  }
-  __device__ lds32* yrow(int base, int r) const { return luma() + ywrap(base + r) * YWD; }
-  // Chroma row r (0 <= r < CR) of sub-tile k is ring row cbase(k) + r (CROWS
-  // is a multiple of CR, so a sub-tile never wraps).  The row above the
-  // segment is ring row CROWS - 1, the row below it ring row below_row().
+  // the luma area (slot k mod NYB).  ybase is uniform.
+  __device__ static int ybase(int k) { return (k % NYB) * YROWS; }
+  __device__ lds32* yrow(int base, int r) const { return luma() + (base + r) * YWD; }
+  // Chroma row r (0 <= r < CR) of sub-tile k is ring row cbase(k) + r (a
+  // sub-tile never wraps).  The row above the segment is ring row
+  // CROWS - 1 (read at step 1, before sub-tile 2 takes that slot), the row
+  // below it row CROWS, after the ring.
   __device__ static int cbase(int k) { return (CR * k) % CROWS; }
-  __device__ int below_row() const { return (8 * (r1 - r0)) % CROWS; }
+  static constexpr int BELOW_ROW = CROWS;
   __device__ static int ring_prev(int rc) { return rc == 0 ? CROWS - 1 : rc - 1; }
   __device__ static int ring_next(int rc) { return rc == CROWS - 1 ? 0 : rc + 1; }
+  // The chroma row after the pair at ring rows rc, rc + 1 (global rows gy,
+  // gy + 1): row rc + 1 itself at the image's last chroma row, the row
+  // below the segment after the segment's last row, else the next ring row.
+  __device__ int row_after_pair(int gy, int rc) const {
+    return gy + 1 >= im.chroma_h - 1 ? rc + 1 : (gy + 2 == 8 * r1 ? BELOW_ROW : ring_next(rc + 1));
+  }
 
   __device__ int sub_r0(int k) const { return r0 + k * SY; }
   __device__ int sub_rows(int k) const { return min(SY, r1 - (r0 + k * SY)); }
@@ -192,7 +191,6 @@ struct SegmentDecoder {
   // source base, is uniform per instruction, and a lane's offset inside the
   // 8 blocks depends on its lane number only: block J + (lane >> 3), row
   // (lane - (lane >> 3)) & 7.
-  static constexpr int DMA_CHUNKS = N_SLOT * 8;
   static constexpr int RUNB = SX * BPM;
   static_assert(RUNB % 8 == 0 && N_MAIN % 64 == 0, "DMA instructions never straddle a run or the side blocks");
 
@@ -212,88 +210,113 @@ struct SegmentDecoder {
     return pos < nmy && mx >= 0 && mx < im.mcus_x;
   }
 
-  // Copy sub-tile k's blocks into the staging buffer, on the lanes from
-  // lane0 (a multiple of 64) on.
-  __device__ void dma(int k, int lane0 = 0) const {
+  // Copy sub-tile k's blocks into the staging buffer.  Each wave copies
+  // exactly the blocks its own lanes read in read_stage (main block J is
+  // read by lane J; side chunk s by the side lanes from SIDE_LANE0 + s,
+  // islow, or by the first side wave, AAN), so a wave needs no other
+  // wave's copies before it reads.  Lanes whose block lies outside the
+  // image or below the sub-tile read the sub-tile's first block instead,
+  // into a slot nothing reads, so the copy loop has no branches.
+  static constexpr int SIDE_CHUNKS = 8 * N_SIDE;
+  static constexpr int SIDE_W0 = C::SIDE_LANE0 / 64;
+  static constexpr int SIDE_INSTR = (SIDE_CHUNKS + 63) / 64;
+  __device__ void dma(int k) const {
     const uint8_t* src0 = reinterpret_cast<const uint8_t*>(block_ptr(sub_r0(k), mx0, 0));
     const int nmy = sub_rows(k);
     const int row_bytes = im.mcus_x * (BPM * 128);
     const int lane = tid & 63;
     const uint32_t lane_off = static_cast<uint32_t>(lane_chunk_offset(lane));
     const int main_blocks = nmx * BPM;  // staged blocks of each run that exist
-    // the wave's first chunk, as a scalar (every lane of a wave has the same)
-    const int wave0 = __builtin_amdgcn_readfirstlane((tid - lane0) & ~63);
-    for (int base = wave0; base < DMA_CHUNKS; base += NT - lane0) {
-      lds_void_t* dst = (lds_void_t*)(stage() + base * 16);
-      const int J = base >> 3;
-      if (J < N_MAIN) {
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (wv < N_MAIN / 64) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int J = 64 * wv + 8 * i;  // first of the instruction's 8 blocks
         const int run = J / RUNB;
         const int jr = J - run * RUNB;
-        const uint8_t* src = src0 + (run * row_bytes + jr * 128);
-        if (run < nmy && (lane >> 3) < main_blocks - jr)
-          __builtin_amdgcn_global_load_lds(static_cast<const void*>(src + lane_off), dst, 16, 0, 0);
-      } else {
-        const int i = base + lane;
-        int off;
-        if (i < DMA_CHUNKS && side_chunk(i, nmy, row_bytes, &off))
-          __builtin_amdgcn_global_load_lds(static_cast<const void*>(src0 + off), dst, 16, 0, 0);
+        const bool ok = run < nmy && (lane >> 3) < main_blocks - jr;
+        const uint8_t* src = ok ? src0 + (run * row_bytes + jr * 128) + lane_off : src0;
+        __builtin_amdgcn_global_load_lds(static_cast<const void*>(src), (lds_void_t*)(stage() + J * 128), 16, 0, 0);
+      }
+    } else if constexpr (N_SIDE > 0) {
+      // islow: wave SIDE_W0 + m copies side chunks [64 m, 64 m + 64); AAN:
+      // wave SIDE_W0 copies them all
+      constexpr int PER_WAVE = C::ISLOW ? 1 : SIDE_INSTR;
+      const int m0 = C::ISLOW ? wv - SIDE_W0 : 0;
+      if (C::ISLOW ? (wv >= SIDE_W0 && wv < SIDE_W0 + SIDE_INSTR) : wv == SIDE_W0) {
+#pragma unroll
+        for (int i = 0; i < PER_WAVE; ++i) {
+          const int s = 64 * (m0 + i) + lane;
+          int off;
+          const bool ok = side_chunk(8 * N_MAIN + s, nmy, row_bytes, &off);
+          if (s < SIDE_CHUNKS)
+            __builtin_amdgcn_global_load_lds(static_cast<const void*>(ok ? src0 + off : src0),
+                                             (lds_void_t*)(stage() + (8 * N_MAIN + 64 * (m0 + i)) * 16), 16, 0, 0);
+        }
       }
     }
   }
 
-  __device__ void load_qtabs() const {
-    if constexpr (!C::ISLOW) {
-      // the method's 64 multipliers per component
-      for (int i = tid; i < 192; i += NT) {
-        const int c = i >> 6, e = i & 63;
-        const int sel = c == 0 ? im.qsel0 : (c == 1 ? im.qsel1 : im.qsel2);
-        const uint32_t q = im.qt[sel * 64 + e];
-        reinterpret_cast<ldsi*>(qtab(c))[e] = C::IDCT == 1 ? aan_ifast_mult(q, e, *ak) : aan_float_mult(q, e, *ak);
+  // The quant tables into LDS, on the 64 lanes of one wave in rounds: the
+  // global loads of every round first, then the LDS writes.  islow: 96
+  // uint16 pairs (and the same times 16); AAN: the 192 multipliers.
+  static constexpr int QN = C::ISLOW ? 96 : 192;
+  static constexpr int QR = (QN + 63) / 64;
+  struct QLoads {
+    uint32_t v[QR];
+  };
+  __device__ QLoads qtab_loads() const {
+    const int l = tid & 63;
+    // the three table selectors as scalars (a per-lane choice among them
+    // would otherwise become a load of its own)
+    const int s0 = opaque(im.qsel0), s1 = opaque(im.qsel1), s2 = opaque(im.qsel2);
+    QLoads f;
+    uint32_t* v = f.v;
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+      const int i = l + 64 * r;
+      v[r] = 0;
+      if (i < QN) {
+        if constexpr (C::ISLOW) {
+          const int c = i >> 5;
+          const int sel = c == 0 ? s0 : (c == 1 ? s1 : s2);
+          const __attribute__((address_space(1))) uint16_t* q =
+              (const __attribute__((address_space(1))) uint16_t*)im.qt + (sel * 64 + 2 * (i & 31));
+          v[r] = static_cast<uint32_t>(q[0]) | (static_cast<uint32_t>(q[1]) << 16);
+        } else {
+          const int c = i >> 6;
+          const int sel = c == 0 ? s0 : (c == 1 ? s1 : s2);
+          v[r] = im.qt[sel * 64 + (i & 63)];
+        }
       }
-      return;
     }
-    if (tid < 96) {
-      const int c = tid >> 5;
-      const int sel = c == 0 ? im.qsel0 : (c == 1 ? im.qsel1 : im.qsel2);
-      // the lane's offset is formed here each time (kept opaque), so the
-      // compiler does not hold a per-lane pointer across the whole walk
-      int idx = sel * 64 + 2 * (tid & 31);
-      asm volatile("" : "+v"(idx));
-      const __attribute__((address_space(1))) uint16_t* q =
-          (const __attribute__((address_space(1))) uint16_t*)im.qt + idx;
-      const uint32_t pair = static_cast<uint32_t>(q[0]) | (static_cast<uint32_t>(q[1]) << 16);
-      qtab(c)[tid & 31] = pair;
-      // 16 Q per half, modulo 2^16 (the products are only used modulo 2^16)
-      qtab16(c)[tid & 31] = ((pair << 4) & 0xFFFFu) | ((pair >> 16) << 20);
+    return f;
+  }
+  __device__ void qtab_stores(const QLoads& f) const {
+    const int l = tid & 63;
+    const uint32_t* v = f.v;
+#pragma unroll
+    for (int r = 0; r < QR; ++r) {
+      const int i = l + 64 * r;
+      if (i < QN) {
+        if constexpr (C::ISLOW) {
+          const int c = i >> 5;
+          qtab(c)[i & 31] = v[r];
+          // 16 Q per half, modulo 2^16 (the products are only used modulo 2^16)
+          qtab16(c)[i & 31] = ((v[r] << 4) & 0xFFFFu) | ((v[r] >> 16) << 20);
+        } else {
+          const int c = i >> 6, e = i & 63;
+          reinterpret_cast<ldsi*>(qtab(c))[e] =
+              C::IDCT == 1 ? aan_ifast_mult(v[r], e, *ak) : aan_float_mult(v[r], e, *ak);
+        }
+      }
     }
   }
 
   // ---- neighbour blocks above/below the segment (vertical fancy filter) ----
-  // The chroma blocks of the MCU row below the segment are fetched after the
-  // last sub-tile into the then idle staging buffer, by DMA like the
-  // sub-tiles, in the same rotated layout.  Those of the row above are
-  // loaded straight into the registers of the lanes that form their row
-  // (run()'s prologue).
-  __device__ lds8* tb_area() const { return stage(); }
-
-  __device__ void dma_tb_below() const {
-    const int my = r1;
-    if (my >= im.mcus_y) return;
-    constexpr int CHUNKS = N_TB * 8;
-    lds8* area = tb_area();
-    for (int base = (tid & ~63); base < CHUNKS; base += NT) {
-      const int i = base + (tid & 63);
-      if (i < CHUNKS) {
-        const int t = i >> 3;
-        const int c = ((i & 7) - t) & 7;
-        const int pos = t >> 1;
-        const int mx = mx0 - 1 + pos;
-        if (pos < nmx + 2 && mx >= 0 && mx < im.mcus_x)
-          __builtin_amdgcn_global_load_lds(static_cast<const void*>(block_ptr(my, mx, NY + (t & 1)) + 8 * c),
-                                           (lds_void_t*)(area + base * 16), 16, 0, 0);
-      }
-    }
-  }
+  // The chroma blocks of the MCU rows just above and below the segment are
+  // loaded straight into the registers of the lanes that form their one
+  // row, by the last wave at the segment's start (run()'s prologue).
 
   // One lane per neighbour block forms the one sample row the filter needs
   // (row 7 of the block above, row 0 of the block below): dequantisation,
@@ -304,46 +327,28 @@ struct SegmentDecoder {
   // lane also writes the replicated sample the filter reads beyond the edge.
   // The neighbour block of lane t (< N_TB) above or below the segment, or
   // false where that MCU lies outside the image.
-  __device__ bool tb_block(bool below, int* pos, int* mx) const {
+  __device__ bool tb_block(bool below, int t, int* pos, int* mx) const {
     const int my = below ? r1 : r0 - 1;
-    *pos = tid >> 1;
+    *pos = t >> 1;
     *mx = mx0 - 1 + *pos;
-    return my >= 0 && my < im.mcus_y && tid < N_TB && *pos < nmx + 2 && *mx >= 0 && *mx < im.mcus_x;
+    return my >= 0 && my < im.mcus_y && t < N_TB && *pos < nmx + 2 && *mx >= 0 && *mx < im.mcus_x;
   }
 
-  // The staged block below the segment, rows in natural order.
-  __device__ void tb_rows_lds(v4i rows[8]) const {
-    const lds8* blk = tb_area() + tid * 128;
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      rows[c] = *reinterpret_cast<const __attribute__((address_space(3))) v4i*>(blk + (((c + tid) & 7) << 4));
-  }
-
-  // The block above the segment straight from global memory (issued early,
-  // used after the quant tables are in LDS).
-  __device__ void tb_rows_global(int mx, v4i rows[8]) const {
+  // Neighbour block t straight from global memory.
+  __device__ void tb_rows_global(bool below, int t, int mx, v4i rows[8]) const {
     const __attribute__((address_space(1))) v4i* src =
-        (const __attribute__((address_space(1))) v4i*)(block_ptr(r0 - 1, mx, NY + (tid & 1)));
+        (const __attribute__((address_space(1))) v4i*)(block_ptr(below ? r1 : r0 - 1, mx, NY + (t & 1)));
 #pragma unroll
     for (int c = 0; c < 8; ++c) rows[c] = src[c];
   }
 
-  // The row below the segment, from the staged blocks.
-  __device__ void tb_edge_below() const {
-    int pos, mx;
-    if (!tb_block(true, &pos, &mx)) return;
-    v4i rows[8];
-    tb_rows_lds(rows);
-    tb_row(true, pos, mx, rows);
-  }
-
-  __device__ void tb_row(bool below, int pos, int mx, const v4i rows[8]) const {
-    const int t = tid;
+  // The row of neighbour block t (component 1 + (t & 1) at MCU column mx).
+  __device__ void tb_row(bool below, int t, int pos, int mx, const v4i rows[8]) const {
     if constexpr (!C::ISLOW) {
       // the AAN methods: the one row on this lane
       uint32_t lo, hi;
       aan_block_row<C::IDCT>(rows, reinterpret_cast<const ldsi*>(qtab(1 + (t & 1))), *ak, !below, &lo, &hi);
-      lds32* row = cring(t & 1) + (below ? below_row() : CROWS - 1) * CWD;
+      lds32* row = cring(t & 1) + (below ? BELOW_ROW : CROWS - 1) * CWD;
       row[2 * pos] = lo;
       row[2 * pos + 1] = hi;
       lds8* row8 = reinterpret_cast<lds8*>(row);
@@ -386,7 +391,7 @@ struct SegmentDecoder {
     idct8_raw(x[0], x[1], x[2], x[3], x[4], x[5], x[6], x[7], kPass2Bias, y);
 #pragma unroll
     for (int i = 0; i < 8; ++i) y[i] >>= kPass2Shift;
-    lds32* row = cring(t & 1) + (below ? below_row() : CROWS - 1) * CWD;
+    lds32* row = cring(t & 1) + (below ? BELOW_ROW : CROWS - 1) * CWD;
     row[2 * pos] = pack4(y[0], y[1], y[2], y[3]);
     row[2 * pos + 1] = pack4(y[4], y[5], y[6], y[7]);
     lds8* row8 = reinterpret_cast<lds8*>(row);
@@ -652,26 +657,37 @@ struct SegmentDecoder {
     }
   }
 
-  // 4:2:0 fancy, step k: every chroma row of sub-tile k-1 but its last two,
-  // and the last two rows of sub-tile k-2 (the last of which needs the first
-  // row of k-1), as pairs of rows: one pair of rows and 4 samples per lane.
+  // Vertical fancy filter, step k (1..K): every chroma row of sub-tile k-1
+  // but its last two, and the last two rows of sub-tile k-2 (the last of
+  // which needs the first row of k-1), as pairs of rows: one pair of rows
+  // and 4 samples per lane; at step K also the last two rows of sub-tile
+  // K-1, whose last row reads the row below the segment.
   __device__ void phase2_pairs(int k) const {
     // work items: (row pair rp, unit g), rp 0 the tail pair of k - 2; a
     // workgroup of fewer lanes than items takes them in turns
     constexpr int ITEMS = (C::CR / 2) * C::UX;
     static_assert(ITEMS % NT == 0, "the row pairs of a sub-tile fill the workgroup a whole number of times");
-    const bool has_a = k >= 1 && k <= K;
-    const bool has_b = k >= 2 && k <= K + 1;
-    if (!has_a && !has_b) return;
-    const SubInfo sa = uniform(sub_info(has_a ? k - 1 : 0)), sb = uniform(sub_info(has_b ? k - 2 : 0));
+    const bool has_b = k >= 2;
+    const SubInfo sa = uniform(sub_info(k - 1)), sb = uniform(sub_info(has_b ? k - 2 : 0));
     // every unit of the strip is whole and its rows 4-byte aligned: the
     // plain store path alone
     const bool plain = im.aligned_out && (gcx0 + 8 * nmx) * HF <= im.width;
 #pragma unroll
-    for (int it = tid; it < ITEMS; it += NT) {
-      const int g = it % C::UX, rp = it / C::UX;
+    for (int it0 = 0; it0 < ITEMS; it0 += NT) {
+      const int it = it0 + tid;
+      int g, rp;
+      if constexpr (C::UX % 64 == 0) {
+        // a row pair per wave: the pair and everything derived from it
+        // are scalars
+        const int wb = __builtin_amdgcn_readfirstlane(it & ~63);
+        rp = wb / C::UX;
+        g = wb - rp * C::UX + (it & 63);
+      } else {
+        g = it % C::UX;
+        rp = it / C::UX;
+      }
       const bool tail = rp == 0;
-      if (g >= 2 * nmx || (tail ? !has_b : !has_a)) continue;
+      if (g >= 2 * nmx || (tail && !has_b)) continue;
       SubInfo si;
       si.rgb = tail ? sb.rgb : sa.rgb;
       si.gcy0 = tail ? sb.gcy0 : sa.gcy0;
@@ -685,6 +701,33 @@ struct SegmentDecoder {
       } else {
         if (plain) unit_pair_v<true>(si, cr, g);
         else unit_pair_v<false>(si, cr, g);
+      }
+    }
+    if (k != K) return;
+    // the last sub-tile's last pair
+    if constexpr (HF == 2 && C::UX % 64 == 0) {
+      // its four output rows spread over the waves (one row of a unit per
+      // lane)
+#pragma unroll
+      for (int it0 = 0; it0 < 4 * C::UX; it0 += NT) {
+        const int it = it0 + tid;
+        if (it >= 4 * C::UX) break;
+        const int wb = __builtin_amdgcn_readfirstlane(it & ~63);  // a row per wave: a scalar
+        const int j = wb / C::UX, g = wb - j * C::UX + (it & 63);
+        if (g >= 2 * nmx) continue;
+        if (plain) unit_row<true>(sa, sa.rows - 2, g, j);
+        else unit_row<false>(sa, sa.rows - 2, g, j);
+      }
+    } else {
+      for (int g = tid; g < C::UX; g += NT) {
+        if (g >= 2 * nmx) continue;
+        if constexpr (HF == 2) {
+          if (plain) unit_pair<true>(sa, sa.rows - 2, g);
+          else unit_pair<false>(sa, sa.rows - 2, g);
+        } else {
+          if (plain) unit_pair_v<true>(sa, sa.rows - 2, g);
+          else unit_pair_v<false>(sa, sa.rows - 2, g);
+        }
       }
     }
   }
@@ -741,7 +784,7 @@ struct SegmentDecoder {
     // neighbours, repeated at the true top and bottom chroma edges
     const int ru = gy == 0 ? rc : ring_prev(rc);
     const bool last0 = gy == ch - 1;  // row cr is the last chroma row (row cr + 1 lies below the image)
-    const int rd = gy + 1 >= ch - 1 ? rc + 1 : ring_next(rc + 1);
+    const int rd = row_after_pair(gy, rc);
     u16x2 pu[2][3], p0[2][3], p1[2][3], pd[2][3];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -757,7 +800,7 @@ struct SegmentDecoder {
       const int ly = si.yb + 2 * cr;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const lds32* ysrc = luma() + (mul24(ywrap(ly + j), YWD) + 2 * g);
+        const lds32* ysrc = luma() + (mul24(ly + j, YWD) + 2 * g);
         yl[j][0] = ysrc[0];
         yl[j][1] = ysrc[1];
       }
@@ -810,6 +853,67 @@ struct SegmentDecoder {
     }
   }
 
+  // Output row j (0..3) of unit_pair's four, alone: the chroma row nearest
+  // it and the other row the vertical 3:1 filter reads (j uniform across
+  // the wave, so the ring rows are scalars).
+  template <bool PLAIN>
+  __device__ void unit_row(const SubInfo& si, const int cr, const int g, const int j) const {
+    const int W = im.width, H = im.height;
+    const int px0 = (gcx0 + 4 * g) * 2;
+    const int gy = si.gcy0 + cr;
+    const int py = 2 * gy + j;
+    if (px0 >= W || py >= H) return;
+    const int ch = im.chroma_h;
+    const int rc = si.cb + cr;
+    const int r1 = gy == ch - 1 ? rc : rc + 1;  // row cr + 1, or row cr at the true bottom edge
+    int rn, rf;
+    if (j == 0) {
+      rn = rc;
+      rf = gy == 0 ? rc : ring_prev(rc);
+    } else if (j == 1) {
+      rn = rc;
+      rf = r1;
+    } else if (j == 2) {
+      rn = r1;
+      rf = rc;
+    } else {
+      rn = r1;
+      rf = row_after_pair(gy, rc);
+    }
+    int xs[2][8];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const lds32* ring = cring(c) + (g + 2);
+      u16x2 pn[3], pf[3], sv[3];
+      chroma_pairs(ring + mul24(rn, CWD), pn);
+      chroma_pairs(ring + mul24(rf, CWD), pf);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) sv[i] = mad3(pn[i], pf[i]);
+      h2v2_row_x(sv, xs[c]);
+    }
+    const lds32* ysrc = luma() + (mul24(si.yb + 2 * cr + j, YWD) + 2 * g);
+    const uint32_t yl[2] = {ysrc[0], ysrc[1]};
+    uint32_t w[6];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      RGBWide px[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) px[i] = ycc_wide(y16_of(yl[kk], i), xs[0][4 * kk + i], xs[1][4 * kk + i]);
+      pack_rgb4(px, w + 3 * kk);
+    }
+    const int nv = min(8, W - px0);
+    gbl8* row = si.rgb + (mul24(2 * cr + j, static_cast<int>(im.pitch)) + 24 * g);
+    if (PLAIN || (nv == 8 && im.aligned_out)) {
+      gbl32* wd = reinterpret_cast<gbl32*>(row);
+#pragma unroll
+      for (int kk = 0; kk < 6; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
+    } else if (nv == 8) {
+      store_shifted(row, w);
+    } else {
+      store_ragged(row, w, 3 * nv);
+    }
+  }
+
   // Chroma rows cr and cr + 1 of a sub-tile's strip, samples 4g..4g+3
   // (h1v2 fancy: the 3:1 filter turned vertical, no horizontal filter):
   // four output rows of 4 pixels.
@@ -824,7 +928,7 @@ struct SegmentDecoder {
     const int rc = si.cb + cr;  // ring row of row cr; rc + 1 is row cr + 1
     const int ru = gy == 0 ? rc : ring_prev(rc);
     const bool last0 = gy == ch - 1;
-    const int rd = gy + 1 >= ch - 1 ? rc + 1 : ring_next(rc + 1);
+    const int rd = row_after_pair(gy, rc);
     uint32_t cu[2], c0[2], c1[2], cd[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -842,7 +946,7 @@ struct SegmentDecoder {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (py0 + j >= H) break;
-      const uint32_t yd = luma()[mul24(ywrap(ly + j), YWD) + g];
+      const uint32_t yd = luma()[mul24(ly + j, YWD) + g];
       int x[2][4];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
@@ -1035,64 +1139,82 @@ struct SegmentDecoder {
 
     __syncthreads();  // the previous segment's readers are done with every buffer
     __builtin_amdgcn_s_setprio(3);
-    load_qtabs();
-    if constexpr (HALO_Y) {
-      // The first waves fetch the blocks above the segment straight into
-      // registers and form their one row (into the ring row above the
-      // segment, which phase 2 first reads one step later) while the other
-      // waves' DMA of sub-tile 0 is in flight.
-      constexpr int TBL = round64c(N_TB);
-      static_assert(TBL < NT, "waves left for the DMA");
-      int pos, mx;
-      const bool tb = tb_block(false, &pos, &mx);
-      v4i rows[8];
-      if (tb) tb_rows_global(mx, rows);
-      if (tid >= TBL) dma(0, TBL);
-      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");  // quant tables visible
-      if (tb) tb_row(false, pos, mx, rows);
-    } else {
+    // Every wave but the last starts its own copies of sub-tile 0 at once.
+    // The last wave loads the quant tables first (so its LDS writes wait
+    // for those loads alone), then makes its own copies, and after the
+    // barrier forms the rows just above and below the segment (vertical
+    // fancy filter) while the other waves wait for their blocks.  The first
+    // step has no barrier: each wave starts its transform once its own
+    // blocks are in.
+    constexpr int AUXW = NT / 64 - 1;
+    constexpr int TBP = (N_TB + 63) / 64;  // passes over the neighbour blocks of one side
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (wv != AUXW) {
       dma(0);
-      __syncthreads();  // quant tables visible
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");  // quant tables visible
+    } else {
+      const QLoads ql = qtab_loads();
+      // the blocks above the segment, in flight with the table loads
+      int pos[TBP > 0 ? TBP : 1], mx[TBP > 0 ? TBP : 1];
+      bool tb[TBP > 0 ? TBP : 1];
+      v4i rows[TBP > 0 ? TBP : 1][8];
+      if constexpr (HALO_Y) {
+#pragma unroll
+        for (int p = 0; p < TBP; ++p) {
+          tb[p] = tb_block(false, 64 * p + (tid & 63), &pos[p], &mx[p]);
+          if (tb[p]) tb_rows_global(false, 64 * p + (tid & 63), mx[p], rows[p]);
+        }
+      }
+      qtab_stores(ql);
+      dma(0);
+      asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");  // quant tables visible
+      if constexpr (HALO_Y) {
+        // the rows above and below; phase 2 first reads them a step later
+#pragma unroll
+        for (int p = 0; p < TBP; ++p)
+          if (tb[p]) tb_row(false, 64 * p + (tid & 63), pos[p], mx[p], rows[p]);
+#pragma unroll
+        for (int p = 0; p < TBP; ++p) {
+          const int t = 64 * p + (tid & 63);
+          if (tb_block(true, t, &pos[p], &mx[p])) {
+            tb_rows_global(true, t, mx[p], rows[p]);
+            tb_row(true, t, pos[p], mx[p], rows[p]);
+          }
+        }
+      }
     }
 
-    for (int k = 0; k < K + LAG; ++k) {
-      Held h{};  // per step, fully defined so it stays in registers
-      // Wait for the DMA of the previous step (the counter also covers the
-      // RGB stores, so the steps with no DMA in flight skip it).
-      if (k < K || (HALO_Y && k == K)) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();  // staging of k landed; last step's LDS writes visible
+    for (int k = 0; k <= K; ++k) {
+      Held h;  // per step; lanes that stage nothing never read it
+      // Wait for this wave's copies of the sub-tile (the counter also
+      // covers the RGB stores, so the last step skips it).
+      if (k < K) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      // Phase 1 of the last step (and the rows above and below) visible.
+      // Each wave copies and reads its own staging blocks, and phase 2 of
+      // k and phase 1 of k use different luma and chroma slots, so a step
+      // needs no other barrier.
+      if (k > 0) __syncthreads();
       // the step's priority falls as the segment advances, so the
       // workgroup that is behind on a CU catches up
       if (k == 0) __builtin_amdgcn_s_setprio(3);
       else if (k == 1) __builtin_amdgcn_s_setprio(2);
       else if (k == 2) __builtin_amdgcn_s_setprio(1);
       else __builtin_amdgcn_s_setprio(0);
-      if constexpr (HALO_Y) {
-        // the row below (its blocks were staged after the last sub-tile):
-        // phase 2 of the next step reads it
-        if (k == K) tb_edge_below();
-        if (k < K) read_stage(k, h);
-        // Phase 2 reads the luma rows that phase 1 of k overwrites in the
-        // ring, so it goes first, in the interval that also frees the
-        // staging buffer; its stores drain while the IDCT runs.
-        phase2_pairs(k);
-        __syncthreads();  // staging free; phase 2's luma rows read
-        if (k + 1 < K) dma(k + 1);
-        if (k + 1 == K) dma_tb_below();  // staging is idle from here on
-      } else {
-        if (k < K) read_stage(k, h);
-        __syncthreads();  // staging free for the next sub-tile
-        if (k + 1 < K) dma(k + 1);
-        // Phase 2 of the previous sub-tile and phase 1 of this one use
-        // disjoint luma buffers and chroma ring rows, so they share one
-        // barrier interval; phase 2 goes first so its stores drain while
-        // the IDCT runs, and lanes without a block of their own take most
-        // of it.
-        if (k >= LAG) phase2(k - LAG);
+      if (k < K) {
+        read_stage(k, h);
+        if (k + 1 < K) {
+          asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // this wave's staging reads done
+          dma(k + 1);
+        }
+      }
+      // Phase 2 first, so its stores drain while the transform runs.
+      if (k > 0) {
+        if constexpr (HALO_Y) phase2_pairs(k);
+        else phase2(k - 1);
       }
       // Phase 1 also finishes the neighbour-column blocks and the edge
       // copies in place, so its LDS writes only need to be visible at the
-      // next step's first barrier.
+      // next step's barrier.
       if (k < K) phase1(k, h);
     }
   }
