@@ -1142,10 +1142,10 @@ struct SegmentDecoder {
     // Every wave but the last starts its own copies of sub-tile 0 at once.
     // The last wave loads the quant tables first (so its LDS writes wait
     // for those loads alone), then makes its own copies, and after the
-    // barrier forms the rows just above and below the segment (vertical
-    // fancy filter) while the other waves wait for their blocks.  The first
-    // step has no barrier: each wave starts its transform once its own
-    // blocks are in.
+    // barrier loads and forms the rows just above and below the segment
+    // (vertical fancy filter) while the other waves wait for their blocks.
+    // The first step has no barrier: each wave starts its transform once
+    // its own blocks are in.
     constexpr int AUXW = NT / 64 - 1;
     constexpr int TBP = (N_TB + 63) / 64;  // passes over the neighbour blocks of one side
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1153,34 +1153,29 @@ struct SegmentDecoder {
       dma(0);
       asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");  // quant tables visible
     } else {
-      const QLoads ql = qtab_loads();
-      // the blocks above the segment, in flight with the table loads
-      int pos[TBP > 0 ? TBP : 1], mx[TBP > 0 ? TBP : 1];
-      bool tb[TBP > 0 ? TBP : 1];
-      v4i rows[TBP > 0 ? TBP : 1][8];
-      if constexpr (HALO_Y) {
-#pragma unroll
-        for (int p = 0; p < TBP; ++p) {
-          tb[p] = tb_block(false, 64 * p + (tid & 63), &pos[p], &mx[p]);
-          if (tb[p]) tb_rows_global(false, 64 * p + (tid & 63), mx[p], rows[p]);
-        }
-      }
-      qtab_stores(ql);
+      qtab_stores(qtab_loads());
       dma(0);
       asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");  // quant tables visible
       if constexpr (HALO_Y) {
-        // the rows above and below; phase 2 first reads them a step later
+        // the rows just above and below the segment (phase 2 first reads
+        // them a step later): their blocks straight into registers, loaded
+        // after the other waves' first copies
+        int pos[2][TBP], mx[2][TBP];
+        bool tb[2][TBP];
+        v4i rows[2][TBP][8];
 #pragma unroll
-        for (int p = 0; p < TBP; ++p)
-          if (tb[p]) tb_row(false, 64 * p + (tid & 63), pos[p], mx[p], rows[p]);
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int p = 0; p < TBP; ++p) {
-          const int t = 64 * p + (tid & 63);
-          if (tb_block(true, t, &pos[p], &mx[p])) {
-            tb_rows_global(true, t, mx[p], rows[p]);
-            tb_row(true, t, pos[p], mx[p], rows[p]);
+          for (int p = 0; p < TBP; ++p) {
+            const int t = 64 * p + (tid & 63);
+            tb[b][p] = tb_block(b == 1, t, &pos[b][p], &mx[b][p]);
+            if (tb[b][p]) tb_rows_global(b == 1, t, mx[b][p], rows[b][p]);
           }
-        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int p = 0; p < TBP; ++p)
+            if (tb[b][p]) tb_row(b == 1, 64 * p + (tid & 63), pos[b][p], mx[b][p], rows[b][p]);
       }
     }
 
@@ -1194,12 +1189,17 @@ struct SegmentDecoder {
       // k and phase 1 of k use different luma and chroma slots, so a step
       // needs no other barrier.
       if (k > 0) __syncthreads();
-      // the step's priority falls as the segment advances, so the
-      // workgroup that is behind on a CU catches up
-      if (k == 0) __builtin_amdgcn_s_setprio(3);
-      else if (k == 1) __builtin_amdgcn_s_setprio(2);
-      else if (k == 2) __builtin_amdgcn_s_setprio(1);
-      else __builtin_amdgcn_s_setprio(0);
+      // Wave priority: the steps left, plus one in the last step for the
+      // workgroups of the grid's second half (the later of two on a CU,
+      // whose waves lose every tie on age), so the two end together.
+      {
+        const bool later = 2 * static_cast<int>(blockIdx.x) >= static_cast<int>(gridDim.x);
+        const int pr = min(3, K - k + (later && k == K ? 1 : 0));
+        if (pr >= 3) __builtin_amdgcn_s_setprio(3);
+        else if (pr == 2) __builtin_amdgcn_s_setprio(2);
+        else if (pr == 1) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+      }
       if (k < K) {
         read_stage(k, h);
         if (k + 1 < K) {
