@@ -1,7 +1,9 @@
 """Builds the HIP library (libmjd.so) in-tree for gfx950 with hipcc."""
 from __future__ import annotations
 
+import json
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -58,6 +60,25 @@ def _run(cmd):
     return r
 
 
+# per-kernel register, scratch and spill figures of the last build, from the
+# compiler's resource-usage remarks (tests check that no kernel spills)
+RESOURCES = os.path.join(BUILD, "kernel_resources.json")
+_REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|ScratchSize \[bytes/lane\]|Occupancy \[waves/SIMD\]|"
+                     r"VGPRs Spill|SGPRs Spill|LDS Size \[bytes/block\]):\s+(\S+)")
+
+
+def parse_resource_remarks(text: str) -> dict:
+    """{kernel symbol: {figure: value}} from -Rpass-analysis=kernel-resource-usage output."""
+    out, cur = {}, None
+    for m in _REMARK.finditer(text):
+        key, val = m.group(1), m.group(2)
+        if key == "Function Name":
+            cur = out.setdefault(val, {})
+        elif cur is not None:
+            cur[key.split(" [")[0]] = int(val) if val.lstrip("-").isdigit() else val
+    return out
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(LIBDIR, exist_ok=True)
     os.makedirs(BUILD, exist_ok=True)
@@ -67,15 +88,20 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmds.append([cc, *HIPCC_FLAGS, *HIPCC_FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([cc, *HIPCC_FLAGS, *HIPCC_FILE_FLAGS.get(src, []), "-Rpass-analysis=kernel-resource-usage",
+                     "-c", os.path.join(CSRC, src), "-o", obj])
     for src in HOST_SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".host.o")
         objs.append(obj)
         cmds.append([cxx(), *CXX_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+    resources = {}
     with ThreadPoolExecutor(max_workers=min(4, len(cmds))) as ex:
         for r in ex.map(_run, cmds):
+            resources.update(parse_resource_remarks(r.stderr))
             if verbose and (r.stdout or r.stderr):
                 print(r.stdout, r.stderr, file=sys.stderr)
+    with open(RESOURCES, "w") as f:
+        json.dump(resources, f, indent=1, sort_keys=True)
     tmp = LIB + ".tmp"
     _run([cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs])
     os.replace(tmp, LIB)

@@ -660,41 +660,47 @@ struct SegmentDecoder {
   // Vertical fancy filter, step k (1..K): every chroma row of sub-tile k-1
   // but its last two, and the last two rows of sub-tile k-2 (the last of
   // which needs the first row of k-1), as pairs of rows: one pair of rows
-  // and 4 samples per lane; at step K also the last two rows of sub-tile
-  // K-1, whose last row reads the row below the segment.
+  // and 4 samples per lane.  At step K also the last pair of sub-tile K-1,
+  // whose last row reads the row below the segment: in the same item walk
+  // for strips narrower than a wave, else after phase 1 (last_pair_rows).
+  static constexpr bool LAST_IN_WALK = C::UX % 64 != 0;
+  static_assert(!HALO_Y || LAST_IN_WALK || HF == 2, "spread last pair rows: the h2v2 filter");
   __device__ void phase2_pairs(int k) const {
-    // work items: (row pair rp, unit g), rp 0 the tail pair of k - 2; a
-    // workgroup of fewer lanes than items takes them in turns
+    // work items: (pair v, unit g); v 0 the last pair of k - 2, v = CR/2
+    // (step K only) the last pair of k - 1; a workgroup of fewer lanes than
+    // items takes them in turns
     constexpr int ITEMS = (C::CR / 2) * C::UX;
     static_assert(ITEMS % NT == 0, "the row pairs of a sub-tile fill the workgroup a whole number of times");
     const bool has_b = k >= 2;
+    const int n_items = ITEMS + (LAST_IN_WALK && k == K ? C::UX : 0);
     const SubInfo sa = uniform(sub_info(k - 1)), sb = uniform(sub_info(has_b ? k - 2 : 0));
     // every unit of the strip is whole and its rows 4-byte aligned: the
     // plain store path alone
     const bool plain = im.aligned_out && (gcx0 + 8 * nmx) * HF <= im.width;
-#pragma unroll
-    for (int it0 = 0; it0 < ITEMS; it0 += NT) {
+    for (int it0 = 0; it0 < n_items; it0 += NT) {
       const int it = it0 + tid;
-      int g, rp;
+      int g, v;
       if constexpr (C::UX % 64 == 0) {
         // a row pair per wave: the pair and everything derived from it
         // are scalars
         const int wb = __builtin_amdgcn_readfirstlane(it & ~63);
-        rp = wb / C::UX;
-        g = wb - rp * C::UX + (it & 63);
+        v = wb / C::UX;
+        g = wb - v * C::UX + (it & 63);
       } else {
         g = it % C::UX;
-        rp = it / C::UX;
+        v = it / C::UX;
       }
-      const bool tail = rp == 0;
-      if (g >= 2 * nmx || (tail && !has_b)) continue;
+      const bool tail = v == 0;
+      if (it >= n_items || g >= 2 * nmx || (tail && !has_b)) continue;
       SubInfo si;
       si.rgb = tail ? sb.rgb : sa.rgb;
       si.gcy0 = tail ? sb.gcy0 : sa.gcy0;
       si.yb = tail ? sb.yb : sa.yb;
       si.cb = tail ? sb.cb : sa.cb;
-      const int cr = tail ? sb.rows - 2 : 2 * (rp - 1);
-      if (!tail && cr >= sa.rows - 2) continue;
+      // v = CR/2 gives sa.rows - 2 (sa.rows is CR there: only the last
+      // sub-tile can be short, and its last pair is v = CR/2)
+      const int cr = tail ? sb.rows - 2 : (v == C::CR / 2 ? sa.rows - 2 : 2 * (v - 1));
+      if (!tail && v < C::CR / 2 && cr >= sa.rows - 2) continue;
       if constexpr (HF == 2) {
         if (plain) unit_pair<true>(si, cr, g);
         else unit_pair<false>(si, cr, g);
@@ -703,32 +709,24 @@ struct SegmentDecoder {
         else unit_pair_v<false>(si, cr, g);
       }
     }
-    if (k != K) return;
-    // the last sub-tile's last pair
-    if constexpr (HF == 2 && C::UX % 64 == 0) {
-      // its four output rows spread over the waves (one row of a unit per
-      // lane)
+  }
+
+  // Vertical fancy filter, step K, strips of a wave or more: the last pair
+  // of sub-tile K-1 (its last row reads the row below the segment), its
+  // four output rows spread over the waves, one row of a unit per lane,
+  // after phase 1.
+  __device__ void last_pair_rows() const {
+    const SubInfo sa = uniform(sub_info(K - 1));
+    const bool plain = im.aligned_out && (gcx0 + 8 * nmx) * HF <= im.width;
 #pragma unroll
-      for (int it0 = 0; it0 < 4 * C::UX; it0 += NT) {
-        const int it = it0 + tid;
-        if (it >= 4 * C::UX) break;
-        const int wb = __builtin_amdgcn_readfirstlane(it & ~63);  // a row per wave: a scalar
-        const int j = wb / C::UX, g = wb - j * C::UX + (it & 63);
-        if (g >= 2 * nmx) continue;
-        if (plain) unit_row<true>(sa, sa.rows - 2, g, j);
-        else unit_row<false>(sa, sa.rows - 2, g, j);
-      }
-    } else {
-      for (int g = tid; g < C::UX; g += NT) {
-        if (g >= 2 * nmx) continue;
-        if constexpr (HF == 2) {
-          if (plain) unit_pair<true>(sa, sa.rows - 2, g);
-          else unit_pair<false>(sa, sa.rows - 2, g);
-        } else {
-          if (plain) unit_pair_v<true>(sa, sa.rows - 2, g);
-          else unit_pair_v<false>(sa, sa.rows - 2, g);
-        }
-      }
+    for (int it0 = 0; it0 < 4 * C::UX; it0 += NT) {
+      const int it = it0 + tid;
+      if (it >= 4 * C::UX) break;
+      const int wb = __builtin_amdgcn_readfirstlane(it & ~63);  // a row per wave: a scalar
+      const int j = wb / C::UX, g = wb - j * C::UX + (it & 63);
+      if (g >= 2 * nmx) continue;
+      if (plain) unit_row<true>(sa, sa.rows - 2, g, j);
+      else unit_row<false>(sa, sa.rows - 2, g, j);
     }
   }
 
@@ -1180,7 +1178,13 @@ struct SegmentDecoder {
     }
 
     for (int k = 0; k <= K; ++k) {
-      Held h;  // per step; lanes that stage nothing never read it
+      // The staged registers get a fresh, opaque definition every step (no
+      // instruction): lanes that stage nothing never read them, and the
+      // compiler need not keep the last step's values alive across the
+      // loop (which costs about 32 registers, and spills with 3 waves per
+      // SIMD).
+      Held h;
+      asm("" : "=v"(h.r0), "=v"(h.r1), "=v"(h.r2), "=v"(h.r3), "=v"(h.r4), "=v"(h.r5), "=v"(h.r6), "=v"(h.r7));
       // Wait for this wave's copies of the sub-tile (the counter also
       // covers the RGB stores, so the last step skips it).
       if (k < K) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -1216,6 +1220,8 @@ struct SegmentDecoder {
       // copies in place, so its LDS writes only need to be visible at the
       // next step's barrier.
       if (k < K) phase1(k, h);
+      if constexpr (HALO_Y && !LAST_IN_WALK && HF == 2)
+        if (k == K) last_pair_rows();
     }
   }
 };
