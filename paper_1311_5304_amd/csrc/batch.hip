@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBatchThreads, 2) void decode_batch(const ImageView
     r.r1 = bi.r1;
     switch (bi.cls) {
       case kC420F: {
-        SegmentDecoder<B420F> d(lds, im, tid);
+        SegmentDecoder<B420F, true> d(lds, im, tid);
         d.run(r);
         break;
       }

@@ -124,7 +124,12 @@ struct SegCfg {
   static_assert(YROWS % 8 == 0, "whole block rows");
 };
 
-template <class C>
+// WALK_LAST: the last row pair of a segment is upsampled in the same item
+// walk as the others (one unit per lane) even where its rows could be spread
+// over the waves; the batched kernel, which holds every sampling class in
+// one function, takes it so (a separate pass there put the kernel over its
+// register budget).
+template <class C, bool WALK_LAST = false>
 struct SegmentDecoder {
   static constexpr int HF = C::HF, VF = C::VF, SX = C::SX, SY = C::SY, NT = C::NT;
   static constexpr int NY = C::NY, BPM = C::BPM, SM = C::SM, N_MAIN = C::N_MAIN;
@@ -661,10 +666,11 @@ struct SegmentDecoder {
   // but its last two, and the last two rows of sub-tile k-2 (the last of
   // which needs the first row of k-1), as pairs of rows: one pair of rows
   // and 4 samples per lane.  At step K also the last pair of sub-tile K-1,
-  // whose last row reads the row below the segment: in the same item walk
-  // for strips narrower than a wave, else after phase 1 (last_pair_rows).
-  static constexpr bool LAST_IN_WALK = C::UX % 64 != 0;
-  static_assert(!HALO_Y || LAST_IN_WALK || HF == 2, "spread last pair rows: the h2v2 filter");
+  // whose last row reads the row below the segment: after phase 1, its
+  // rows spread over the waves (last_pair_rows, the h2v2 filter), or in the
+  // same item walk (h1v2).
+  static constexpr bool LAST_IN_WALK = HF != 2 || WALK_LAST;
+  static_assert(!HALO_Y || LAST_IN_WALK || C::UX % 64 == 0 || NT >= 256, "a wave for each output row");
   __device__ void phase2_pairs(int k) const {
     // work items: (pair v, unit g); v 0 the last pair of k - 2, v = CR/2
     // (step K only) the last pair of k - 1; a workgroup of fewer lanes than
@@ -711,22 +717,32 @@ struct SegmentDecoder {
     }
   }
 
-  // Vertical fancy filter, step K, strips of a wave or more: the last pair
-  // of sub-tile K-1 (its last row reads the row below the segment), its
-  // four output rows spread over the waves, one row of a unit per lane,
-  // after phase 1.
+  // Vertical fancy filter (h2v2), step K: the last pair of sub-tile K-1
+  // (its last row reads the row below the segment), its four output rows
+  // spread over the waves, one row of a unit per lane, after phase 1: a
+  // strip of a wave or more takes its units in turns, a narrower strip
+  // gives wave j output row j.
   __device__ void last_pair_rows() const {
     const SubInfo sa = uniform(sub_info(K - 1));
     const bool plain = im.aligned_out && (gcx0 + 8 * nmx) * HF <= im.width;
+    if constexpr (C::UX % 64 == 0) {
 #pragma unroll
-    for (int it0 = 0; it0 < 4 * C::UX; it0 += NT) {
-      const int it = it0 + tid;
-      if (it >= 4 * C::UX) break;
-      const int wb = __builtin_amdgcn_readfirstlane(it & ~63);  // a row per wave: a scalar
-      const int j = wb / C::UX, g = wb - j * C::UX + (it & 63);
-      if (g >= 2 * nmx) continue;
-      if (plain) unit_row<true>(sa, sa.rows - 2, g, j);
-      else unit_row<false>(sa, sa.rows - 2, g, j);
+      for (int it0 = 0; it0 < 4 * C::UX; it0 += NT) {
+        const int it = it0 + tid;
+        if (it >= 4 * C::UX) break;
+        const int wb = __builtin_amdgcn_readfirstlane(it & ~63);  // a row per wave: a scalar
+        const int j = wb / C::UX, g = wb - j * C::UX + (it & 63);
+        if (g >= 2 * nmx) continue;
+        if (plain) unit_row<true>(sa, sa.rows - 2, g, j);
+        else unit_row<false>(sa, sa.rows - 2, g, j);
+      }
+    } else {
+      const int j = __builtin_amdgcn_readfirstlane(tid >> 6);  // a scalar
+      const int g = tid & 63;
+      if (j < 4 && g < C::UX && g < 2 * nmx) {
+        if (plain) unit_row<true>(sa, sa.rows - 2, g, j);
+        else unit_row<false>(sa, sa.rows - 2, g, j);
+      }
     }
   }
 
@@ -1220,7 +1236,7 @@ struct SegmentDecoder {
       // copies in place, so its LDS writes only need to be visible at the
       // next step's barrier.
       if (k < K) phase1(k, h);
-      if constexpr (HALO_Y && !LAST_IN_WALK && HF == 2)
+      if constexpr (HALO_Y && !LAST_IN_WALK)
         if (k == K) last_pair_rows();
     }
   }
