@@ -94,7 +94,13 @@ struct SegCfg {
   // beside phase 1 of k), or three with the vertical fancy filter (the last
   // row pair of k - 2 is also upsampled at step k).
   static constexpr int NYB = HALO_Y ? 3 : 2;
-  static constexpr int Y_BYTES = NYB * YROWS * YWD * 4;
+  // Workgroups of two waves, whose residency LDS sets, keep luma in a ring
+  // of two sub-tiles plus one block row instead (which still holds the last
+  // two chroma rows' luma of sub-tile k-2 while k is transformed): 4 rather
+  // than 3 of them fit a CU.
+  static constexpr bool YCOMPACT = HALO_Y && NT <= 128;
+  static constexpr int YRING = YCOMPACT ? 2 * YROWS + 8 : NYB * YROWS;
+  static constexpr int Y_BYTES = YRING * YWD * 4;
   static constexpr int CWD = (SX + 2) * 2;                 // chroma ring row, dwords (8-sample margins)
   static constexpr int CROWS = NYB * CR;                   // chroma ring rows
   // with the vertical filter, one more chroma row after the ring: the row
@@ -121,7 +127,7 @@ struct SegCfg {
   static_assert(NT % 64 == 0 && NT >= 96, "whole waves; quant table load needs 96 lanes");
   static_assert(!HALO_Y || HF <= 2, "vertical fancy filtering with HF 1 or 2");
   static_assert(N_MAIN % 64 == 0, "tile blocks fill whole waves");
-  static_assert(YROWS % 8 == 0, "whole block rows");
+  static_assert(YROWS % 8 == 0 && YRING % 8 == 0, "whole block rows; blocks never straddle the luma ring's wrap");
 };
 
 // WALK_LAST: the last row pair of a segment is upsampled in the same item
@@ -134,7 +140,7 @@ struct SegmentDecoder {
   static constexpr int HF = C::HF, VF = C::VF, SX = C::SX, SY = C::SY, NT = C::NT;
   static constexpr int NY = C::NY, BPM = C::BPM, SM = C::SM, N_MAIN = C::N_MAIN;
   static constexpr int N_SIDE = C::N_SIDE, N_SLOT = C::N_SLOT, N_TB = C::N_TB;
-  static constexpr int YWD = C::YWD, YROWS = C::YROWS, NYB = C::NYB;
+  static constexpr int YWD = C::YWD, YROWS = C::YROWS, NYB = C::NYB, YRING = C::YRING;
   static constexpr int CR = C::CR, CWD = C::CWD, CROWS = C::CROWS;
   static constexpr bool FANCY = C::FANCY, HALO_X = C::HALO_X, HALO_Y = C::HALO_Y;
 
@@ -156,9 +162,15 @@ struct SegmentDecoder {
   __device__ lds32* qtab16(int c) const { return reinterpret_cast<lds32*>(lds + C::OFF_Q16) + c * 32; }
 
   // Luma row r (0 <= r < YROWS) of sub-tile k lives in row ybase(k) + r of
-  // the luma area (slot k mod NYB).  ybase is uniform.
-  __device__ static int ybase(int k) { return (k % NYB) * YROWS; }
-  __device__ lds32* yrow(int base, int r) const { return luma() + (base + r) * YWD; }
+  // the luma area (slot k mod NYB), taken modulo YRING for the compact
+  // ring (a multiple of 8 rows, so a block never straddles its wrap).
+  // ybase is uniform.
+  __device__ static int ybase(int k) { return C::YCOMPACT ? (YROWS * k) % YRING : (k % NYB) * YROWS; }
+  __device__ static int ywrap(int i) {
+    if constexpr (C::YCOMPACT) i = i >= YRING ? i - YRING : i;
+    return i;
+  }
+  __device__ lds32* yrow(int base, int r) const { return luma() + ywrap(base + r) * YWD; }
   // Chroma row r (0 <= r < CR) of sub-tile k is ring row cbase(k) + r (a
   // sub-tile never wraps).  The row above the segment is ring row
   // CROWS - 1 (read at step 1, before sub-tile 2 takes that slot), the row
@@ -814,7 +826,7 @@ struct SegmentDecoder {
       const int ly = si.yb + 2 * cr;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const lds32* ysrc = luma() + (mul24(ly + j, YWD) + 2 * g);
+        const lds32* ysrc = luma() + (mul24(ywrap(ly + j), YWD) + 2 * g);
         yl[j][0] = ysrc[0];
         yl[j][1] = ysrc[1];
       }
@@ -905,7 +917,7 @@ struct SegmentDecoder {
       for (int i = 0; i < 3; ++i) sv[i] = mad3(pn[i], pf[i]);
       h2v2_row_x(sv, xs[c]);
     }
-    const lds32* ysrc = luma() + (mul24(si.yb + 2 * cr + j, YWD) + 2 * g);
+    const lds32* ysrc = luma() + (mul24(ywrap(si.yb + 2 * cr + j), YWD) + 2 * g);
     const uint32_t yl[2] = {ysrc[0], ysrc[1]};
     uint32_t w[6];
 #pragma unroll
@@ -960,7 +972,7 @@ struct SegmentDecoder {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       if (py0 + j >= H) break;
-      const uint32_t yd = luma()[mul24(ly + j, YWD) + g];
+      const uint32_t yd = luma()[mul24(ywrap(ly + j), YWD) + g];
       int x[2][4];
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
