@@ -14,7 +14,7 @@ from ._binding import (MJD_IDCT_FLOAT, MJD_IDCT_IFAST, MJD_IDCT_ISLOW, MJD_PART_
                        mjd_entropy_batch_info, mjd_entropy_batch_launch, mjd_entropy_batch_status,
                        mjd_entropy_decode, mjd_geometry_of, mjd_model, mjd_model_predict, mjd_poly1, mjd_poly2,
                        mjd_poly1_eval, mjd_poly1_fit, mjd_poly2_eval, mjd_poly2_fit, mjd_last_error, mjd_parse,
-                       mjd_restart_index, scan_frame)
+                       mjd_restart_index, make_frame, scan_frame)
 
 UPSAMPLE = {"simple": MJD_UPSAMPLE_SIMPLE, "fancy": MJD_UPSAMPLE_FANCY}
 

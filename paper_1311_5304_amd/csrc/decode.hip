@@ -5,6 +5,8 @@
 // workgroup walks its segments with the pipelined SegmentDecoder.  The grid
 // holds as many workgroups as the device keeps resident, so a workgroup that
 // finishes early takes further segments rather than leaving its slot idle.
+#include <atomic>
+
 #include "mjd_internal.h"
 #include "segment.h"
 
@@ -52,13 +54,26 @@ __global__ __launch_bounds__(C::NT, C::WAVES_PER_SIMD) void decode_segments_aan(
   walk_segments<C>(lds, im, sg, &ak);
 }
 
+// Workgroups of the kernel that stay resident on one CU, from the occupancy
+// API once per device (every launch asks; the query costs microseconds).
+constexpr int kMaxDevices = 64;
 template <class C>
 static hipError_t resident_per_cu(int* per_cu) {
+  static std::atomic<int> cached[kMaxDevices];
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices) {
+    const int c = cached[dev].load(std::memory_order_relaxed);
+    if (c > 0) {
+      *per_cu = c;
+      return hipSuccess;
+    }
+  }
   *per_cu = 0;
   hipError_t e;
   if constexpr (C::ISLOW) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, decode_segments<C>, C::NT, 0);
   else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, decode_segments_aan<C>, C::NT, 0);
   if (e == hipSuccess && *per_cu < 1) *per_cu = 1;
+  if (e == hipSuccess && dev >= 0 && dev < kMaxDevices) cached[dev].store(*per_cu, std::memory_order_relaxed);
   return e;
 }
 
