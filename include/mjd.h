@@ -238,9 +238,11 @@ int mjd_variant_geometry(const mjd_variant* variant, mjd_geometry* out, uint64_t
  * scale), < 2^31; < 2^24 for full-size colour images), only each row's
  * first ncomp * ceil(W / scale) bytes written; d_work: device workspace of
  * at least the size mjd_variant_geometry gives, 16-byte aligned, owned by
- * the caller, overwritten (may be NULL when that size is 0).  Asynchronous on
- * `stream`.  MJD_EINVAL for bad arguments, MJD_EDEVICE for launch
- * failures. */
+ * the caller, overwritten (may be NULL when that size is 0).  A full-size
+ * colour image runs with the context's tuning (segment length, workgroup
+ * count; the shape index only where the sampling's islow kernel is
+ * mjd_decode's), which changes speed only.  Asynchronous on `stream`.
+ * MJD_EINVAL for bad arguments, MJD_EDEVICE for launch failures. */
 int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* d_coef, const uint16_t* d_qt,
                        uint8_t* d_out, size_t pitch, void* d_work, uint64_t work_bytes, void* stream);
 

@@ -175,12 +175,11 @@ hipError_t shape_info(int hf, int vf, bool fancy, int index, int* sx, int* sy, i
 
 // The decoder variants on the fused path: every sampling (luma (1,1), (2,1),
 // (1,2), (2,2), (4,1)) with every IDCT method, one sub-tile shape each
-// (islow's 4:4:4 / 4:2:2 / 4:2:0 are the single-image kernel's defaults).
+// (islow's 4:4:4 / 4:2:2 / 4:2:0 are the single-image kernel's shape lists).
 // A factor of 4 is replicated in both modes.
 template <int M>
 static hipError_t launch_variant_method(const ImageView& im, int hf, int vf, bool fancy, int cu_count,
-                                       hipStream_t stream) {
-  const mjd_tuning tu{0, 0, 0};
+                                       const mjd_tuning& tu, hipStream_t stream) {
   const int rows = im.mcus_y;
   if (hf == 4) return launch_cfg<SegCfg<4, 1, false, 8, 4, 192, M>>(im, 0, rows, cu_count, tu, stream);
   if (hf == 1 && vf == 2)
@@ -207,11 +206,12 @@ hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf,
   return l[i].launch(im, row0, row1, cu_count, tu, stream);
 }
 
-hipError_t launch_variant(const ImageView& im, int hf, int vf, bool fancy, int idct, int cu_count, hipStream_t stream) {
+hipError_t launch_variant(const ImageView& im, int hf, int vf, bool fancy, int idct, int cu_count,
+                          const mjd_tuning& tu, hipStream_t stream) {
   switch (idct) {
-    case 0: return launch_variant_method<0>(im, hf, vf, fancy, cu_count, stream);
-    case 1: return launch_variant_method<1>(im, hf, vf, fancy, cu_count, stream);
-    default: return launch_variant_method<2>(im, hf, vf, fancy, cu_count, stream);
+    case 0: return launch_variant_method<0>(im, hf, vf, fancy, cu_count, tu, stream);
+    case 1: return launch_variant_method<1>(im, hf, vf, fancy, cu_count, tu, stream);
+    default: return launch_variant_method<2>(im, hf, vf, fancy, cu_count, tu, stream);
   }
 }
 

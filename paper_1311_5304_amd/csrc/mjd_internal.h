@@ -29,8 +29,11 @@ hipError_t launch_image(const ImageView& im, int row0, int row1, int hf, int vf,
 // per CU (index < shape_count).
 int shape_count(int hf, int vf, bool fancy);
 // The decoder variants on the fused path: luma sampling hf x vf ((1,1),
-// (2,1), (1,2), (2,2), (4,1)), IDCT method MJD_IDCT_*, the whole image.
-hipError_t launch_variant(const ImageView& im, int hf, int vf, bool fancy, int idct, int cu_count, hipStream_t stream);
+// (2,1), (1,2), (2,2), (4,1)), IDCT method MJD_IDCT_*, the whole image, with
+// the tuning's segment length and workgroup count (and shape, for the classes
+// whose islow kernel is the single-image kernel's shape list).
+hipError_t launch_variant(const ImageView& im, int hf, int vf, bool fancy, int idct, int cu_count,
+                          const mjd_tuning& tu, hipStream_t stream);
 hipError_t shape_info(int hf, int vf, bool fancy, int index, int* sx, int* sy, int* nt, int* lds_bytes, int* per_cu);
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);

@@ -539,7 +539,7 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
       if (hipSetDevice(ctx->device) != hipSuccess) return fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
     }
     const hipError_t e = launch_variant(im, static_cast<int>(variant->frame.h[0]), static_cast<int>(variant->frame.v[0]),
-                                        variant->upsample == MJD_UPSAMPLE_FANCY, variant->idct, ctx->cu_count,
+                                        variant->upsample == MJD_UPSAMPLE_FANCY, variant->idct, ctx->cu_count, ctx->tuning,
                                         static_cast<hipStream_t>(stream));
     if (cur != ctx->device) (void)hipSetDevice(cur);
     if (e != hipSuccess) return fail(MJD_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));

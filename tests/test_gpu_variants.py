@@ -2,6 +2,7 @@
 variant oracle, byte for byte: every IDCT method (islow, ifast, float) on
 every sampling ((1,1), (2,1), (1,2), (2,2), (4,1)) in both upsampling modes,
 and grayscale; ragged sizes spanning several workgroups, a 1x1 image,
+segments of one sub-tile up to a whole strip under several launch tunings,
 extreme coefficients of the whole input domain, padded and misaligned
 output rows, the largest widths and heights, and a 4096x3072 image per
 method.  islow through the variants
@@ -71,6 +72,33 @@ def test_every_sampling_and_mode_matches_oracle(M, ctx, method):
                 got = _run(M, ctx, fr, coef, qt, method, mode)
                 exp = V.decode_variant(fr, coef, qt, method, mode)
                 assert np.array_equal(got, exp), (method, hy, vy, w, h, mode, int((got != exp).sum()))
+
+
+# launch tunings: (sub-tiles per segment, workgroups, shape index).  Long
+# segments wrap every luma/chroma ring of the segment walk several times
+# (the 190-pixel image holds 6 sub-tiles of 2 MCU rows per strip); 8
+# workgroups walk many segments each; the shape index picks among the
+# single-image kernel's shapes where the islow class has several.
+TUNINGS = [(1, 8, 0), (3, 0, 1), (64, 0, 2), (64, 8, 0)]
+
+
+@pytest.mark.parametrize("method", V.IDCT_METHODS)
+def test_long_segments_and_tunings_match_oracle(M, ctx, method):
+    w, h = 257, 190
+    try:
+        for i, (hy, vy) in enumerate(SAMPLINGS):
+            fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 2)}
+            coef, qt = _case(5000 + 100 * i, fr)
+            for mode in ("simple", "fancy"):
+                exp = V.decode_variant(fr, coef, qt, method, mode)
+                for seg, wg, shape in TUNINGS:
+                    say(f"{method} {hy}x{vy} {mode} seg={seg} wg={wg} shape={shape}")
+                    M.mjd_ctx_set_tuning(ctx, seg, wg, shape)
+                    got = _run(M, ctx, fr, coef, qt, method, mode)
+                    assert np.array_equal(got, exp), (method, hy, vy, mode, seg, wg, shape,
+                                                      int((got != exp).sum()))
+    finally:
+        M.mjd_ctx_set_tuning(ctx, 0, 0, 0)
 
 
 @pytest.mark.parametrize("method", V.IDCT_METHODS)
