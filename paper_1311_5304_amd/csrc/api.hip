@@ -34,7 +34,6 @@ int job_view(const mjd_job* j, int upsample, ImageView* im, mjd_geometry* g) {
   im->qsel0 = j->frame.qsel[0];
   im->qsel1 = j->frame.qsel[1];
   im->qsel2 = j->frame.qsel[2];
-  im->aligned_out = (reinterpret_cast<uintptr_t>(j->d_rgb) % 4 == 0 && j->pitch % 4 == 0) ? 1 : 0;
   return MJD_OK;
 }
 

@@ -39,7 +39,7 @@ typedef __attribute__((address_space(3))) int16_t lds16;
 typedef __attribute__((address_space(3))) uint16_t ldsu16;
 // global-memory pointers for the RGB stores (global, not flat, instructions)
 typedef __attribute__((address_space(1))) uint8_t gbl8;
-typedef __attribute__((address_space(1))) uint32_t gbl32;
+typedef __attribute__((address_space(1), aligned(1))) uint32_t gbl32u;  // any byte address
 
 constexpr int round64c(int n) { return (n + 63) & ~63; }
 
@@ -56,7 +56,6 @@ struct ImageView {
   int mcus_x, mcus_y;
   int chroma_w, chroma_h;
   int qsel0, qsel1, qsel2;
-  int aligned_out;
 };
 
 // Segment = MCU columns [mx0, mx0 + SX) (clipped) x MCU rows [r0, r1).
@@ -694,7 +693,7 @@ struct SegmentDecoder {
     const SubInfo sa = uniform(sub_info(k - 1)), sb = uniform(sub_info(has_b ? k - 2 : 0));
     // every unit of the strip is whole and its rows 4-byte aligned: the
     // plain store path alone
-    const bool plain = im.aligned_out && (gcx0 + 8 * nmx) * HF <= im.width;
+    const bool plain = (gcx0 + 8 * nmx) * HF <= im.width;
     for (int it0 = 0; it0 < n_items; it0 += NT) {
       const int it = it0 + tid;
       int g, v;
@@ -736,7 +735,7 @@ struct SegmentDecoder {
   // gives wave j output row j.
   __device__ void last_pair_rows() const {
     const SubInfo sa = uniform(sub_info(K - 1));
-    const bool plain = im.aligned_out && (gcx0 + 8 * nmx) * HF <= im.width;
+    const bool plain = (gcx0 + 8 * nmx) * HF <= im.width;
     if constexpr (C::UX % 64 == 0) {
 #pragma unroll
       for (int it0 = 0; it0 < 4 * C::UX; it0 += NT) {
@@ -866,15 +865,8 @@ struct SegmentDecoder {
         for (int i = 0; i < 4; ++i) px[i] = ycc_wide(y16_of(yl[j][kk], i), xs[0][4 * kk + i], xs[1][4 * kk + i]);
         pack_rgb4(px, w + 3 * kk);
       }
-      if (PLAIN || (nv == 8 && im.aligned_out)) {
-        gbl32* wd = reinterpret_cast<gbl32*>(row);
-#pragma unroll
-        for (int kk = 0; kk < 6; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
-      } else if (nv == 8) {
-        store_shifted(row, w);
-      } else {
-        store_ragged(row, w, 3 * nv);
-      }
+      if (PLAIN || nv == 8) store_unit(row, w);
+      else store_ragged(row, w, 3 * nv);
       row += pitch24;
     }
   }
@@ -929,15 +921,8 @@ struct SegmentDecoder {
     }
     const int nv = min(8, W - px0);
     gbl8* row = si.rgb + (mul24(2 * cr + j, static_cast<int>(im.pitch)) + 24 * g);
-    if (PLAIN || (nv == 8 && im.aligned_out)) {
-      gbl32* wd = reinterpret_cast<gbl32*>(row);
-#pragma unroll
-      for (int kk = 0; kk < 6; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
-    } else if (nv == 8) {
-      store_shifted(row, w);
-    } else {
-      store_ragged(row, w, 3 * nv);
-    }
+    if (PLAIN || nv == 8) store_unit(row, w);
+    else store_ragged(row, w, 3 * nv);
   }
 
   // Chroma rows cr and cr + 1 of a sub-tile's strip, samples 4g..4g+3
@@ -988,15 +973,8 @@ struct SegmentDecoder {
       for (int i = 0; i < 4; ++i) px[i] = ycc_wide(y16_of(yd, i), x[0][i], x[1][i]);
       uint32_t w[3];
       pack_rgb4(px, w);
-      if (PLAIN || (nv == 4 && im.aligned_out)) {
-        gbl32* wd = reinterpret_cast<gbl32*>(row);
-#pragma unroll
-        for (int kk = 0; kk < 3; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
-      } else if (nv == 4) {
-        store_shifted(row, w);
-      } else {
-        store_ragged(row, w, 3 * nv);
-      }
+      if (PLAIN || nv == 4) store_unit(row, w);
+      else store_ragged(row, w, 3 * nv);
       row += pitch24;
     }
   }
@@ -1094,54 +1072,30 @@ struct SegmentDecoder {
           pack_rgb4(px, w + 3 * kk);
         }
         gbl8* row = si.rgb + (mul24(cr_l * VF + dy, pitch24) + 12 * HF * g);
-        if (nv == 4 * HF && im.aligned_out) {
-          gbl32* wd = reinterpret_cast<gbl32*>(row);
-          // streaming stores: RGB is written once and never read back
-          // here.  Except for islow 4:1:1, whose 48-byte rows left the L2
-          // as partial lines (1.63x the RGB bytes written; ordinary stores
-          // write 1.00x at the same speed, while the AAN configurations
-          // run 10% slower with them and keep these).
-          if constexpr (HF == 4 && C::ISLOW) {
-#pragma unroll
-            for (int kk = 0; kk < 3 * HF; ++kk) wd[kk] = w[kk];
-          } else {
-#pragma unroll
-            for (int kk = 0; kk < 3 * HF; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
-          }
-        } else if (nv == 4 * HF) {
-          store_shifted(row, w);
-        } else {
-          store_ragged(row, w, 3 * nv);
-        }
+        if (nv == 4 * HF) store_unit(row, w);
+        else store_ragged(row, w, 3 * nv);
       }
     }
   }
 
-  // A whole unit's 12*HF bytes at a row address that need not be 4-byte
-  // aligned (a pitch or base that is not a multiple of 4): the bytes are
-  // regrouped into the aligned dwords that cover them (one byte permute
-  // each), the dwords wholly inside the run are stored whole and the two
-  // partial end dwords byte by byte, so no byte outside the run is written.
-  __device__ static void store_shifted(gbl8* row, const uint32_t* w) {
-    constexpr int ND = 3 * HF;  // data dwords; the aligned cover has ND + 1
-    const int m = static_cast<int>(reinterpret_cast<uintptr_t>(row) & 3u);
-    gbl8* const a = row - m;  // 4-byte aligned
-    // cover dword j holds data bytes 4j - m .. 4j - m + 3: bytes 4 - m ..
-    // 7 - m of the pair (w[j], w[j - 1])
-    const uint32_t sel = 0x07060504u - static_cast<uint32_t>(m) * 0x01010101u;
-    uint32_t d[ND + 1];
+  // A whole unit's 12*HF bytes, in dword stores at the row address whether
+  // or not it is 4-byte aligned (a pitch or base that is not a multiple of
+  // 4): the HSA runtime runs the GPU in its unaligned access mode, which the
+  // compiler assumes for this target as well (it turns a byte-aligned 4-byte
+  // copy into one dword store).  Streaming stores, as RGB is written once
+  // and never read back here; except for islow 4:1:1, whose 48-byte rows
+  // left the L2 as partial lines with them (1.63x the RGB bytes written;
+  // ordinary stores write 1.00x at the same speed, while the AAN 4:1:1
+  // kernels run 10% slower with ordinary stores and keep streaming ones).
+  __device__ static void store_unit(gbl8* row, const uint32_t* w) {
+    gbl32u* wd = reinterpret_cast<gbl32u*>(row);
+    if constexpr (HF == 4 && C::ISLOW) {
 #pragma unroll
-    for (int j = 0; j <= ND; ++j)
-      d[j] = __builtin_amdgcn_perm(j < ND ? w[j] : 0u, j > 0 ? w[j - 1] : 0u, sel);
-    gbl32* ad = reinterpret_cast<gbl32*>(a);
+      for (int kk = 0; kk < 3 * HF; ++kk) wd[kk] = w[kk];
+    } else {
 #pragma unroll
-    for (int j = 1; j < ND; ++j) __builtin_nontemporal_store(d[j], &ad[j]);
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (b >= m) a[b] = static_cast<uint8_t>(d[0] >> (8 * b));
-#pragma unroll
-    for (int b = 0; b < 3; ++b)
-      if (b < m) a[4 * ND + b] = static_cast<uint8_t>(d[ND] >> (8 * b));
+      for (int kk = 0; kk < 3 * HF; ++kk) __builtin_nontemporal_store(w[kk], &wd[kk]);
+    }
   }
 
   // Ragged right edge: byte stores of the first nbytes bytes of w (constant

@@ -103,12 +103,17 @@ struct View {
   uint64_t plane_off[3];
   uint32_t plane_pitch[3];
   uint32_t pitch;
-  int width, height, ncomp, hy, vy, mcus_x, bpm, fancy, aligned_out;
+  int width, height, ncomp, hy, vy, mcus_x, bpm, fancy;
   int qsel[3];
   int comp_w, comp_h;  // the chroma components' true size
 };
 
 __device__ __forceinline__ uint32_t clamp_u8(int v) { return static_cast<uint32_t>(min(max(v, 0), 255)); }
+
+// A dword at any byte address: output rows need not be 4-byte aligned, and
+// the HSA runtime runs the GPU in its unaligned access mode (the compiler
+// assumes it for this target too), so whole runs take dword stores.
+typedef uint32_t __attribute__((aligned(1))) u32u;
 
 // --- kernel 1: dequantise + IDCT -------------------------------------------
 // One decoded row of eight samples: into the component's plane, or, for
@@ -121,8 +126,10 @@ __device__ __forceinline__ void store_row(const View& v, int comp, int bx, int b
     if (y >= v.height) return;
     uint8_t* dst = v.out + static_cast<size_t>(y) * v.pitch + bx * 8;
     const int n = min(8, v.width - bx * 8);
-    if (n == 8 && v.aligned_out) {
-      *reinterpret_cast<uint2*>(dst) = make_uint2(lo, hi);
+    if (n == 8) {
+      u32u* d = reinterpret_cast<u32u*>(dst);
+      d[0] = lo;
+      d[1] = hi;
     } else {
 #pragma unroll
       for (int i = 0; i < 8; ++i)
@@ -460,8 +467,8 @@ __global__ __launch_bounds__(256) void var_colour(const View v) {
   }
   uint8_t* dst = v.out + static_cast<size_t>(y) * v.pitch + 3 * x0;
   const int n = min(8, v.width - x0);
-  if (n == 8 && v.aligned_out) {
-    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+  if (n == 8) {
+    u32u* d = reinterpret_cast<u32u*>(dst);
 #pragma unroll
     for (int i = 0; i < 6; ++i) d[i] = b[4 * i] | (b[4 * i + 1] << 8) | (b[4 * i + 2] << 16) | (b[4 * i + 3] << 24);
   } else {
@@ -533,7 +540,6 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
     im.qsel0 = static_cast<int>(variant->frame.qsel[0]);
     im.qsel1 = static_cast<int>(variant->frame.qsel[1]);
     im.qsel2 = static_cast<int>(variant->frame.qsel[2]);
-    im.aligned_out = (reinterpret_cast<uintptr_t>(d_out) % 4 == 0 && pitch % 4 == 0) ? 1 : 0;
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess || cur != ctx->device) {
       if (hipSetDevice(ctx->device) != hipSuccess) return fail(MJD_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
@@ -565,8 +571,6 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   v.mcus_x = static_cast<int>(g.mcus_x);
   v.bpm = static_cast<int>(g.blocks_per_mcu);
   v.fancy = variant->upsample == MJD_UPSAMPLE_FANCY ? 1 : 0;
-  const size_t align = nc == 1 ? 8 : 4;
-  v.aligned_out = (reinterpret_cast<uintptr_t>(d_out) % align == 0 && pitch % align == 0) ? 1 : 0;
   for (int c = 0; c < 3; ++c) v.qsel[c] = c < nc ? variant->frame.qsel[c] : 0;
   v.comp_w = static_cast<int>(g.comp_w[1]);
   v.comp_h = static_cast<int>(g.comp_h[1]);
