@@ -79,6 +79,38 @@ def test_batch_matches_oracle(M, ctx, batch_inputs, mode):
             b.close()
 
 
+@pytest.mark.parametrize("mode", ["fancy", "simple"])
+def test_batch_rows_at_any_byte_address(M, ctx, batch_inputs, mode):
+    """Every image written at a base 1..3 bytes past a 4-byte boundary with
+    a padded pitch (3W + 1..5 bytes): whole units take dword stores at those
+    unaligned addresses; every RGB byte equals the oracle's and no byte of
+    the padding or around the image changes."""
+    exp = [oracle.decode(f, c, q, mode) for f, c, q in batch_inputs]
+    jobs, bufs, geo = [], [], []
+    for i, (frame, coef, qt) in enumerate(batch_inputs):
+        w, h = frame["width"], frame["height"]
+        off, pitch = 1 + i % 3, 3 * w + 1 + i % 5
+        buf = torch.full((h * pitch + off + 16,), 0xA5, dtype=torch.uint8, device="cuda")
+        c = torch.from_numpy(coef).cuda()
+        q = torch.from_numpy(qt.view(np.int16)).cuda()
+        jobs.append((frame, c, q, buf.data_ptr() + off, pitch))
+        bufs.append(buf)
+        geo.append((off, pitch, w, h))
+    say(f"batch {mode} at unaligned bases and pitches")
+    b = M.Batch(ctx, jobs, M.UPSAMPLE[mode])
+    try:
+        b.launch()
+        torch.cuda.synchronize()
+    finally:
+        b.close()
+    for i, (buf, e, (off, pitch, w, h)) in enumerate(zip(bufs, exp, geo)):
+        got = buf.cpu().numpy()
+        rows = got[off:off + h * pitch].reshape(h, pitch)
+        assert np.array_equal(rows[:, :3 * w].reshape(h, w, 3), e), (i, off, pitch)
+        assert (rows[:, 3 * w:] == 0xA5).all() and (got[:off] == 0xA5).all() and (got[off + h * pitch:] == 0xA5).all(), \
+            (i, off, pitch)
+
+
 def test_batch_equals_per_image_calls(M, ctx, batch_inputs):
     jobs, outs = _device_jobs(batch_inputs)
     b = M.Batch(ctx, jobs, M.MJD_UPSAMPLE_FANCY)
