@@ -691,8 +691,7 @@ struct SegmentDecoder {
     const bool has_b = k >= 2;
     const int n_items = ITEMS + (LAST_IN_WALK && k == K ? C::UX : 0);
     const SubInfo sa = uniform(sub_info(k - 1)), sb = uniform(sub_info(has_b ? k - 2 : 0));
-    // every unit of the strip is whole and its rows 4-byte aligned: the
-    // plain store path alone
+    // every unit of the strip is whole: the plain store path alone
     const bool plain = (gcx0 + 8 * nmx) * HF <= im.width;
     for (int it0 = 0; it0 < n_items; it0 += NT) {
       const int it = it0 + tid;
