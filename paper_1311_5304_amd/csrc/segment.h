@@ -1079,9 +1079,9 @@ struct SegmentDecoder {
 
   // A whole unit's 12*HF bytes, in dword stores at the row address whether
   // or not it is 4-byte aligned (a pitch or base that is not a multiple of
-  // 4): the HSA runtime runs the GPU in its unaligned access mode, which the
-  // compiler assumes for this target as well (it turns a byte-aligned 4-byte
-  // copy into one dword store).  Streaming stores, as RGB is written once
+  // 4): the ROCm kernel driver runs compute queues in the GPU's unaligned
+  // access mode, which the compiler assumes for this target as well (it
+  // turns a byte-aligned 4-byte copy into one dword store).  Streaming stores, as RGB is written once
   // and never read back here; except for islow 4:1:1, whose 48-byte rows
   // left the L2 as partial lines with them (1.63x the RGB bytes written;
   // ordinary stores write 1.00x at the same speed, while the AAN 4:1:1

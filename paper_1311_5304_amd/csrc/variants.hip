@@ -111,8 +111,9 @@ struct View {
 __device__ __forceinline__ uint32_t clamp_u8(int v) { return static_cast<uint32_t>(min(max(v, 0), 255)); }
 
 // A dword at any byte address: output rows need not be 4-byte aligned, and
-// the HSA runtime runs the GPU in its unaligned access mode (the compiler
-// assumes it for this target too), so whole runs take dword stores.
+// the ROCm kernel driver runs compute queues in the GPU's unaligned access
+// mode (the compiler assumes it for this target too), so whole runs take
+// dword stores.
 typedef uint32_t __attribute__((aligned(1))) u32u;
 
 // --- kernel 1: dequantise + IDCT -------------------------------------------
