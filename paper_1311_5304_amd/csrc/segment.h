@@ -39,6 +39,7 @@ typedef __attribute__((address_space(3))) int16_t lds16;
 typedef __attribute__((address_space(3))) uint16_t ldsu16;
 // global-memory pointers for the RGB stores (global, not flat, instructions)
 typedef __attribute__((address_space(1))) uint8_t gbl8;
+typedef __attribute__((address_space(1), aligned(1))) uint16_t gbl16u;  // any byte address
 typedef __attribute__((address_space(1), aligned(1))) uint32_t gbl32u;  // any byte address
 
 constexpr int round64c(int n) { return (n + 63) & ~63; }
@@ -1097,14 +1098,22 @@ struct SegmentDecoder {
     }
   }
 
-  // Ragged right edge: byte stores of the first nbytes bytes of w (constant
-  // register indices; the run is at most 12*HF bytes).
+  // Ragged right edge: the first nbytes bytes of w (nbytes < 12*HF, a
+  // partial unit), as its whole dwords and then a 16-bit and a byte store
+  // for the last 1..3 bytes, all at any byte address (unaligned access
+  // mode, as above; constant register indices).
   __device__ static void store_ragged(gbl8* row, const uint32_t* w, int nbytes) {
+    gbl32u* wd = reinterpret_cast<gbl32u*>(row);
+    const int nd = nbytes >> 2;  // whole dwords, at most 3*HF - 1
+    uint32_t last = w[0];        // the dword holding the last 1..3 bytes
 #pragma unroll
-    for (int kk = 0; kk < 3 * HF; ++kk)
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-        if (4 * kk + b < nbytes) row[4 * kk + b] = static_cast<uint8_t>(w[kk] >> (8 * b));
+    for (int kk = 0; kk < 3 * HF - 1; ++kk) {
+      if (kk < nd) wd[kk] = w[kk];
+      if (kk + 1 == nd) last = w[kk + 1];
+    }
+    gbl8* tail = row + 4 * nd;
+    if (nbytes & 2) *reinterpret_cast<gbl16u*>(tail) = static_cast<uint16_t>(last);
+    if (nbytes & 1) tail[nbytes & 2] = static_cast<uint8_t>(last >> (8 * (nbytes & 2)));
   }
 
   // ---- the pipelined walk over one segment ----
