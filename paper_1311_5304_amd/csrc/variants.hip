@@ -3,10 +3,12 @@
 // samplings beyond 4:4:4 / 4:2:2 / 4:2:0 (the paper decodes the others the
 // same way, Sec. 4.2) and grayscale.  A generic two-kernel path, not the
 // tuned segment pipeline of the fixed configurations:
+//   var_gray    grayscale islow: one block per lane, the fused kernel's
+//               dequantise + IDCT, straight into the output rows;
 //   var_idct    dequantise + 8x8 IDCT, one block per 8 lanes (column pass,
 //               then row pass, through LDS), into per-component sample
-//               planes in a caller workspace (grayscale: straight into the
-//               output rows);
+//               planes in a caller workspace (grayscale ifast and float:
+//               straight into the output rows);
 //   var_colour  chroma upsampling (simple; triangle filter for factors of 2,
 //               Algorithm 1, vertical for h1v2) + YCbCr->RGB (Algorithm 2),
 //               eight pixels per lane.
@@ -274,6 +276,84 @@ __global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts 
   }
 }
 
+// --- kernel 1a: grayscale islow, one block per lane ---------------------------
+// A grayscale MCU is one block, so the blocks lie in raster order.  Each wave
+// takes runs of 64 consecutive blocks, one per lane: the block's 8
+// coefficient rows go straight into registers (the wave's next run loads
+// while this one is transformed), through the fused kernel's dequantise +
+// IDCT (dot-product passes, the same islow arithmetic), and out as 8-byte
+// sample rows at any byte address (unaligned access mode, as above),
+// cropped at the image's right and bottom edges.
+constexpr int kGrayThreads = 256;
+constexpr int kGrayWaves = kGrayThreads / 64;
+
+__global__ __launch_bounds__(kGrayThreads) void var_gray(const View v) {
+  __shared__ __align__(16) uint32_t qs[32];
+  __shared__ __align__(16) uint32_t qs16[32];
+  const int t = static_cast<int>(threadIdx.x);
+  if (t < 32) {
+    // the table as uint16 pairs, and times 16 (the scaled pass 1 reads it)
+    const uint16_t* qt = v.qt + 64 * v.qsel[0];
+    const uint32_t lo = qt[2 * t], hi = qt[2 * t + 1];
+    qs[t] = lo | (hi << 16);
+    qs16[t] = ((lo << 4) & 0xFFFFu) | (((hi << 4) & 0xFFFFu) << 16);
+  }
+  __syncthreads();
+  const lds32* q = (const lds32*)qs;
+  const lds32* q16 = (const lds32*)qs16;
+  const uint32_t n_blocks = static_cast<uint32_t>(v.n_blocks);
+  const uint32_t n_runs = (n_blocks + 63) / 64;
+  const uint32_t lane = static_cast<uint32_t>(t & 63);
+  const uint32_t stride = gridDim.x * kGrayWaves;
+  const uint32_t mcx = static_cast<uint32_t>(v.mcus_x);
+  auto load = [&](uint32_t run, v4i rows[8]) {
+    const uint32_t b = run * 64 + lane;
+    if (run < n_runs && b < n_blocks) {
+      const v4i* src = reinterpret_cast<const v4i*>(v.coef) + static_cast<size_t>(b) * 8;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) rows[r] = src[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) rows[r] = v4i{0, 0, 0, 0};
+    }
+  };
+  uint32_t run = blockIdx.x * kGrayWaves + static_cast<uint32_t>(t >> 6);
+  v4i next[8];
+  load(run, next);
+  for (; run < n_runs; run += stride) {
+    v4i rows[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) rows[r] = next[r];
+    load(run + stride, next);
+    uint32_t out[16];
+    idct_block_fast(rows, q, q16, out);  // every lane of the wave (the range test is wave-wide)
+    const uint32_t b = run * 64 + lane;
+    if (b >= n_blocks) continue;
+    const uint32_t by = b / mcx, bx = b - by * mcx;
+    const int px0 = static_cast<int>(bx) * 8;
+    const int n = min(8, v.width - px0);
+    // the output as a global (not flat) pointer: the store instructions
+    gbl8* dst = (gbl8*)(v.out + static_cast<size_t>(by) * 8 * v.pitch + px0);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (static_cast<int>(by) * 8 + r >= v.height) break;
+      if (n == 8) {
+        gbl32u* d = reinterpret_cast<gbl32u*>(dst);
+        __builtin_nontemporal_store(out[2 * r], &d[0]);
+        __builtin_nontemporal_store(out[2 * r + 1], &d[1]);
+      } else {
+        // n = 1..7: a whole dword if n >= 4, then a 16-bit and a byte store
+        if (n >= 4) *reinterpret_cast<gbl32u*>(dst) = out[2 * r];
+        const uint32_t last = n >= 4 ? out[2 * r + 1] : out[2 * r];
+        gbl8* tail = dst + (n & 4);
+        if (n & 2) *reinterpret_cast<gbl16u*>(tail) = static_cast<uint16_t>(last);
+        if (n & 1) tail[n & 2] = static_cast<uint8_t>(last >> (8 * (n & 2)));
+      }
+      dst += v.pitch;
+    }
+  }
+}
+
 // --- kernel 1b: reduced IDCT for scaled decoding -----------------------------
 template <int N>
 __device__ __forceinline__ void red_1d(const int x[N], int y[N], const int32_t* K, int bias) {
@@ -479,6 +559,26 @@ __global__ __launch_bounds__(256) void var_colour(const View v) {
 
 // The IDCT kernel runs as many workgroups as stay resident (each loops over
 // tiles), or about one per tile when there are fewer.
+// Grayscale islow: as many workgroups as stay resident, at most one wave per
+// run of 64 blocks.
+hipError_t launch_gray(const View& v, int cu_count, hipStream_t s) {
+  static std::atomic<int> cached{0};  // resident workgroups per CU (the same on every gfx950 device)
+  int per_cu = cached.load(std::memory_order_relaxed);
+  if (per_cu == 0) {
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, var_gray, kGrayThreads, 0);
+    if (e != hipSuccess) return e;
+    per_cu = n > 0 ? n : 1;
+    cached.store(per_cu, std::memory_order_relaxed);
+  }
+  const uint64_t slots = static_cast<uint64_t>(per_cu) * (cu_count > 0 ? cu_count : 256);
+  const uint64_t runs = (v.n_blocks + 63) / 64;
+  const uint64_t want = (runs + kGrayWaves - 1) / kGrayWaves;
+  const unsigned grid = static_cast<unsigned>(want < slots ? want : slots);
+  hipLaunchKernelGGL(var_gray, dim3(grid), dim3(kGrayThreads), 0, s, v);
+  return hipGetLastError();
+}
+
 template <int M>
 hipError_t launch_idct(const View& v, const Consts& k, uint64_t n_tiles, int cu_count, hipStream_t s) {
   static std::atomic<int> cached{0};  // resident workgroups per CU (the same on every gfx950 device)
@@ -591,7 +691,9 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
     else hipLaunchKernelGGL(var::var_idct_red<1>, dim3(grid_red), dim3(256), 0, s, v, rk);
     e = hipGetLastError();
   } else switch (variant->idct) {
-    case MJD_IDCT_ISLOW: e = var::launch_idct<MJD_IDCT_ISLOW>(v, k, n_tiles, ctx->cu_count, s); break;
+    case MJD_IDCT_ISLOW:
+      e = nc == 1 ? var::launch_gray(v, ctx->cu_count, s) : var::launch_idct<MJD_IDCT_ISLOW>(v, k, n_tiles, ctx->cu_count, s);
+      break;
     case MJD_IDCT_IFAST: e = var::launch_idct<MJD_IDCT_IFAST>(v, k, n_tiles, ctx->cu_count, s); break;
     default: e = var::launch_idct<MJD_IDCT_FLOAT>(v, k, n_tiles, ctx->cu_count, s); break;
   }
