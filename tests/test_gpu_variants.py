@@ -129,24 +129,25 @@ def test_islow_variant_equals_the_fused_kernel(M, ctx):
 def test_padded_and_misaligned_rows(M, ctx):
     # rows of pitch 3w + 5 starting one byte past an aligned address: the
     # bytes between rows and around the image stay untouched
-    for ncomp, (hy, vy) in ((3, (2, 2)), (3, (4, 1)), (1, (1, 1))):
+    for method, ncomp, (hy, vy) in (("float", 3, (2, 2)), ("float", 3, (4, 1)), ("float", 1, (1, 1)),
+                                    ("islow", 3, (2, 2)), ("islow", 1, (1, 1))):
         w, h = 61, 35
         fr = {"width": w, "height": h, "h": (hy, 1, 1), "v": (vy, 1, 1), "qsel": (0, 1, 1), "ncomp": ncomp}
         coef, qt = _case(31 + hy, fr)
-        v = M.make_variant(fr, ncomp, "float", "fancy")
+        v = M.make_variant(fr, ncomp, method, "fancy")
         g, wb = M.mjd_variant_geometry(v)
         pitch = ncomp * w + 5
         buf = torch.full((h * pitch + 64,), 0xA5, dtype=torch.uint8, device="cuda")
         work = torch.empty(max(wb, 16), dtype=torch.uint8, device="cuda")
         cd = torch.from_numpy(coef.reshape(-1)).cuda()
         qd = torch.from_numpy(qt.view(np.int16).reshape(-1)).cuda()
-        say(f"misaligned ncomp={ncomp} {hy}x{vy}")
+        say(f"misaligned {method} ncomp={ncomp} {hy}x{vy}")
         M.mjd_decode_variant(ctx, v, cd, qd, buf.data_ptr() + 1, pitch, work, wb)
         torch.cuda.synchronize()
         b = buf.cpu().numpy()
         rows = b[1:1 + h * pitch].reshape(h, pitch)
-        exp = V.decode_variant(fr, coef, qt, "float", "fancy")
-        assert np.array_equal(rows[:, :ncomp * w].reshape(exp.shape), exp)
+        exp = V.decode_variant(fr, coef, qt, method, "fancy")
+        assert np.array_equal(rows[:, :ncomp * w].reshape(exp.shape), exp), method
         assert np.all(rows[:, ncomp * w:] == 0xA5) and b[0] == 0xA5 and np.all(b[1 + h * pitch:] == 0xA5)
 
 
