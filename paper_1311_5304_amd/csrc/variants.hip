@@ -1,14 +1,11 @@
 // Decoder variants: the IDCT methods libjpeg offers beside islow (the paper
 // notes AAN-based and integer-or-float IDCTs, Sec. 2 and Sec. 3), the
 // samplings beyond 4:4:4 / 4:2:2 / 4:2:0 (the paper decodes the others the
-// same way, Sec. 4.2) and grayscale.  A generic two-kernel path, not the
-// tuned segment pipeline of the fixed configurations:
-//   var_gray    grayscale islow: one block per lane, the fused kernel's
-//               dequantise + IDCT, straight into the output rows;
-//   var_idct    dequantise + 8x8 IDCT, one block per 8 lanes (column pass,
-//               then row pass, through LDS), into per-component sample
-//               planes in a caller workspace (grayscale ifast and float:
-//               straight into the output rows);
+// same way, Sec. 4.2) and grayscale.  Full-size colour images run the fused
+// segment kernel; the kernels here serve the rest:
+//   var_gray    grayscale: one block per lane, the fused kernels'
+//               dequantise + IDCT of each method, straight into the output
+//               rows;
 //   var_colour  chroma upsampling (simple; triangle filter for factors of 2,
 //               Algorithm 1, vertical for h1v2) + YCbCr->RGB (Algorithm 2),
 //               eight pixels per lane.
@@ -40,12 +37,6 @@
 #pragma clang fp contract(off)
 
 namespace mjd {
-namespace var {
-
-constexpr int kBlocksPerWG = 32;
-constexpr int kThreads = 8 * kBlocksPerWG;
-}  // namespace var
-
 // Scale factors and constants of the AAN methods (aan.h), from the C
 // library's cos, once.
 const AanConsts& aan_consts() {
@@ -73,7 +64,6 @@ const AanConsts& aan_consts() {
 
 namespace var {
 
-using Consts = AanConsts;
 
 // Constants of the reduced transforms: K[m][u] = round(2^13 sqrt(2)
 // cos((2m+1) u pi / 2N)), index N*m + u.
@@ -118,185 +108,35 @@ __device__ __forceinline__ uint32_t clamp_u8(int v) { return static_cast<uint32_
 // dword stores.
 typedef uint32_t __attribute__((aligned(1))) u32u;
 
-// --- kernel 1: dequantise + IDCT -------------------------------------------
-// One decoded row of eight samples: into the component's plane, or, for
-// grayscale, straight into the output row (cropped to the image).
-__device__ __forceinline__ void store_row(const View& v, int comp, int bx, int by, int lane, const uint32_t px[8]) {
-  const uint32_t lo = px[0] | (px[1] << 8) | (px[2] << 16) | (px[3] << 24);
-  const uint32_t hi = px[4] | (px[5] << 8) | (px[6] << 16) | (px[7] << 24);
-  const int y = by * 8 + lane;
-  if (v.ncomp == 1) {
-    if (y >= v.height) return;
-    uint8_t* dst = v.out + static_cast<size_t>(y) * v.pitch + bx * 8;
-    const int n = min(8, v.width - bx * 8);
-    if (n == 8) {
-      u32u* d = reinterpret_cast<u32u*>(dst);
-      d[0] = lo;
-      d[1] = hi;
-    } else {
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < n) dst[i] = static_cast<uint8_t>(px[i]);
-    }
-    return;
-  }
-  uint8_t* dst = v.work + v.plane_off[comp] + static_cast<size_t>(y) * v.plane_pitch[comp] + bx * 8;
-  *reinterpret_cast<uint2*>(dst) = make_uint2(lo, hi);
-}
-
-// LDS layouts without bank conflicts for the eight blocks of a wave:
-// coefficients 72 int16 (144 bytes) per block, so the eight blocks' column
-// reads fall on distinct banks; transform values in rows of 9 words, 72
-// words per block, so both the column writes and the row reads of a wave
-// cover 64 distinct banks.
-constexpr int kCfStride = 72;
-constexpr int kWsRow = 9;
-constexpr int kWsStride = 72;
-
-template <int M>
-__global__ __launch_bounds__(kThreads) void var_idct(const View v, const Consts k) {
-  __shared__ __align__(16) int16_t cf[kBlocksPerWG * kCfStride];
-  __shared__ __align__(16) int32_t ws[kBlocksPerWG * kWsStride];
-  __shared__ int32_t tab[4 * 64];
-  const int t = static_cast<int>(threadIdx.x);
-  // the four multiplier tables
-  {
-    const int e = t & 63;
-    const uint32_t q = v.qt[t];
-    if constexpr (M == MJD_IDCT_ISLOW) {
-      tab[t] = static_cast<int32_t>(q);
-    } else if constexpr (M == MJD_IDCT_IFAST) {
-      tab[t] = static_cast<int32_t>((static_cast<int64_t>(q) * k.a14[e] + (1 << (13 - kIfastFrac))) >> (14 - kIfastFrac));
-    } else {
-      tab[t] = __float_as_int(static_cast<float>(static_cast<double>(q) / k.ss8[e]));
-    }
-  }
-  // block indices fit 32 bits: at most 65535^2 / 64 * 3 blocks
-  const uint32_t n_blocks = static_cast<uint32_t>(v.n_blocks);
-  const uint32_t n_tiles = (n_blocks + kBlocksPerWG - 1) / kBlocksPerWG;
-  const int blk = t >> 3, lane = t & 7;
-  // persistent over tiles of 32 blocks; the next tile's coefficients load
-  // into registers while this one is transformed
-  auto load = [&](uint32_t tile) {
-    int4 d = {0, 0, 0, 0};
-    const uint32_t bb = tile * kBlocksPerWG + blk;
-    if (tile < n_tiles && bb < n_blocks) d = reinterpret_cast<const int4*>(v.coef + static_cast<size_t>(bb) * 64)[lane];
-    return d;
-  };
-  // Workgroups are dealt to the 8 XCDs round-robin (the grid is a multiple
-  // of 8): each XCD walks its own contiguous run of tiles, so the partial
-  // plane lines that neighbouring tiles write meet in one L2.
-  const uint32_t per_xcd = (n_tiles + 7) / 8;
-  const uint32_t xcd = blockIdx.x & 7u;
-  const uint32_t end = min(n_tiles, (xcd + 1) * per_xcd);
-  const uint32_t stride = gridDim.x >> 3;
-  uint32_t tile = xcd * per_xcd + (blockIdx.x >> 3);
-  int4 next = tile < end ? load(tile) : int4{0, 0, 0, 0};
-  for (; tile < end; tile += stride) {
-    *reinterpret_cast<int4*>(cf + blk * kCfStride + lane * 8) = next;
-    next = tile + stride < end ? load(tile + stride) : int4{0, 0, 0, 0};
-    __syncthreads();
-    const uint32_t b = tile * kBlocksPerWG + blk;
-    const bool live = b < n_blocks;
-    // the block's component and position in that component's block grid
-    int comp = 0, bx, by;
-    {
-      const uint32_t bpm = static_cast<uint32_t>(v.bpm), mcx = static_cast<uint32_t>(v.mcus_x);
-      const uint32_t m = live ? b / bpm : 0;
-      const int j = live ? static_cast<int>(b - m * bpm) : 0;
-      const uint32_t myu = m / mcx;
-      const int mx = static_cast<int>(m - myu * mcx);
-      const int my = static_cast<int>(myu);
-      const int ny = v.hy * v.vy;
-      if (v.ncomp == 1 || j < ny) {
-        const int jy = j / v.hy, jx = j - jy * v.hy;
-        bx = mx * v.hy + jx;
-        by = my * v.vy + jy;
-      } else {
-        comp = j - ny + 1;
-        bx = mx;
-        by = my;
-      }
-    }
-    const int32_t* q = tab + 64 * v.qsel[comp];
-    const int16_t* c = cf + kCfStride * blk;
-    int32_t* w = ws + kWsStride * blk;
-    // column pass: this lane's column `lane`
-    if constexpr (M == MJD_IDCT_ISLOW) {
-      int y[8];
-      idct8_raw(c[lane] * q[lane], c[8 + lane] * q[8 + lane], c[16 + lane] * q[16 + lane],
-                c[24 + lane] * q[24 + lane], c[32 + lane] * q[32 + lane], c[40 + lane] * q[40 + lane],
-                c[48 + lane] * q[48 + lane], c[56 + lane] * q[56 + lane], kPass1Bias, y);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) w[kWsRow * i + lane] = y[i] >> kPass1Shift;
-    } else if constexpr (M == MJD_IDCT_IFAST) {
-      const IfastOps ops{k.ki[0], k.ki[1], k.ki[2], k.ki[3]};
-      int in[8], y[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) in[u] = c[8 * u + lane] * q[8 * u + lane];
-      aan8(in, y, ops);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) w[kWsRow * i + lane] = y[i];
-    } else {
-      const FloatOps ops{k.kf[0], k.kf[1], k.kf[2], k.kf[3]};
-      float in[8], y[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) in[u] = static_cast<float>(c[8 * u + lane]) * __int_as_float(q[8 * u + lane]);
-      aan8(in, y, ops);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) w[kWsRow * i + lane] = __float_as_int(y[i]);
-    }
-    __syncthreads();
-    // row pass: this lane's row `lane`
-    uint32_t px[8];
-    const int* r = w + kWsRow * lane;
-    if constexpr (M == MJD_IDCT_ISLOW) {
-      int s[8];
-      idct8_raw(r[0], r[1], r[2], r[3], r[4], r[5], r[6], r[7], kPass2Bias, s);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) px[i] = clamp_u8(s[i] >> kPass2Shift);
-    } else if constexpr (M == MJD_IDCT_IFAST) {
-      const IfastOps ops{k.ki[0], k.ki[1], k.ki[2], k.ki[3]};
-      int in[8], s[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) in[i] = r[i];
-      aan8(in, s, ops);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) px[i] = clamp_u8(((s[i] + (1 << (kIfastShift - 1))) >> kIfastShift) + 128);
-    } else {
-      const FloatOps ops{k.kf[0], k.kf[1], k.kf[2], k.kf[3]};
-      float in[8], s[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) in[i] = __int_as_float(r[i]);
-      aan8(in, s, ops);
-#pragma unroll
-      for (int i = 0; i < 8; ++i) px[i] = clamp_u8(static_cast<int>(floorf(s[i] + 128.5f)));
-    }
-    if (live) store_row(v, comp, bx, by, lane, px);
-  }
-}
-
-// --- kernel 1a: grayscale islow, one block per lane ---------------------------
+// --- kernel 1: grayscale, one block per lane ----------------------------------
 // A grayscale MCU is one block, so the blocks lie in raster order.  Each wave
 // takes runs of 64 consecutive blocks, one per lane: the block's 8
 // coefficient rows go straight into registers (the wave's next run loads
-// while this one is transformed), through the fused kernel's dequantise +
-// IDCT (dot-product passes, the same islow arithmetic), and out as 8-byte
-// sample rows at any byte address (unaligned access mode, as above),
-// cropped at the image's right and bottom edges.
+// while this one is transformed), through the fused kernels' dequantise +
+// IDCT of the method (islow: the dot-product passes; ifast, float: the AAN
+// flowgraph on one lane), and out as 8-byte sample rows at any byte address
+// (unaligned access mode, as above), cropped at the image's right and
+// bottom edges.
 constexpr int kGrayThreads = 256;
 constexpr int kGrayWaves = kGrayThreads / 64;
 
-__global__ __launch_bounds__(kGrayThreads) void var_gray(const View v) {
-  __shared__ __align__(16) uint32_t qs[32];
+template <int M>
+__global__ __launch_bounds__(kGrayThreads) void var_gray(const View v, const AanConsts k) {
+  // islow: the table as uint16 pairs, and times 16 (the scaled pass 1
+  // reads it); ifast, float: the 64 AAN multipliers
+  __shared__ __align__(16) uint32_t qs[64];
   __shared__ __align__(16) uint32_t qs16[32];
   const int t = static_cast<int>(threadIdx.x);
-  if (t < 32) {
-    // the table as uint16 pairs, and times 16 (the scaled pass 1 reads it)
-    const uint16_t* qt = v.qt + 64 * v.qsel[0];
-    const uint32_t lo = qt[2 * t], hi = qt[2 * t + 1];
-    qs[t] = lo | (hi << 16);
-    qs16[t] = ((lo << 4) & 0xFFFFu) | (((hi << 4) & 0xFFFFu) << 16);
+  const uint16_t* qt = v.qt + 64 * v.qsel[0];
+  if constexpr (M == MJD_IDCT_ISLOW) {
+    if (t < 32) {
+      const uint32_t lo = qt[2 * t], hi = qt[2 * t + 1];
+      qs[t] = lo | (hi << 16);
+      qs16[t] = ((lo << 4) & 0xFFFFu) | (((hi << 4) & 0xFFFFu) << 16);
+    }
+  } else {
+    if (t < 64)
+      qs[t] = static_cast<uint32_t>(M == MJD_IDCT_IFAST ? aan_ifast_mult(qt[t], t, k) : aan_float_mult(qt[t], t, k));
   }
   __syncthreads();
   const lds32* q = (const lds32*)qs;
@@ -326,7 +166,8 @@ __global__ __launch_bounds__(kGrayThreads) void var_gray(const View v) {
     for (int r = 0; r < 8; ++r) rows[r] = next[r];
     load(run + stride, next);
     uint32_t out[16];
-    idct_block_fast(rows, q, q16, out);  // every lane of the wave (the range test is wave-wide)
+    if constexpr (M == MJD_IDCT_ISLOW) idct_block_fast(rows, q, q16, out);  // every lane (a wave-wide range test)
+    else aan_block<M>(rows, reinterpret_cast<const ldsi*>(q), k, out);
     const uint32_t b = run * 64 + lane;
     if (b >= n_blocks) continue;
     const uint32_t by = b / mcx, bx = b - by * mcx;
@@ -559,14 +400,15 @@ __global__ __launch_bounds__(256) void var_colour(const View v) {
 
 // The IDCT kernel runs as many workgroups as stay resident (each loops over
 // tiles), or about one per tile when there are fewer.
-// Grayscale islow: as many workgroups as stay resident, at most one wave per
-// run of 64 blocks.
-hipError_t launch_gray(const View& v, int cu_count, hipStream_t s) {
+// Grayscale: as many workgroups as stay resident, at most one wave per run
+// of 64 blocks.
+template <int M>
+hipError_t launch_gray(const View& v, const AanConsts& k, int cu_count, hipStream_t s) {
   static std::atomic<int> cached{0};  // resident workgroups per CU (the same on every gfx950 device)
   int per_cu = cached.load(std::memory_order_relaxed);
   if (per_cu == 0) {
     int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, var_gray, kGrayThreads, 0);
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, var_gray<M>, kGrayThreads, 0);
     if (e != hipSuccess) return e;
     per_cu = n > 0 ? n : 1;
     cached.store(per_cu, std::memory_order_relaxed);
@@ -575,26 +417,7 @@ hipError_t launch_gray(const View& v, int cu_count, hipStream_t s) {
   const uint64_t runs = (v.n_blocks + 63) / 64;
   const uint64_t want = (runs + kGrayWaves - 1) / kGrayWaves;
   const unsigned grid = static_cast<unsigned>(want < slots ? want : slots);
-  hipLaunchKernelGGL(var_gray, dim3(grid), dim3(kGrayThreads), 0, s, v);
-  return hipGetLastError();
-}
-
-template <int M>
-hipError_t launch_idct(const View& v, const Consts& k, uint64_t n_tiles, int cu_count, hipStream_t s) {
-  static std::atomic<int> cached{0};  // resident workgroups per CU (the same on every gfx950 device)
-  int per_cu = cached.load(std::memory_order_relaxed);
-  if (per_cu == 0) {
-    int n = 0;
-    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, var_idct<M>, kThreads, 0);
-    if (e != hipSuccess) return e;
-    per_cu = n > 0 ? n : 1;
-    cached.store(per_cu, std::memory_order_relaxed);
-  }
-  // a multiple of 8, at most the resident slots and about one tile each
-  const uint64_t slots = (static_cast<uint64_t>(per_cu) * (cu_count > 0 ? cu_count : 256)) & ~7ull;
-  const uint64_t want = (n_tiles + 7) & ~7ull;
-  const unsigned grid = static_cast<unsigned>(want < slots ? want : (slots >= 8 ? slots : 8));
-  hipLaunchKernelGGL(var_idct<M>, dim3(grid), dim3(kThreads), 0, s, v, k);
+  hipLaunchKernelGGL(var_gray<M>, dim3(grid), dim3(kGrayThreads), 0, s, v, k);
   return hipGetLastError();
 }
 
@@ -681,7 +504,6 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
   }
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const AanConsts& k = aan_consts();
-  const uint64_t n_tiles = (g.n_blocks + var::kBlocksPerWG - 1) / var::kBlocksPerWG;
   hipError_t e;
   const unsigned grid_red = static_cast<unsigned>((g.n_blocks + 255) / 256);
   if (scale > 1) {
@@ -690,12 +512,10 @@ int mjd_decode_variant(mjd_ctx* ctx, const mjd_variant* variant, const int16_t* 
     else if (scale == 4) hipLaunchKernelGGL(var::var_idct_red<2>, dim3(grid_red), dim3(256), 0, s, v, rk);
     else hipLaunchKernelGGL(var::var_idct_red<1>, dim3(grid_red), dim3(256), 0, s, v, rk);
     e = hipGetLastError();
-  } else switch (variant->idct) {
-    case MJD_IDCT_ISLOW:
-      e = nc == 1 ? var::launch_gray(v, ctx->cu_count, s) : var::launch_idct<MJD_IDCT_ISLOW>(v, k, n_tiles, ctx->cu_count, s);
-      break;
-    case MJD_IDCT_IFAST: e = var::launch_idct<MJD_IDCT_IFAST>(v, k, n_tiles, ctx->cu_count, s); break;
-    default: e = var::launch_idct<MJD_IDCT_FLOAT>(v, k, n_tiles, ctx->cu_count, s); break;
+  } else switch (variant->idct) {  // full-size grayscale (colour returned above)
+    case MJD_IDCT_ISLOW: e = var::launch_gray<MJD_IDCT_ISLOW>(v, k, ctx->cu_count, s); break;
+    case MJD_IDCT_IFAST: e = var::launch_gray<MJD_IDCT_IFAST>(v, k, ctx->cu_count, s); break;
+    default: e = var::launch_gray<MJD_IDCT_FLOAT>(v, k, ctx->cu_count, s); break;
   }
   if (e == hipSuccess && nc == 3) {
     const uint64_t groups = static_cast<uint64_t>((v.width + 7) / 8) * v.height;
