@@ -209,6 +209,10 @@ __device__ __forceinline__ void red_1d(const int x[N], int y[N], const int32_t* 
 
 template <int N>
 __global__ __launch_bounds__(256) void var_idct_red(const View v, const RedConsts k) {
+  // the four quant tables, once per workgroup
+  __shared__ uint16_t qs[4 * 64];
+  qs[threadIdx.x] = v.qt[threadIdx.x];
+  __syncthreads();
   const uint32_t b = blockIdx.x * 256u + threadIdx.x;
   if (b >= static_cast<uint32_t>(v.n_blocks)) return;
   const int32_t* K = N == 4 ? k.k4 : k.k2;
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(256) void var_idct_red(const View v, const RedConst
     }
   }
   const int16_t* c = v.coef + static_cast<size_t>(b) * 64;
-  const uint16_t* q = v.qt + 64 * v.qsel[comp];
+  const uint16_t* q = qs + 64 * v.qsel[comp];
   uint32_t px[N][N];
   if constexpr (N == 1) {
     px[0][0] = clamp_u8(((c[0] * static_cast<int>(q[0])) * 32768 + (1 << 17) + (128 << 18)) >> 18);
